@@ -1,0 +1,336 @@
+"""Seeded synthetic inputs shaped like the paper's colloid configurations.
+
+This module builds inputs only: particle templates, pair tables, particle
+placements, orientations and external forces.  It holds none of the step's
+arithmetic (no kernel, spreading, interpolation, spring force or fluid solve)
+and imports neither the GPU library nor the oracle, so both sides can be fed
+identical arrays.
+
+Particle model (Sec. "Multiblob particle model", Fig. 1): 12 blobs on the
+vertices of an icosahedron of circumradius ``a`` plus one blob at its centre
+(index 12), all pairs joined by harmonic springs whose rest lengths are the
+template distances.  The circumradius relates to the vertex distance d as
+a = sqrt(10 + 2 sqrt 5) / 4 * d = 0.95106 d (appendix, eq. jm2a context).
+
+Workloads (all h = 1, periodic cubic boxes):
+  single   one particle in a 32^3 box, centre uniform in the box, canonical
+           orientation, Fext = (1, 0, 0).
+  dense    128^3 box, 36,669 particles at volume fraction 0.3 for the
+           effective radius 1.6 h, random sequential addition with centre
+           distance >= 3.2 h, uniformly random orientations,
+           Fext ~ N(0, 1) per component.
+  large    256^3 box, 391,139 particles at volume fraction 0.4; random
+           sequential addition cannot reach 0.4 (its jamming limit is about
+           0.38), so centres are a random subset of a 74^3 simple-cubic
+           lattice with a bounded random displacement that keeps every pair
+           at least 3.2 h apart (a valid hard-sphere configuration, as used
+           for the paper's viscosity runs).
+  pair     two particles separated along x (pair-mobility set-up).
+  diff     64^3 box with 16 particles by random sequential addition.
+The seeded generator is numpy's PCG64 (``numpy.random.default_rng``).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GOLDEN = (1.0 + math.sqrt(5.0)) / 2.0
+CIRCUMRADIUS_OVER_EDGE = math.sqrt(10.0 + 2.0 * math.sqrt(5.0)) / 4.0
+EFFECTIVE_RADIUS = 1.6  # hard-sphere radius used to set volume fractions
+
+
+def icosahedron_template(a: float = 1.0, centre: bool = True) -> np.ndarray:
+    """Blob offsets s_i from the particle centre, shape (13, 3) (or (12, 3)).
+
+    Vertices are the cyclic permutations of (0, +-1, +-golden), scaled to
+    circumradius ``a``; the centre blob, if present, is last."""
+    verts = []
+    for s1 in (-1.0, 1.0):
+        for s2 in (-1.0, 1.0):
+            base = (0.0, s1, s2 * GOLDEN)
+            for rot in range(3):
+                verts.append(base[-rot:] + base[:-rot] if rot else base)
+    v = np.array(verts, dtype=np.float64)
+    v *= a / np.linalg.norm(v[0])
+    if centre:
+        v = np.vstack([v, np.zeros((1, 3))])
+    return v
+
+
+def pair_table(template: np.ndarray):
+    """All blob pairs (a < b) of the template with rest lengths |s_b - s_a|.
+
+    Returns (pair_a int32, pair_b int32, rest_len float64); 78 pairs for 13
+    blobs."""
+    n = template.shape[0]
+    pa, pb, r0 = [], [], []
+    for i in range(n):
+        for j in range(i + 1, n):
+            pa.append(i)
+            pb.append(j)
+            r0.append(float(np.linalg.norm(template[j] - template[i])))
+    return (np.array(pa, dtype=np.int32), np.array(pb, dtype=np.int32),
+            np.array(r0, dtype=np.float64))
+
+
+def random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Uniformly random rotation matrices (n, 3, 3) from normalised
+    Gaussian quaternions."""
+    qt = rng.standard_normal((n, 4))
+    qt /= np.linalg.norm(qt, axis=1, keepdims=True)
+    w, x, y, z = qt.T
+    R = np.empty((n, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - z * w)
+    R[:, 0, 2] = 2 * (x * z + y * w)
+    R[:, 1, 0] = 2 * (x * y + z * w)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - x * w)
+    R[:, 2, 0] = 2 * (x * z - y * w)
+    R[:, 2, 1] = 2 * (y * z + x * w)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def particles_for_fraction(L: float, phi: float,
+                           radius: float = EFFECTIVE_RADIUS) -> int:
+    """Number of spheres of ``radius`` filling fraction phi of an L^3 box."""
+    return int(round(phi * L ** 3 / (4.0 / 3.0 * math.pi * radius ** 3)))
+
+
+def rsa_centres(rng: np.random.Generator, L: float, n: int,
+                dmin: float = 2 * EFFECTIVE_RADIUS,
+                max_attempts: int | None = None) -> np.ndarray:
+    """Random sequential addition of n centres in a periodic box with
+    minimum-image distance >= dmin.
+
+    Candidates are drawn uniformly in batches; candidate i is accepted iff it
+    keeps dmin from every centre accepted before it (earlier batches through
+    a cell grid whose cells hold at most one centre, earlier members of its
+    own batch through a pairwise check), which is exactly sequential
+    addition over the candidate stream."""
+    ncell = int(math.ceil(L * math.sqrt(3.0) / dmin))
+    cs = L / ncell                       # cell diagonal < dmin
+    reach = int(math.ceil(dmin / cs))
+    rng_off = np.arange(-reach, reach + 1)
+    offs = np.stack(np.meshgrid(rng_off, rng_off, rng_off, indexing="ij"),
+                    axis=-1).reshape(-1, 3)
+    occ = np.full((ncell, ncell, ncell), -1, dtype=np.int64)
+    # Fine grid of cells lying wholly within dmin of an accepted centre: a
+    # candidate in such a cell is rejected without the exact test.
+    nfine = int(math.ceil(L / 0.5))
+    g = L / nfine
+    blocked = np.zeros((nfine, nfine, nfine), dtype=bool)
+    rfine = int(math.ceil(dmin / g)) + 1
+    f_off = np.arange(-rfine, rfine + 1)
+    f_offs = np.stack(np.meshgrid(f_off, f_off, f_off, indexing="ij"),
+                      axis=-1).reshape(-1, 3)
+    r_block = dmin - 0.5 * g * math.sqrt(3.0) - 1e-9
+    f_offs = f_offs[np.linalg.norm(f_offs, axis=1) * g
+                    <= r_block + 2.0 * g * math.sqrt(3.0)]
+    out = np.empty((n, 3))
+    count = 0
+    attempts = 0
+    limit = max_attempts if max_attempts is not None else 400 * n + 10000
+    d2min = dmin * dmin
+    while count < n:
+        if attempts > limit:
+            raise RuntimeError(f"RSA stalled after {count} of {n} centres")
+        B = int(min(2048, max(64, 4 * (n - count))))
+        cand = rng.uniform(0.0, L, size=(B, 3))
+        attempts += B
+        fi = np.floor(cand / g).astype(np.int64) % nfine
+        cand = cand[~blocked[fi[:, 0], fi[:, 1], fi[:, 2]]]
+        if cand.shape[0] == 0:
+            continue
+        ci = np.floor(cand / cs).astype(np.int64) % ncell
+        nbr = (ci[:, None, :] + offs[None, :, :]) % ncell
+        occupant = occ[nbr[..., 0], nbr[..., 1], nbr[..., 2]]
+        has = occupant >= 0
+        d = out[np.where(has, occupant, 0)] - cand[:, None, :]
+        d -= L * np.round(d / L)
+        ok = ~(has & ((d * d).sum(-1) < d2min)).any(axis=1)
+        idx = np.nonzero(ok)[0]
+        if idx.size == 0:
+            continue
+        C = cand[idx]
+        dd = C[:, None, :] - C[None, :, :]
+        dd -= L * np.round(dd / L)
+        ci_, cj_ = np.nonzero(np.triu((dd * dd).sum(-1) < d2min, 1))
+        earlier = [[] for _ in range(idx.size)]
+        for i_, j_ in zip(ci_.tolist(), cj_.tolist()):
+            earlier[j_].append(i_)
+        taken = [False] * idx.size
+        accepted = []
+        for j in range(idx.size):
+            if count + len(accepted) >= n:
+                break
+            if not any(taken[i_] for i_ in earlier[j]):
+                taken[j] = True
+                accepted.append(j)
+        acc = C[accepted]
+        m = acc.shape[0]
+        out[count:count + m] = acc
+        aci = np.floor(acc / cs).astype(np.int64) % ncell
+        occ[aci[:, 0], aci[:, 1], aci[:, 2]] = np.arange(count, count + m)
+        base = np.floor(acc / g).astype(np.int64)
+        cells = base[:, None, :] + f_offs[None, :, :]
+        dc = (cells + 0.5) * g - acc[:, None, :]
+        inside = (dc * dc).sum(-1) <= r_block * r_block
+        cw = cells[inside] % nfine
+        blocked[cw[:, 0], cw[:, 1], cw[:, 2]] = True
+        count += m
+    return out
+
+
+def lattice_centres(rng: np.random.Generator, L: float, n: int,
+                    dmin: float = 2 * EFFECTIVE_RADIUS) -> np.ndarray:
+    """n centres on a random subset of the densest simple-cubic lattice whose
+    spacing exceeds dmin, each displaced uniformly within +-(spacing-dmin)/2
+    per axis, which keeps every pair at least dmin apart."""
+    m = int(L // dmin)
+    while m > 0 and L / m < dmin:
+        m -= 1
+    if m ** 3 < n:
+        raise ValueError(f"{n} centres do not fit a {m}^3 lattice")
+    spacing = L / m
+    pick = rng.choice(m ** 3, size=n, replace=False)
+    iz, rem = np.divmod(pick, m * m)
+    iy, ix = np.divmod(rem, m)
+    c = (np.stack([ix, iy, iz], axis=1) + 0.5) * spacing
+    slack = 0.5 * (spacing - dmin) * (1.0 - 1e-9)
+    c += rng.uniform(-slack, slack, size=c.shape)
+    return c % L
+
+
+def place_particles(centres: np.ndarray, template: np.ndarray,
+                    rotations: np.ndarray | None = None) -> np.ndarray:
+    """Blob positions (P * nb, 3), blob nb*p + b of particle p."""
+    s = template if rotations is None else np.einsum("pij,bj->pbi", rotations,
+                                                     template)
+    if s.ndim == 2:
+        s = np.broadcast_to(s, (centres.shape[0],) + s.shape)
+    q = centres[:, None, :] + s
+    return np.ascontiguousarray(q.reshape(-1, 3))
+
+
+@dataclass
+class Workload:
+    """One synthetic workload: grid/fluid parameters, springs and blobs."""
+    name: str
+    L: int
+    h: float
+    rho: float
+    eta: float
+    dt: float
+    steps: int
+    q: np.ndarray                      # (M, 3) blob positions
+    Fext: np.ndarray                   # (P, 3) per-particle external force
+    nb: int
+    pa: np.ndarray
+    pb: np.ndarray
+    r0: np.ndarray
+    k: float
+    template: np.ndarray
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def P(self) -> int:
+        return self.Fext.shape[0]
+
+    @property
+    def M(self) -> int:
+        return self.q.shape[0]
+
+    def springs(self) -> dict:
+        return {"nb": self.nb, "pa": self.pa, "pb": self.pb, "r0": self.r0,
+                "k": self.k}
+
+
+def _make(name, L, centres, rng, rotate, Fext, steps, a=1.0, k=100.0,
+          dt=0.01, rho=1.0, eta=1.0, h=1.0, extra=None):
+    tmpl = icosahedron_template(a)
+    pa, pb, r0 = pair_table(tmpl)
+    R = random_rotations(rng, centres.shape[0]) if rotate else None
+    q = place_particles(centres, tmpl, R)
+    return Workload(name, L, h, rho, eta, dt, steps, q,
+                    np.ascontiguousarray(Fext, dtype=np.float64), tmpl.shape[0],
+                    pa, pb, r0, k, tmpl, extra or {})
+
+
+def single(seed: int = 1) -> Workload:
+    """One 13-blob particle in a periodic 32^3 box, Fext = (1, 0, 0),
+    dt = 0.01, 200 steps."""
+    rng = np.random.default_rng(seed)
+    L = 32
+    c = rng.uniform(0.0, L, size=(1, 3))
+    return _make("single", L, c, rng, False, np.array([[1.0, 0.0, 0.0]]), 200)
+
+
+def dense(seed: int = 2, L: int = 128, phi: float = 0.3,
+          n: int | None = None) -> Workload:
+    """Dense suspension: 36,669 particles in 128^3 at phi = 0.3 (RSA)."""
+    rng = np.random.default_rng(seed)
+    P = particles_for_fraction(L, phi) if n is None else n
+    c = rsa_centres(rng, float(L), P)
+    F = rng.standard_normal((P, 3))
+    return _make("dense", L, c, rng, True, F, 1000,
+                 extra={"phi": phi})
+
+
+def large(seed: int = 5, L: int = 256, phi: float = 0.4,
+          n: int | None = None) -> Workload:
+    """Large suspension: 391,139 particles in 256^3 at phi = 0.4."""
+    rng = np.random.default_rng(seed)
+    P = particles_for_fraction(L, phi) if n is None else n
+    c = lattice_centres(rng, float(L), P)
+    F = rng.standard_normal((P, 3))
+    return _make("large", L, c, rng, True, F, 100, extra={"phi": phi})
+
+
+def pair(seed: int = 3, L: int = 32, sep: float | None = None) -> Workload:
+    """Two particles separated along x, opposite forces +-(1, 0, 0)."""
+    rng = np.random.default_rng(seed)
+    if sep is None:
+        sep = float(rng.uniform(2.0, 6.0))
+    mid = np.full(3, L / 2.0)
+    c = np.stack([mid - [sep / 2, 0, 0], mid + [sep / 2, 0, 0]])
+    F = np.array([[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0]])
+    return _make("pair", L, c, rng, False, F, 500, extra={"sep": sep})
+
+
+def diff(seed: int = 4) -> Workload:
+    """64^3 box with 16 particles placed by random sequential addition."""
+    rng = np.random.default_rng(seed)
+    c = rsa_centres(rng, 64.0, 16)
+    F = rng.standard_normal((16, 3))
+    return _make("diff", 64, c, rng, True, F, 100)
+
+
+def random_suspension(seed: int, L: int, P: int, phi_cap: float = 0.3,
+                      rotate: bool = True, spread_box: bool = True) -> Workload:
+    """A smaller seeded suspension for parity cases: P particles by RSA."""
+    rng = np.random.default_rng(seed)
+    c = rsa_centres(rng, float(L), P)
+    F = rng.standard_normal((P, 3))
+    return _make(f"rsa{L}_{P}", L, c, rng, rotate, F, 1)
+
+
+def random_blobs(seed: int, M: int, L: int, spread: float = 1.0,
+                 offset: float = 0.0) -> np.ndarray:
+    """M free blob positions, uniform in [offset, offset + spread * L)^3."""
+    rng = np.random.default_rng(seed)
+    return offset + rng.uniform(0.0, spread * L, size=(M, 3))
+
+
+def random_forces(seed: int, M: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((M, 3))
+
+
+def random_field(seed: int, L: int, scale: float = 1.0) -> np.ndarray:
+    """A (3, L, L, L) Gaussian staggered field."""
+    rng = np.random.default_rng(seed)
+    return scale * rng.standard_normal((3, L, L, L))

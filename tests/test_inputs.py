@@ -1,0 +1,46 @@
+"""Checks of the seeded input generators (no method arithmetic here)."""
+import numpy as np
+from scipy.spatial import cKDTree
+
+from paper_1407_5600_amd import inputs
+
+
+def test_template():
+    t = inputs.icosahedron_template(1.0)
+    assert t.shape == (13, 3)
+    assert np.allclose(np.linalg.norm(t[:12], axis=1), 1.0)
+    assert np.allclose(t[12], 0.0)
+    assert np.allclose(t.mean(0), 0.0, atol=1e-15)
+
+
+def test_particle_count_for_fraction():
+    assert inputs.particles_for_fraction(128, 0.3) == 36669
+    assert inputs.particles_for_fraction(256, 0.4) == 391139
+
+
+def test_rsa_nonoverlap_and_determinism():
+    rng = np.random.default_rng(5)
+    c = inputs.rsa_centres(rng, 24.0, 200)
+    tr = cKDTree(c % 24.0, boxsize=24.0)
+    assert len(tr.query_pairs(3.2 - 1e-12)) == 0
+    c2 = inputs.rsa_centres(np.random.default_rng(5), 24.0, 200)
+    assert np.array_equal(c, c2)
+
+
+def test_lattice_nonoverlap():
+    c = inputs.lattice_centres(np.random.default_rng(1), 40.0, 1500)
+    tr = cKDTree(c, boxsize=40.0)
+    assert len(tr.query_pairs(3.2 - 1e-12)) == 0
+
+
+def test_rotations_orthonormal():
+    R = inputs.random_rotations(np.random.default_rng(0), 50)
+    assert np.allclose(np.einsum("pij,pkj->pik", R, R), np.eye(3), atol=1e-14)
+    assert np.allclose(np.linalg.det(R), 1.0)
+
+
+def test_single_workload():
+    w = inputs.single()
+    assert w.L == 32 and w.M == 13 and w.P == 1
+    assert np.allclose(w.Fext, [[1, 0, 0]])
+    assert len(w.pa) == 78
