@@ -1,0 +1,195 @@
+"""Benchmark of the multiblob step on one MI355X.
+
+Workload (default): the dense suspension -- periodic 128^3 MAC grid, h = 1,
+36,669 thirteen-blob icosahedral particles (476,697 blobs) at volume
+fraction 0.3 (effective radius 1.6 h), random sequential addition, uniformly
+random orientations, Fext ~ N(0, 1) per particle, dt = 0.01, rho = eta = 1,
+springs k = 100 on all 78 pairs.  Synthetic, seeded inputs resident in HBM
+before the timed region.
+
+One step = springs + binning + spreading + the FFT fluid solve with the
+projection + interpolation and the position update + the momentum and
+divergence reductions (everything mb_step runs).  `value` is the mixed
+precision step rate; the float64 step rate on the same GPU is reported
+beside it.  The dominant kernel's duration is measured live in the timed
+region with HIP events around that kernel only, and set against the HBM
+roofline with the kernel's algorithmic bytes.  The oracle (float64, one CPU
+thread) is timed on a bounded sample of the same workload as the CPU
+baseline.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
+GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def algorithmic_bytes(L, M, P, prec, steady=False):
+    """Bytes each kernel of one step must move at minimum (one read or write
+    of every array it consumes or produces), per launch."""
+    s = 4 if prec == "mixed" else 8
+    rec = 48 if prec == "mixed" else 80
+    N = L ** 3
+    field = 3 * N * s
+    spec = 3 * L * L * (L // 2 + 1) * 2 * s
+    return {
+        "bin_count": 24 * M + 4 * M + 8 * M,
+        "scan_reduce": 4 * N,
+        "scan_blocks": 8 * ((N + 4095) // 4096),
+        "scan_apply": 12 * N,
+        "springs_scatter": 24 * M + 24 * P + 12 * M + rec * M,
+        "spread": rec * M + field,
+        "fft_x_fwd": (1 if steady else 2) * field + spec,
+        "fft_y_fwd": 2 * spec,
+        "fft_z_spectral": 2 * spec,
+        "fft_y_inv": 2 * spec,
+        "fft_x_inv": spec + field,
+        "interp_step": field + rec * M + 4 * M + 48 * M,
+    }
+
+
+def run_steps(torch, g, sp, q, v, Fe, n):
+    for _ in range(n):
+        g.step(sp, q, v, Fe, 1)
+
+
+def bench_precision(torch, w, prec, steps, warmup, live_kernel=None):
+    from paper_1407_5600_amd import Grid, Springs
+    g = Grid(w.L, h=w.h, rho=w.rho, eta=w.eta, dt=w.dt, precision=prec, max_blobs=w.M)
+    sp = Springs(w.nb, w.pa, w.pb, w.r0, w.k)
+    q = torch.from_numpy(w.q.copy()).cuda()
+    v = g.field()
+    Fe = torch.from_numpy(w.Fext).cuda()
+    run_steps(torch, g, sp, q, v, Fe, warmup)
+    torch.cuda.synchronize()
+    # calibration pass: every kernel timed, to find the dominant one
+    g.set_timing("all")
+    ncal = 3
+    run_steps(torch, g, sp, q, v, Fe, ncal)
+    kt = g.kernel_times()
+    g.set_timing(None)
+    per_step = {k: ms / ncal for k, (ms, n) in kt.items()}
+    avg = {k: ms / n for k, (ms, n) in kt.items()}
+    dominant = live_kernel or max(per_step, key=per_step.get)
+    # timed region: only the dominant kernel is bracketed by events
+    g.set_timing([dominant])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(torch, g, sp, q, v, Fe, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    live = g.kernel_times()
+    g.set_timing(None)
+    ms, n = live[dominant]
+    assert bool(torch.isfinite(v).all()), "non-finite velocity"
+    return {
+        "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "per_step_ms": per_step,
+        "avg_launch_ms": avg,
+        "dominant": dominant,
+        "dominant_live_ms": ms / n,
+    }
+
+
+def cpu_baseline(w, nsteps):
+    import numpy as np
+    import oracle
+    prm = oracle.params(w.L, h=w.h, rho=w.rho, eta=w.eta, dt=w.dt)
+    v = np.zeros((3, w.L, w.L, w.L))
+    t0 = time.perf_counter()
+    oracle.step(prm, w.springs(), w.q, v, w.Fext, nsteps)
+    dt = time.perf_counter() - t0
+    return {"value": nsteps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} float64 steps of the same workload "
+                      f"({w.L}^3, {w.P} particles), single-threaded C oracle",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="dense", choices=["dense", "large", "single"])
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
+                    help="run one precision (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1407_5600_amd import inputs
+    torch.cuda.set_device(0)
+    w = inputs.cached(args.workload)
+    res = {}
+    for prec in (["mixed", "fp64"] if args.only is None else [args.only]):
+        print(f"[bench] {prec} {args.workload} L={w.L} M={w.M}", file=sys.stderr, flush=True)
+        res[prec] = bench_precision(torch, w, prec, args.steps, args.warmup)
+        print(f"[bench] {prec}: {res[prec]['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+
+    head = res.get("mixed") or res["fp64"]
+    head_prec = "mixed" if "mixed" in res else "fp64"
+    ab = algorithmic_bytes(w.L, w.M, w.P, head_prec)
+    dom = head["dominant"]
+    dom_bytes = ab.get(dom)
+    achieved = dom_bytes / (head["dominant_live_ms"] * 1e-3) / 1e9 if dom_bytes else None
+    kernels = {}
+    for k, ms in head["per_step_ms"].items():
+        b = ab.get(k)
+        kernels[k] = {"ms_per_step": round(ms, 5),
+                      "avg_launch_ms": round(head["avg_launch_ms"][k], 5),
+                      "alg_GBps": round(b / (head["avg_launch_ms"][k] * 1e-3) / 1e9, 1) if b else None}
+    t_s = head["avg_launch_ms"].get("spread", 0.0)
+    t_j = head["avg_launch_ms"].get("interp_step", 0.0)
+    out = {
+        "metric": "steps/s at 128^3 phi=0.3 (FP32 mixed vs FP64); blob S+J/s; HBM GB/s",
+        "value": round(1e3 / head["ms_per_step"], 2),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-mixed" if head_prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} suspension {w.L}^3 h=1, {w.P} particles x {w.nb} blobs"
+                               f" ({w.M} blobs), phi={w.extra.get('phi', '')}, dt={w.dt}, k={w.k}",
+                   "L": w.L, "particles": w.P, "blobs": w.M, "precision": head_prec},
+        "fp64_steps_per_s": round(1e3 / res["fp64"]["ms_per_step"], 2) if "fp64" in res else None,
+        "mixed_over_fp64": (round(res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"], 3)
+                            if "fp64" in res and "mixed" in res else None),
+        "blob_SJ_per_s": round(w.M / ((t_s + t_j) * 1e-3), 1) if t_s + t_j > 0 else None,
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": None,
+                     "alg_bytes_per_launch": dom_bytes,
+                     "live_avg_launch_ms": round(head["dominant_live_ms"], 5)},
+    }
+    if "fp64" in res:
+        out["kernels_fp64"] = {k: round(ms, 5) for k, ms in res["fp64"]["per_step_ms"].items()}
+    if not args.no_cpu_baseline and args.workload != "large":
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

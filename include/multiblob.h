@@ -1,0 +1,177 @@
+/*
+ * multiblob.h -- C ABI of the MI355X (gfx950) multiblob immersed-boundary
+ * step.
+ *
+ * Method: Vazquez-Quesada, Balboa Usabiaga, Delgado-Buscalioni, "A multiblob
+ * approach to colloidal hydrodynamics with inherent lubrication",
+ * arXiv:1407.5600.  A particle is a set of blobs (12 on the vertices of an
+ * icosahedron plus one at its centre) held together by harmonic springs
+ * (Fig. 1).  Blob i couples to the fluid through the kernel delta_h of
+ * eq. delta: interpolation u_i = J_i v (eq. ju), spreading S_i = J_i^*, and
+ * the fluid obeys eq. vf with the solenoidal projector P.
+ *
+ * Discretisation used by every call:
+ *   - periodic cube of L^3 cells of side h;
+ *   - staggered (MAC) velocity: component a of node (i,j,k) lives at
+ *     h*(i,j,k) + (h/2) e_a;
+ *   - delta_h(r) = h^-3 prod_a Phi(r_a / h) with the 3-point function Phi
+ *     fixed by the moment conditions stated after eq. delta;
+ *   - fluid solve: Crank-Nicolson for the viscous term, or steady Stokes,
+ *     with exact projection, solved by FFT on the MAC grid (the convective
+ *     and fluctuating stresses of eq. vf are not included).
+ *
+ * Memory: every pointer argument except those marked "host" is a device
+ * pointer on the grid's device.  The caller owns all buffers; the library
+ * never frees or keeps them beyond the call.  Layouts:
+ *   q, F, u     [M][3] float64, row-major; blob nb*p + b belongs to
+ *               particle p (b = 0..11 vertices, 12 the centre).
+ *   Fext, U0    [P][3] float64.
+ *   fields      [3][L][L][L], x fastest; float64 for MB_FP64 grids,
+ *               float32 for MB_MIXED grids.  f is a force density.
+ *   Positions are unwrapped (any real value); only indices are wrapped.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = default stream).  Every call
+ * only enqueues work on that stream and returns; errors found while
+ * enqueueing are returned, device faults surface at a later
+ * synchronisation.  One grid must not be used from two streams or threads
+ * at once (it owns scratch buffers).
+ *
+ * Errors: every call returns an mb_status and never throws.  Invalid
+ * arguments (null pointers, sizes out of range, a grid from another
+ * device) give MB_ERR_INVALID; no usable GPU gives MB_ERR_DEVICE;
+ * allocation failure gives MB_ERR_NOMEM.
+ */
+#ifndef MULTIBLOB_H
+#define MULTIBLOB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MB_OK = 0,
+    MB_ERR_INVALID = -1,
+    MB_ERR_UNSUPPORTED = -2,
+    MB_ERR_NOMEM = -3,
+    MB_ERR_DEVICE = -4
+} mb_status;
+
+typedef enum {
+    MB_FP64 = 0,  /* every field and accumulation in float64 */
+    MB_MIXED = 1  /* fields, kernel weights, FFT and accumulation in float32;
+                     positions, spring forces, the k = 0 mode and momentum
+                     reductions in float64 */
+} mb_precision;
+
+typedef enum {
+    MB_UNSTEADY_CN = 0,   /* rho dv/dt = eta L v - grad pi + f (eq. vf at
+                             zero Reynolds number), Crank-Nicolson */
+    MB_STEADY_STOKES = 1  /* 0 = eta L v - grad pi + f, mean(v) = 0 (the
+                             Stokes limit used for the paper's viscosity
+                             runs, Sec. Stresslet and viscosity) */
+} mb_mode;
+
+/* Grid description.  L = 2^a 3^b with 8 <= L <= 512 and L a multiple of 8;
+ * h > 0, dt > 0; rho > 0 in MB_UNSTEADY_CN; eta > 0 in MB_STEADY_STOKES
+ * (eta = 0 is allowed in MB_UNSTEADY_CN: ideal fluid).  zero_mean = 1 holds
+ * the k = 0 velocity mode at zero (a periodic array of particles with no net
+ * flow, the setting of eq. rhinf); zero_mean = 0 evolves it exactly,
+ * mean(v') = mean(v) + (dt/rho) mean(f).  max_blobs bounds the M of every
+ * later call on this grid (blob-sized scratch is allocated once). */
+typedef struct {
+    int32_t L;
+    int32_t precision; /* mb_precision */
+    int32_t mode;      /* mb_mode */
+    int32_t zero_mean;
+    double h;
+    double rho;
+    double eta;
+    double dt;
+    int64_t max_blobs;
+} mb_grid_desc;
+
+typedef struct mb_grid mb_grid;       /* opaque; owns FFT tables and scratch */
+typedef struct mb_springs mb_springs; /* opaque; owns the pair table */
+
+/* Create a grid on the current HIP device.  Allocates the spectrum, binning
+ * and blob scratch (about 3 L^3 complex values plus 2 L^3 int32 plus
+ * ~100 B per blob).  *out is set to NULL on error. */
+mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out);
+
+/* Release a grid (synchronises its device first).  NULL is accepted. */
+mb_status mb_grid_destroy(mb_grid* grid);
+
+/* Spring table of one particle template (Fig. 1: hard springs joining the
+ * blobs): npairs pairs (pair_a[e], pair_b[e]) of blob indices in
+ * [0, blobs_per_particle) with rest lengths rest_len[e] > 0 and stiffness
+ * k >= 0; energy sum_e (k/2)(|q_b - q_a| - rest_len[e])^2 per particle.
+ * All three arrays are HOST arrays, copied.  blobs_per_particle <= 64, each
+ * blob in at most 63 pairs. */
+mb_status mb_springs_create(int32_t blobs_per_particle, int32_t npairs,
+                            const int32_t* pair_a, const int32_t* pair_b,
+                            const double* rest_len, double k,
+                            mb_springs** out);
+mb_status mb_springs_destroy(mb_springs* springs);
+
+/* Spreading S (definition of S_i after eq. jm): f_out = sum_i
+ * delta_h(x - q_i) F_i at every staggered node, overwriting f_out.
+ * M blobs (0 <= M <= max_blobs).  q, F: [M][3] float64; f_out: field. */
+mb_status mb_spread(mb_grid* grid, int64_t M, const double* q,
+                    const double* F, void* f_out, void* stream);
+
+/* Interpolation J (eq. ju): u_out[i] = sum_x h^3 delta_h(x - q_i) v(x).
+ * v: field (not modified); u_out: [M][3] float64. */
+mb_status mb_interpolate(mb_grid* grid, int64_t M, const double* q,
+                         const void* v, double* u_out, void* stream);
+
+/* Fluid solve of eq. vf (mode of the grid) with the solenoidal projection P:
+ * v_out = new velocity from v_in and the force density f.  v_in may equal
+ * v_out; v_in is unused in MB_STEADY_STOKES (may be NULL there). */
+mb_status mb_fluid_solve(mb_grid* grid, const void* v_in, const void* f,
+                         void* v_out, void* stream);
+
+/* Spring forces plus the particle's external force split evenly over its
+ * blobs: F_out[nb*p + b] = Fext[p]/nb + sum of the springs of blob b.
+ * Fext may be NULL (no external force).  q, F_out: [P*nb][3]; Fext [P][3]. */
+mb_status mb_spring_forces(const mb_springs* springs, int64_t nparticles,
+                           const double* q, const double* Fext,
+                           double* F_out, void* stream);
+
+/* nsteps time steps of the coupled system, in place on q and v:
+ *   F^n = springs(q^n) + Fext/nb;  f = S(q^n) F^n;  v^{n+1} = solve(v^n, f);
+ *   u = J(q^n) v^{n+1};  q^{n+1} = q^n + dt u;
+ * (eq. vf with neutrally buoyant blobs, m_e = 0 as in Table 1, so the
+ * fluid-blob force is minus the blob force; no-slip u_i = J_i v).
+ * u_out [M][3] and U0_out [P][3] (particle velocity U0 = (1/N) sum_i u_i,
+ * Sec. Multiblob particle model) receive the last step's values and may be
+ * NULL.  diag_out (may be NULL) receives 7 float64 on the device:
+ * {Pi_x, Pi_y, Pi_z, sumF_x, sumF_y, sumF_z, max|D v|} of the last step,
+ * with Pi = rho h^3 sum_x v after the step.  nsteps >= 0. */
+mb_status mb_step(mb_grid* grid, const mb_springs* springs,
+                  int64_t nparticles, double* q, void* v, const double* Fext,
+                  double* u_out, double* U0_out, double* diag_out,
+                  int32_t nsteps, void* stream);
+
+/* Human-readable text for a status. */
+const char* mb_status_string(mb_status status);
+
+/* Per-kernel timing (measurement support).  Kernels whose id bit is set in
+ * kernel_mask (bit i = kernel id i; 0 disables timing) are bracketed by HIP
+ * events on the caller's stream, and their durations are accumulated per
+ * kernel id.  mb_grid_kernel_times synchronises the stream, then writes up
+ * to `cap` entries of total milliseconds and launch counts per kernel id
+ * (ids are stable; names from mb_kernel_name) and returns the number of ids
+ * in *n_out.  Setting a mask clears the accumulators. */
+mb_status mb_grid_set_timing(mb_grid* grid, uint32_t kernel_mask);
+mb_status mb_grid_kernel_times(mb_grid* grid, void* stream, double* ms_out,
+                               int64_t* launches_out, int32_t cap,
+                               int32_t* n_out);
+const char* mb_kernel_name(int32_t id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

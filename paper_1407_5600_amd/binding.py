@@ -1,0 +1,307 @@
+"""ctypes binding of libmultiblob.so (the C ABI in include/multiblob.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Tensors are torch tensors on the library's device; the binding
+checks dtype, device, shape and contiguity, then passes raw pointers and the
+current HIP stream.  Loading fails loudly if the shared library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmultiblob.so")
+
+MB_OK, MB_ERR_INVALID, MB_ERR_UNSUPPORTED, MB_ERR_NOMEM, MB_ERR_DEVICE = 0, -1, -2, -3, -4
+MB_FP64, MB_MIXED = 0, 1
+MB_UNSTEADY_CN, MB_STEADY_STOKES = 0, 1
+NDIAG = 7
+
+
+class MultiblobError(RuntimeError):
+    def __init__(self, status: int, call: str):
+        self.status = status
+        super().__init__(f"{call}: {status_string(status)} ({status})")
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("zero_mean", ctypes.c_int32),
+        ("h", ctypes.c_double),
+        ("rho", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("max_blobs", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python paper_1407_5600_amd/build.py` (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "mb_grid_create": ([ctypes.POINTER(GridDesc), ctypes.POINTER(vp)], i32),
+            "mb_grid_destroy": ([vp], i32),
+            "mb_springs_create": ([i32, i32, vp, vp, vp, d, ctypes.POINTER(vp)], i32),
+            "mb_springs_destroy": ([vp], i32),
+            "mb_spread": ([vp, i64, vp, vp, vp, vp], i32),
+            "mb_interpolate": ([vp, i64, vp, vp, vp, vp], i32),
+            "mb_fluid_solve": ([vp, vp, vp, vp, vp], i32),
+            "mb_spring_forces": ([vp, i64, vp, vp, vp, vp], i32),
+            "mb_step": ([vp, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp], i32),
+            "mb_status_string": ([i32], ctypes.c_char_p),
+            "mb_grid_set_timing": ([vp, ctypes.c_uint32], i32),
+            "mb_grid_kernel_times": ([vp, vp, vp, vp, i32, ctypes.POINTER(i32)], i32),
+            "mb_kernel_name": ([i32], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("mb_grid_create", "mb_grid_destroy", "mb_springs_create",
+            "mb_springs_destroy", "mb_spread", "mb_interpolate", "mb_fluid_solve",
+            "mb_spring_forces", "mb_step", "mb_status_string", "mb_grid_set_timing",
+            "mb_grid_kernel_times", "mb_kernel_name")
+
+
+def status_string(st: int) -> str:
+    return lib().mb_status_string(int(st)).decode()
+
+
+def _check(st: int, call: str):
+    if st != MB_OK:
+        raise MultiblobError(st, call)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="tensor", device=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on {t.device}, the grid on cuda:{device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Springs:
+    """Spring table of one particle template (mb_springs_create)."""
+
+    def __init__(self, nb, pair_a, pair_b, rest_len, k):
+        import numpy as np
+        pa = np.ascontiguousarray(pair_a, dtype=np.int32)
+        pb = np.ascontiguousarray(pair_b, dtype=np.int32)
+        r0 = np.ascontiguousarray(rest_len, dtype=np.float64)
+        if not (len(pa) == len(pb) == len(r0)):
+            raise ValueError("pair arrays differ in length")
+        h = ctypes.c_void_p()
+        _check(lib().mb_springs_create(int(nb), len(pa), pa.ctypes.data_as(ctypes.c_void_p),
+                                       pb.ctypes.data_as(ctypes.c_void_p),
+                                       r0.ctypes.data_as(ctypes.c_void_p), float(k),
+                                       ctypes.byref(h)), "mb_springs_create")
+        self.handle = h
+        self.nb = int(nb)
+        self.k = float(k)
+
+    def close(self):
+        if self.handle:
+            lib().mb_springs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Grid:
+    """A periodic MAC grid with its FFT tables and scratch (mb_grid_create)."""
+
+    def __init__(self, L, h=1.0, rho=1.0, eta=1.0, dt=0.01, precision="fp64",
+                 mode="unsteady", zero_mean=False, max_blobs=0):
+        import torch
+        prec = {"fp64": MB_FP64, "mixed": MB_MIXED}[precision]
+        md = {"unsteady": MB_UNSTEADY_CN, "steady": MB_STEADY_STOKES}[mode]
+        self.desc = GridDesc(int(L), prec, md, int(bool(zero_mean)), float(h), float(rho),
+                             float(eta), float(dt), int(max_blobs))
+        h_ = ctypes.c_void_p()
+        _check(lib().mb_grid_create(ctypes.byref(self.desc), ctypes.byref(h_)), "mb_grid_create")
+        self.handle = h_
+        self.L = int(L)
+        self.precision = precision
+        self.field_dtype = torch.float64 if prec == MB_FP64 else torch.float32
+        self.device = torch.cuda.current_device()
+
+    def close(self):
+        if self.handle:
+            lib().mb_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers --------------------------------------------------------
+    def field(self, zero=True):
+        import torch
+        shape = (3, self.L, self.L, self.L)
+        dev = torch.device("cuda", self.device)
+        return (torch.zeros if zero else torch.empty)(shape, dtype=self.field_dtype, device=dev)
+
+    def _fptr(self, t, name):
+        return _ptr(t, self.field_dtype, (3, self.L, self.L, self.L), name, self.device)
+
+    # -- calls ----------------------------------------------------------
+    def spread(self, q, F, f_out=None, stream=None):
+        import torch
+        M = q.shape[0]
+        f_out = self.field(zero=False) if f_out is None else f_out
+        _check(lib().mb_spread(self.handle, M, _ptr(q, torch.float64, (M, 3), "q", self.device),
+                               _ptr(F, torch.float64, (M, 3), "F", self.device),
+                               self._fptr(f_out, "f_out"), _stream(stream)), "mb_spread")
+        return f_out
+
+    def interpolate(self, q, v, u_out=None, stream=None):
+        import torch
+        M = q.shape[0]
+        if u_out is None:
+            u_out = torch.empty((M, 3), dtype=torch.float64, device=q.device)
+        _check(lib().mb_interpolate(self.handle, M, _ptr(q, torch.float64, (M, 3), "q", self.device),
+                                    self._fptr(v, "v"),
+                                    _ptr(u_out, torch.float64, (M, 3), "u_out", self.device),
+                                    _stream(stream)), "mb_interpolate")
+        return u_out
+
+    def fluid_solve(self, v_in, f, v_out=None, stream=None):
+        v_out = self.field(zero=False) if v_out is None else v_out
+        vin = None if v_in is None else self._fptr(v_in, "v_in")
+        _check(lib().mb_fluid_solve(self.handle, vin, self._fptr(f, "f"),
+                                    self._fptr(v_out, "v_out"), _stream(stream)),
+               "mb_fluid_solve")
+        return v_out
+
+    def step(self, springs, q, v, Fext, nsteps=1, u_out=None, U0_out=None,
+             diag_out=None, stream=None):
+        import torch
+        M = q.shape[0]
+        P = M // springs.nb
+        if P * springs.nb != M:
+            raise ValueError("blob count is not a multiple of blobs per particle")
+        _check(lib().mb_step(
+            self.handle, springs.handle, P,
+            _ptr(q, torch.float64, (M, 3), "q", self.device), self._fptr(v, "v"),
+            _ptr(Fext, torch.float64, (P, 3), "Fext", self.device),
+            _ptr(u_out, torch.float64, (M, 3), "u_out", self.device),
+            _ptr(U0_out, torch.float64, (P, 3), "U0_out", self.device),
+            _ptr(diag_out, torch.float64, (NDIAG,), "diag_out", self.device),
+            int(nsteps), _stream(stream)), "mb_step")
+
+    # -- timing ---------------------------------------------------------
+    def set_timing(self, kernels=None):
+        """Time the named kernels (None: none, "all": every kernel)."""
+        if kernels is None:
+            mask = 0
+        elif kernels == "all":
+            mask = 0xFFFFFFFF
+        else:
+            names = kernel_names()
+            mask = 0
+            for k in kernels:
+                mask |= 1 << names.index(k)
+        _check(lib().mb_grid_set_timing(self.handle, mask), "mb_grid_set_timing")
+
+    def kernel_times(self, stream=None):
+        """{kernel name: (total ms, launches)} since timing was enabled."""
+        cap = 64
+        ms = (ctypes.c_double * cap)()
+        n = (ctypes.c_int64 * cap)()
+        cnt = ctypes.c_int32()
+        _check(lib().mb_grid_kernel_times(self.handle, _stream(stream), ms, n, cap,
+                                          ctypes.byref(cnt)), "mb_grid_kernel_times")
+        out = {}
+        for i in range(cnt.value):
+            if n[i]:
+                out[lib().mb_kernel_name(i).decode()] = (ms[i], n[i])
+        return out
+
+
+def spring_forces(springs, q, Fext, F_out=None, stream=None):
+    """mb_spring_forces: spring forces plus Fext/nb per blob."""
+    import torch
+    M = q.shape[0]
+    P = M // springs.nb
+    if F_out is None:
+        F_out = torch.empty((M, 3), dtype=torch.float64, device=q.device)
+    _check(lib().mb_spring_forces(springs.handle, P, _ptr(q, torch.float64, (M, 3), "q"),
+                                  _ptr(Fext, torch.float64, (P, 3), "Fext"),
+                                  _ptr(F_out, torch.float64, (M, 3), "F_out"),
+                                  _stream(stream)), "mb_spring_forces")
+    return F_out
+
+
+def kernel_names():
+    out = []
+    i = 0
+    while True:
+        n = lib().mb_kernel_name(i)
+        if n is None:
+            return out
+        out.append(n.decode())
+        i += 1
+
+
+# C-ABI names, for callers that prefer them.
+def mb_spread(grid, q, F, f_out=None, stream=None):
+    return grid.spread(q, F, f_out, stream)
+
+
+def mb_interpolate(grid, q, v, u_out=None, stream=None):
+    return grid.interpolate(q, v, u_out, stream)
+
+
+def mb_fluid_solve(grid, v_in, f, v_out=None, stream=None):
+    return grid.fluid_solve(v_in, f, v_out, stream)
+
+
+def mb_spring_forces(springs, q, Fext, F_out=None, stream=None):
+    return spring_forces(springs, q, Fext, F_out, stream)
+
+
+def mb_step(grid, springs, q, v, Fext, nsteps=1, u_out=None, U0_out=None,
+            diag_out=None, stream=None):
+    return grid.step(springs, q, v, Fext, nsteps, u_out, U0_out, diag_out, stream)

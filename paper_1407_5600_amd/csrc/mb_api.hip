@@ -1,0 +1,513 @@
+// C ABI of the multiblob library: argument checking, grid set-up (FFT plan,
+// twiddle and symbol tables, tiles, scratch), the call sequences of
+// mb_spread / mb_interpolate / mb_fluid_solve / mb_spring_forces / mb_step,
+// and the per-kernel timing hooks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/multiblob.h"
+#include "mb_internal.h"
+
+namespace mb {
+size_t record_size(int precision);
+}
+
+using namespace mb;
+
+namespace {
+
+const char* const kKernelNames[K_NUM] = {
+    "bin_count",   "scan_reduce", "scan_blocks",      "scan_apply",
+    "springs_scatter", "bin_scatter", "springs",      "spread",
+    "fft_x_fwd",   "fft_y_fwd",   "fft_z_spectral",   "fft_y_inv",
+    "fft_x_inv",   "interp",      "interp_step",      "u0",
+    "diag"};
+
+bool size_ok(int L) {
+    if (L < 8 || L > 512 || L % 8 != 0) return false;
+    int n = L;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+FFTPlan make_plan(int n) {
+    FFTPlan p{};
+    p.n = n;
+    int m = n;
+    while (m % 8 == 0) { p.rad[p.nst++] = 8; m /= 8; }
+    while (m % 4 == 0) { p.rad[p.nst++] = 4; m /= 4; }
+    while (m % 2 == 0) { p.rad[p.nst++] = 2; m /= 2; }
+    while (m % 3 == 0) { p.rad[p.nst++] = 3; m /= 3; }
+    return p;
+}
+
+// largest even divisor of L not above cap (at least 2)
+int even_divisor(int L, int cap) {
+    int best = 2;
+    for (int d = 2; d <= L && d <= cap; d += 2)
+        if (L % d == 0) best = d;
+    return best;
+}
+
+bool device_ok(int* dev) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (hipGetDevice(dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+mb_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return MB_OK;
+    if (e == hipErrorOutOfMemory) return MB_ERR_NOMEM;
+    return MB_ERR_DEVICE;
+}
+
+template <typename T>
+void upload_tables(mb_grid* g, std::vector<T>& tw, std::vector<T>& ds,
+                   std::vector<T>& d2) {
+    const int L = g->L;
+    const double h = g->d.h;
+    tw.resize(2 * L);
+    ds.resize(2 * L);
+    d2.resize(L);
+    for (int k = 0; k < L; ++k) {
+        const double ang = 2.0 * M_PI * (double)k / (double)L;
+        tw[2 * k] = (T)std::cos(ang);
+        tw[2 * k + 1] = (T)(-std::sin(ang));
+        // divergence symbol (1 - e^{-i ang}) / h = (1 - cos ang + i sin ang) / h
+        // with 1 - cos = 2 sin^2(ang/2) to keep small modes accurate
+        const double sh = std::sin(0.5 * ang);
+        ds[2 * k] = (T)(2.0 * sh * sh / h);
+        ds[2 * k + 1] = (T)(std::sin(ang) / h);
+        d2[k] = (T)(4.0 * sh * sh / (h * h));
+    }
+}
+
+void free_grid(mb_grid* g) {
+    if (!g) return;
+    void* ptrs[] = {g->d_tw,    g->d_dsym,  g->d_d2,   g->d_spec,
+                    g->d_psum,  g->d_count, g->d_offs, g->d_bsum,
+                    g->d_rank,  g->d_perm,  g->d_rec,  g->d_tile_part,
+                    g->d_force_part, g->d_f, g->d_u};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto& tp : g->pending) {
+        (void)hipEventDestroy(tp.a);
+        (void)hipEventDestroy(tp.b);
+    }
+    for (auto e : g->free_events) (void)hipEventDestroy(e);
+    delete g;
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+mb_status enter(mb_grid* g) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
+    if (cur != g->device && hipSetDevice(g->device) != hipSuccess)
+        return MB_ERR_DEVICE;
+    return MB_OK;
+}
+
+SpringsDev springs_dev(const mb_springs* sp) {
+    SpringsDev d;
+    d.adj_start = sp->d_adj_start;
+    d.adj_other = sp->d_adj_other;
+    d.adj_r0 = sp->d_adj_r0;
+    d.k = sp->k;
+    d.nb = sp->nb;
+    return d;
+}
+
+}  // namespace
+
+namespace mb {
+
+void timer_begin(mb_grid* g, int id, hipStream_t s, hipEvent_t* ev) {
+    *ev = nullptr;
+    if (!g || !((g->timing >> id) & 1u)) return;
+    hipEvent_t e;
+    if (!g->free_events.empty()) {
+        e = g->free_events.back();
+        g->free_events.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return;
+    }
+    (void)hipEventRecord(e, s);
+    *ev = e;
+}
+
+void timer_end(mb_grid* g, int id, hipStream_t s, hipEvent_t ev) {
+    if (!g || !((g->timing >> id) & 1u) || !ev) return;
+    hipEvent_t e;
+    if (!g->free_events.empty()) {
+        e = g->free_events.back();
+        g->free_events.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        g->free_events.push_back(ev);
+        return;
+    }
+    (void)hipEventRecord(e, s);
+    g->pending.push_back(TimerPair{ev, e, id});
+}
+
+}  // namespace mb
+
+extern "C" {
+
+const char* mb_status_string(mb_status st) {
+    switch (st) {
+        case MB_OK: return "success";
+        case MB_ERR_INVALID: return "invalid argument";
+        case MB_ERR_UNSUPPORTED: return "unsupported configuration";
+        case MB_ERR_NOMEM: return "out of device memory";
+        case MB_ERR_DEVICE: return "no usable GPU or device error";
+    }
+    return "unknown status";
+}
+
+const char* mb_kernel_name(int32_t id) {
+    if (id < 0 || id >= K_NUM) return nullptr;
+    return kKernelNames[id];
+}
+
+mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
+    if (!out) return MB_ERR_INVALID;
+    *out = nullptr;
+    if (!desc) return MB_ERR_INVALID;
+    const mb_grid_desc d = *desc;
+    if (!size_ok(d.L)) return MB_ERR_INVALID;
+    if (d.precision != MB_FP64 && d.precision != MB_MIXED) return MB_ERR_INVALID;
+    if (d.mode != MB_UNSTEADY_CN && d.mode != MB_STEADY_STOKES) return MB_ERR_INVALID;
+    if (d.zero_mean != 0 && d.zero_mean != 1) return MB_ERR_INVALID;
+    if (!(d.h > 0.0) || !std::isfinite(d.h)) return MB_ERR_INVALID;
+    if (!(d.dt > 0.0) || !std::isfinite(d.dt)) return MB_ERR_INVALID;
+    if (!(d.eta >= 0.0) || !std::isfinite(d.eta)) return MB_ERR_INVALID;
+    if (d.mode == MB_UNSTEADY_CN && (!(d.rho > 0.0) || !std::isfinite(d.rho)))
+        return MB_ERR_INVALID;
+    if (d.mode == MB_STEADY_STOKES && !(d.eta > 0.0)) return MB_ERR_INVALID;
+    if (d.max_blobs < 0 || d.max_blobs > (int64_t)1 << 30) return MB_ERR_INVALID;
+    int dev = 0;
+    if (!device_ok(&dev)) return MB_ERR_DEVICE;
+
+    mb_grid* g = new (std::nothrow) mb_grid();
+    if (!g) return MB_ERR_NOMEM;
+    g->d = d;
+    g->device = dev;
+    g->L = d.L;
+    g->NC = d.L / 2 + 1;
+    g->N = (int64_t)d.L * d.L * d.L;
+    g->fsz = d.precision == MB_MIXED ? 4 : 8;
+    g->plan = make_plan(d.L);
+    const int L = d.L;
+    // x passes: row pairs per block so that a block has about 256 threads
+    g->rows_x = even_divisor(L, std::max(2, 4096 / L));
+    g->nblk_x = (int)(3 * (int64_t)L * L / g->rows_x);
+    g->wy = std::max(1, std::min(16, 2048 / L));
+    g->wz = std::max(1, std::min(8, 2048 / L));
+    // tiles: x extent 32, 16 or 8 (dividing L), y and z extent 8
+    Tiles t{};
+    t.tx = (L % 32 == 0) ? 32 : (L % 16 == 0) ? 16 : 8;
+    if (d.precision == MB_FP64 && t.tx == 32) t.tx = 16;  // LDS budget
+    t.ty = 8;
+    t.tz = 8;
+    t.ntx = L / t.tx;
+    t.nty = L / t.ty;
+    t.ntz = L / t.tz;
+    t.n = t.ntx * t.nty * t.ntz;
+    t.remap = (t.n % 8 == 0 && t.n >= 64) ? 1 : 0;
+    g->tiles = t;
+    g->rec_size = record_size(d.precision);
+    g->force_blocks_cap = (int)((std::max<int64_t>(d.max_blobs, 1) + 255) / 256);
+    g->nscan = (int)((g->N + 4095) / 4096);
+
+    const size_t cbytes = 2 * g->fsz;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 16);
+    };
+    alloc(&g->d_tw, (size_t)L * cbytes);
+    alloc(&g->d_dsym, (size_t)L * cbytes);
+    alloc(&g->d_d2, (size_t)L * g->fsz);
+    alloc(&g->d_spec, (size_t)3 * L * L * g->NC * cbytes);
+    alloc((void**)&g->d_psum, (size_t)g->nblk_x * 2 * sizeof(double));
+    alloc((void**)&g->d_count, (size_t)g->N * sizeof(int));
+    alloc((void**)&g->d_offs, (size_t)(g->N + 1) * sizeof(int));
+    alloc((void**)&g->d_bsum, (size_t)g->nscan * sizeof(int));
+    alloc((void**)&g->d_rank, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
+    alloc((void**)&g->d_perm, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
+    alloc(&g->d_rec, (size_t)std::max<int64_t>(d.max_blobs, 1) * g->rec_size);
+    alloc((void**)&g->d_tile_part, (size_t)t.n * 4 * sizeof(double));
+    alloc(&g->d_f, (size_t)3 * g->N * g->fsz);
+    alloc((void**)&g->d_u, (size_t)std::max<int64_t>(d.max_blobs, 1) * 3 * sizeof(double));
+    alloc((void**)&g->d_force_part, (size_t)g->force_blocks_cap * 3 * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)g->N * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(g->d_force_part, 0, (size_t)g->force_blocks_cap * 3 * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)t.n * 4 * sizeof(double));
+    if (e == hipSuccess) {
+        if (d.precision == MB_MIXED) {
+            std::vector<float> tw, ds, d2;
+            upload_tables<float>(g, tw, ds, d2);
+            e = hipMemcpy(g->d_tw, tw.data(), tw.size() * 4, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(g->d_dsym, ds.data(), ds.size() * 4, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(g->d_d2, d2.data(), d2.size() * 4, hipMemcpyHostToDevice);
+        } else {
+            std::vector<double> tw, ds, d2;
+            upload_tables<double>(g, tw, ds, d2);
+            e = hipMemcpy(g->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(g->d_dsym, ds.data(), ds.size() * 8, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(g->d_d2, d2.data(), d2.size() * 8, hipMemcpyHostToDevice);
+        }
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_grid(g);
+        return from_hip(e);
+    }
+    *out = g;
+    return MB_OK;
+}
+
+mb_status mb_grid_destroy(mb_grid* g) {
+    if (!g) return MB_OK;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    free_grid(g);
+    if (cur >= 0 && cur != g->device) (void)hipSetDevice(cur);
+    return MB_OK;
+}
+
+mb_status mb_springs_create(int32_t nb, int32_t npairs, const int32_t* pa,
+                            const int32_t* pb, const double* r0, double k,
+                            mb_springs** out) {
+    if (!out) return MB_ERR_INVALID;
+    *out = nullptr;
+    if (nb < 1 || nb > 64 || npairs < 0 || npairs > nb * (nb - 1) / 2)
+        return MB_ERR_INVALID;
+    if (npairs > 0 && (!pa || !pb || !r0)) return MB_ERR_INVALID;
+    if (!(k >= 0.0) || !std::isfinite(k)) return MB_ERR_INVALID;
+    std::vector<int> deg(nb, 0);
+    for (int e = 0; e < npairs; ++e) {
+        if (pa[e] < 0 || pa[e] >= nb || pb[e] < 0 || pb[e] >= nb || pa[e] == pb[e])
+            return MB_ERR_INVALID;
+        if (!(r0[e] > 0.0) || !std::isfinite(r0[e])) return MB_ERR_INVALID;
+        deg[pa[e]]++;
+        deg[pb[e]]++;
+    }
+    for (int b = 0; b < nb; ++b)
+        if (deg[b] > 63) return MB_ERR_INVALID;
+    int dev = 0;
+    if (!device_ok(&dev)) return MB_ERR_DEVICE;
+    std::vector<int> start(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) start[b + 1] = start[b] + deg[b];
+    std::vector<int> other(std::max(1, 2 * npairs), 0), fill(start.begin(), start.end() - 1);
+    std::vector<double> rest(std::max(1, 2 * npairs), 0.0);
+    for (int e = 0; e < npairs; ++e) {
+        other[fill[pa[e]]] = pb[e];
+        rest[fill[pa[e]]++] = r0[e];
+        other[fill[pb[e]]] = pa[e];
+        rest[fill[pb[e]]++] = r0[e];
+    }
+    mb_springs* sp = new (std::nothrow) mb_springs();
+    if (!sp) return MB_ERR_NOMEM;
+    sp->nb = nb;
+    sp->npairs = npairs;
+    sp->k = k;
+    sp->device = dev;
+    hipError_t e = hipMalloc(&sp->d_adj_start, start.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&sp->d_adj_other, other.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&sp->d_adj_r0, rest.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(sp->d_adj_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sp->d_adj_other, other.data(), other.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sp->d_adj_r0, rest.data(), rest.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        mb_springs_destroy(sp);
+        return from_hip(e);
+    }
+    *out = sp;
+    return MB_OK;
+}
+
+mb_status mb_springs_destroy(mb_springs* sp) {
+    if (!sp) return MB_OK;
+    (void)hipDeviceSynchronize();
+    if (sp->d_adj_start) (void)hipFree(sp->d_adj_start);
+    if (sp->d_adj_other) (void)hipFree(sp->d_adj_other);
+    if (sp->d_adj_r0) (void)hipFree(sp->d_adj_r0);
+    delete sp;
+    return MB_OK;
+}
+
+mb_status mb_spread(mb_grid* g, int64_t M, const double* q, const double* F,
+                    void* f_out, void* stream) {
+    if (!g || !f_out || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (M > 0 && (!q || !F || !aligned8(q) || !aligned8(F))) return MB_ERR_INVALID;
+    if (!aligned8(f_out) && g->fsz == 8) return MB_ERR_INVALID;
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (g->fsz == 4) {
+        e = bin_blobs<float>(g, M, q, s);
+        if (e == hipSuccess) e = scatter_records<float>(g, M, q, F, s);
+        if (e == hipSuccess) e = spread<float>(g, (float*)f_out, s);
+    } else {
+        e = bin_blobs<double>(g, M, q, s);
+        if (e == hipSuccess) e = scatter_records<double>(g, M, q, F, s);
+        if (e == hipSuccess) e = spread<double>(g, (double*)f_out, s);
+    }
+    return from_hip(e);
+}
+
+mb_status mb_interpolate(mb_grid* g, int64_t M, const double* q, const void* v,
+                         double* u_out, void* stream) {
+    if (!g || !v || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (M > 0 && (!q || !u_out || !aligned8(q) || !aligned8(u_out))) return MB_ERR_INVALID;
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    if (M == 0) return MB_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (g->fsz == 4) {
+        e = bin_blobs<float>(g, M, q, s);
+        if (e == hipSuccess) e = scatter_records<float>(g, M, q, nullptr, s);
+        if (e == hipSuccess) e = interpolate<float>(g, M, (const float*)v, u_out, nullptr, 0, s);
+    } else {
+        e = bin_blobs<double>(g, M, q, s);
+        if (e == hipSuccess) e = scatter_records<double>(g, M, q, nullptr, s);
+        if (e == hipSuccess) e = interpolate<double>(g, M, (const double*)v, u_out, nullptr, 0, s);
+    }
+    return from_hip(e);
+}
+
+mb_status mb_fluid_solve(mb_grid* g, const void* v_in, const void* f,
+                         void* v_out, void* stream) {
+    if (!g || !f || !v_out) return MB_ERR_INVALID;
+    const bool steady = g->d.mode == MB_STEADY_STOKES;
+    if (!steady && !v_in) return MB_ERR_INVALID;
+    if (!v_in) v_in = v_out;  // unread in steady mode
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (g->fsz == 4)
+        e = fluid_solve<float>(g, (const float*)v_in, (const float*)f, (float*)v_out, s);
+    else
+        e = fluid_solve<double>(g, (const double*)v_in, (const double*)f, (double*)v_out, s);
+    return from_hip(e);
+}
+
+mb_status mb_spring_forces(const mb_springs* sp, int64_t P, const double* q,
+                           const double* Fext, double* F_out, void* stream) {
+    if (!sp || P < 0) return MB_ERR_INVALID;
+    if (P > 0 && (!q || !F_out || !aligned8(q) || !aligned8(F_out))) return MB_ERR_INVALID;
+    if ((int64_t)P * sp->nb > ((int64_t)1 << 31) - 1) return MB_ERR_INVALID;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
+    if (cur != sp->device && hipSetDevice(sp->device) != hipSuccess) return MB_ERR_DEVICE;
+    return from_hip(spring_forces(springs_dev(sp), P, q, Fext, F_out,
+                                  (hipStream_t)stream, nullptr));
+}
+
+mb_status mb_step(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
+                  void* v, const double* Fext, double* u_out, double* U0_out,
+                  double* diag_out, int32_t nsteps, void* stream) {
+    if (!g || !sp || !v || P < 0 || nsteps < 0) return MB_ERR_INVALID;
+    const int64_t M = P * sp->nb;
+    if (M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (M > 0 && (!q || !aligned8(q))) return MB_ERR_INVALID;
+    if (sp->device != g->device) return MB_ERR_INVALID;
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    if (nsteps == 0) return MB_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const SpringsDev sd = springs_dev(sp);
+    const int fb = (int)((M + 255) / 256);
+    if (M == 0) {
+        // no blobs: the force partials of the diagnostics are zero
+        hipError_t e0 = hipMemsetAsync(g->d_force_part, 0, 3 * sizeof(double), s);
+        if (e0 != hipSuccess) return from_hip(e0);
+    }
+    hipError_t e = hipSuccess;
+    for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+        const bool last = n == nsteps - 1;
+        double* u_dst = nullptr;
+        if (last) u_dst = u_out ? u_out : (U0_out ? g->d_u : nullptr);
+        if (g->fsz == 4) {
+            float* f = (float*)g->d_f;
+            float* vv = (float*)v;
+            e = bin_blobs<float>(g, M, q, s);
+            if (e == hipSuccess) e = scatter_springs<float>(g, sd, P, q, Fext, s);
+            if (e == hipSuccess) e = spread<float>(g, f, s);
+            if (e == hipSuccess) e = fluid_solve<float>(g, vv, f, vv, s);
+            if (e == hipSuccess) e = interpolate<float>(g, M, vv, u_dst, q, 1, s);
+        } else {
+            double* f = (double*)g->d_f;
+            double* vv = (double*)v;
+            e = bin_blobs<double>(g, M, q, s);
+            if (e == hipSuccess) e = scatter_springs<double>(g, sd, P, q, Fext, s);
+            if (e == hipSuccess) e = spread<double>(g, f, s);
+            if (e == hipSuccess) e = fluid_solve<double>(g, vv, f, vv, s);
+            if (e == hipSuccess) e = interpolate<double>(g, M, vv, u_dst, q, 1, s);
+        }
+        if (last && e == hipSuccess && U0_out)
+            e = particle_means(g, P, sp->nb, u_dst, U0_out, s);
+        if (last && e == hipSuccess && diag_out)
+            e = diagnostics(g, M > 0 ? fb : 1, diag_out, s);
+    }
+    return from_hip(e);
+}
+
+mb_status mb_grid_set_timing(mb_grid* g, uint32_t kernel_mask) {
+    if (!g) return MB_ERR_INVALID;
+    g->timing = kernel_mask;
+    for (int i = 0; i < K_NUM; ++i) {
+        g->acc_ms[i] = 0.0;
+        g->acc_n[i] = 0;
+    }
+    return MB_OK;
+}
+
+mb_status mb_grid_kernel_times(mb_grid* g, void* stream, double* ms_out,
+                               int64_t* launches_out, int32_t cap,
+                               int32_t* n_out) {
+    if (!g || cap < 0 || (cap > 0 && (!ms_out || !launches_out))) return MB_ERR_INVALID;
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return from_hip(e);
+    for (auto& tp : g->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, tp.a, tp.b) == hipSuccess) {
+            g->acc_ms[tp.id] += ms;
+            g->acc_n[tp.id] += 1;
+        }
+        g->free_events.push_back(tp.a);
+        g->free_events.push_back(tp.b);
+    }
+    g->pending.clear();
+    for (int i = 0; i < cap && i < K_NUM; ++i) {
+        ms_out[i] = g->acc_ms[i];
+        launches_out[i] = g->acc_n[i];
+    }
+    if (n_out) *n_out = K_NUM;
+    return MB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+// Device helpers: complex arithmetic, the 3-point kernel weights, radix
+// butterflies and the in-LDS Stockham line transform, block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mb_internal.h"
+
+namespace mb {
+
+constexpr int WAVE = 64;
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cplx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+    return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
+    return {a.x - b.x, a.y - b.y};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) {
+    return {a.x, -a.y};
+}
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) {
+    return INV ? cplx<T>{-a.y, a.x} : cplx<T>{a.y, -a.x};
+}
+
+// Weights of the 3-point kernel at the nodes i0-1, i0, i0+1 of a point at
+// offset t in [-1/2, 1/2] from node i0 (t = x/h - i0).  With s = sqrt(1-3t^2):
+// Phi(t) = (1+s)/3 and Phi(1 -+ t) = (2 +- 3t - s)/6.
+template <typename T>
+__device__ __forceinline__ void kernel_weights(T t, T w[3]) {
+    const T s = sqrt(T(1) - T(3) * t * t);
+    const T sixth = T(1) / T(6);
+    w[1] = (T(1) + s) * (T(1) / T(3));
+    w[2] = (T(2) + T(3) * t - s) * sixth;
+    w[0] = (T(2) - T(3) * t - s) * sixth;
+}
+
+// ---------------------------------------------------------------------------
+// Radix-R DFT of R values in registers: y_k = sum_r v_r W_R^{rk} with
+// W_R = exp(-2 pi i / R) (forward) or its conjugate (inverse).
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cplx<T>* v) {
+    cplx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2,
+                                     cplx<T>& a3) {
+    cplx<T> s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    cplx<T> s13 = cadd(a1, a3), d13 = mul_mi<T, INV>(csub(a1, a3));
+    a0 = cadd(s02, s13);
+    a2 = csub(s02, s13);
+    a1 = cadd(d02, d13);
+    a3 = csub(d02, d13);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4v(cplx<T>* v) {
+    dft4<T, INV>(v[0], v[1], v[2], v[3]);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cplx<T>* v) {
+    // even / odd halves, then combine with W_8^k
+    cplx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cplx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<T, INV>(e0, e1, e2, e3);
+    dft4<T, INV>(o0, o1, o2, o3);
+    const T r = T(0.70710678118654752440084436210484903928);
+    // W_8^1 = r(1 - i) forward, r(1 + i) inverse
+    cplx<T> t1 = INV ? cplx<T>{r * (o1.x - o1.y), r * (o1.x + o1.y)}
+                     : cplx<T>{r * (o1.x + o1.y), r * (o1.y - o1.x)};
+    cplx<T> t2 = mul_mi<T, INV>(o2);
+    // W_8^3 = -r(1 + i) forward, -r(1 - i) inverse
+    cplx<T> t3 = INV ? cplx<T>{-r * (o3.x + o3.y), r * (o3.x - o3.y)}
+                     : cplx<T>{r * (o3.y - o3.x), -r * (o3.x + o3.y)};
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, t1);
+    v[5] = csub(e1, t1);
+    v[2] = cadd(e2, t2);
+    v[6] = csub(e2, t2);
+    v[3] = cadd(e3, t3);
+    v[7] = csub(e3, t3);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cplx<T>* v) {
+    const T c = T(0.86602540378443864676372317075293618347);  // sqrt(3)/2
+    cplx<T> s = cadd(v[1], v[2]);
+    cplx<T> d = csub(v[1], v[2]);
+    cplx<T> t = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+    // W_3 = -1/2 - i c (forward): y1 = t - i c d, y2 = t + i c d
+    cplx<T> icd = {-c * d.y, c * d.x};
+    v[0] = cadd(v[0], s);
+    if (INV) {
+        v[1] = cadd(t, icd);
+        v[2] = csub(t, icd);
+    } else {
+        v[1] = csub(t, icd);
+        v[2] = cadd(t, icd);
+    }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(cplx<T>* v) {
+    if constexpr (R == 2) dft2<T, INV>(v);
+    else if constexpr (R == 3) dft3<T, INV>(v);
+    else if constexpr (R == 4) dft4v<T, INV>(v);
+    else dft8<T, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham stage of radix R over `nlines` independent lines of length n
+// stored in LDS: element e of line l at buf[l * ls + e * es].  Stage with
+// Ns = product of the earlier radices: butterfly j reads elements
+// j + r n/R, multiplies input r by W_n^{r (j mod Ns) n/(Ns R)}, applies the
+// R-point DFT and writes output r to (j/Ns) Ns R + (j mod Ns) + r Ns.
+// Every thread first loads all of its butterflies into registers, so one
+// barrier separates all reads from all writes and the stage runs in place.
+// LINES_FAST: consecutive threads take consecutive lines (column tiles);
+// otherwise consecutive butterflies of one line (row tiles).
+template <typename T, int R, bool INV, int MAXB, bool LINES_FAST>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int nlines,
+                                          int es, int ls, int Ns,
+                                          const cplx<T>* __restrict__ tw,
+                                          int tid, int nthr) {
+    const int nb = n / R;
+    const int total = nb * nlines;
+    const int tstep = n / (Ns * R);
+    cplx<T> v[MAXB][R];
+#pragma unroll
+    for (int it = 0; it < MAXB; ++it) {
+        const int w = tid + it * nthr;
+        if (w < total) {
+            int line, j;
+            if (LINES_FAST) {
+                j = w / nlines;
+                line = w - j * nlines;
+            } else {
+                line = w / nb;
+                j = w - line * nb;
+            }
+            const cplx<T>* base = buf + line * ls;
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cplx<T> a = base[(j + r * nb) * es];
+                if (r > 0 && k > 0) {
+                    cplx<T> t = tw[r * k * tstep];
+                    if (INV) t.y = -t.y;
+                    a = cmul(a, t);
+                }
+                v[it][r] = a;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXB; ++it) {
+        const int w = tid + it * nthr;
+        if (w < total) {
+            int line, j;
+            if (LINES_FAST) {
+                j = w / nlines;
+                line = w - j * nlines;
+            } else {
+                line = w / nb;
+                j = w - line * nb;
+            }
+            dftR<T, R, INV>(v[it]);
+            cplx<T>* base = buf + line * ls;
+            const int jm = j % Ns;
+            const int dst = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) base[(dst + r * Ns) * es] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full line transform (all stages of the plan); EPT = elements per thread
+// (nlines * n <= nthr * EPT).  Unnormalised in both directions.
+template <typename T, bool INV, int EPT, bool LINES_FAST>
+__device__ void lds_fft(cplx<T>* buf, const FFTPlan& pl, int nlines, int es,
+                        int ls, const cplx<T>* __restrict__ tw, int tid,
+                        int nthr) {
+    int Ns = 1;
+    for (int s = 0; s < pl.nst; ++s) {
+        const int R = pl.rad[s];
+        if (R == 8)
+            fft_stage<T, 8, INV, (EPT + 7) / 8, LINES_FAST>(buf, pl.n, nlines, es, ls, Ns, tw, tid, nthr);
+        else if (R == 4)
+            fft_stage<T, 4, INV, (EPT + 3) / 4, LINES_FAST>(buf, pl.n, nlines, es, ls, Ns, tw, tid, nthr);
+        else if (R == 2)
+            fft_stage<T, 2, INV, (EPT + 1) / 2, LINES_FAST>(buf, pl.n, nlines, es, ls, Ns, tw, tid, nthr);
+        else
+            fft_stage<T, 3, INV, (EPT + 2) / 3, LINES_FAST>(buf, pl.n, nlines, es, ls, Ns, tw, tid, nthr);
+        Ns *= R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block reductions (blockDim.x a multiple of 64, at most 1024).
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// Sum (or max) of one value per thread; the result is valid in every
+// thread.  `scratch` holds at least 16 doubles.  Contains barriers.
+template <bool MAX>
+__device__ double block_reduce(double v, double* scratch) {
+    const int lane = threadIdx.x % WAVE;
+    const int wid = threadIdx.x / WAVE;
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+    v = MAX ? wave_max(v) : wave_sum(v);
+    __syncthreads();
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double r = MAX ? 0.0 : 0.0;
+    if (MAX) {
+        r = scratch[0];
+        for (int i = 1; i < nw; ++i) r = fmax(r, scratch[i]);
+    } else {
+        for (int i = 0; i < nw; ++i) r += scratch[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// Exclusive prefix sum of one int per thread over the block; returns the
+// thread's exclusive prefix and writes the block total to *total.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* scratch,
+                                                    int* total) {
+    const int lane = threadIdx.x % WAVE;
+    const int wid = threadIdx.x / WAVE;
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+    int x = v;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int y = __shfl_up(x, o, WAVE);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1) scratch[wid] = x;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < wid) before += scratch[i];
+        tot += scratch[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
+
+// Block index -> work index such that each of the 8 XCDs (which receive
+// blocks round-robin) works on one contiguous range of work items.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int per = n / 8;
+    return (b % 8) * per + b / 8;
+}
+
+}  // namespace mb

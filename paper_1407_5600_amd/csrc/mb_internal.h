@@ -1,0 +1,150 @@
+// Internal state of the multiblob library: grid handle, spring table, FFT
+// plans, tile geometry and the per-kernel timing hooks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/multiblob.h"
+
+namespace mb {
+
+// Stable kernel ids (reported by the timing interface).
+enum KernelId : int {
+    K_BIN_COUNT = 0,
+    K_SCAN_REDUCE,
+    K_SCAN_BLOCKS,
+    K_SCAN_APPLY,
+    K_SPRINGS_SCATTER,
+    K_BIN_SCATTER,
+    K_SPRINGS,
+    K_SPREAD,
+    K_FFT_X_FWD,
+    K_FFT_Y_FWD,
+    K_FFT_Z_SPECTRAL,
+    K_FFT_Y_INV,
+    K_FFT_X_INV,
+    K_INTERP,
+    K_INTERP_STEP,
+    K_U0,
+    K_DIAG,
+    K_NUM
+};
+
+// Radix plan of a length-n line transform (product of rad[] = n).
+struct FFTPlan {
+    int n;
+    int nst;
+    int rad[12];
+};
+
+// Spring table on the device, as per-blob adjacency lists of the particle
+// template (each pair appears in the lists of both of its blobs).
+struct SpringsDev {
+    const int* adj_start;   // [nb + 1]
+    const int* adj_other;   // [2 * npairs]
+    const double* adj_r0;   // [2 * npairs]
+    double k;
+    int nb;
+};
+
+// Tile geometry for spreading and interpolation.
+struct Tiles {
+    int tx, ty, tz;     // tile extent in cells
+    int ntx, nty, ntz;  // tiles per axis
+    int n;              // total tiles
+    int remap;          // 1: XCD-aware block -> tile mapping
+};
+
+struct TimerPair {
+    hipEvent_t a, b;
+    int id;
+};
+
+}  // namespace mb
+
+struct mb_springs {
+    int nb;
+    int npairs;
+    double k;
+    int device;
+    int* d_adj_start;
+    int* d_adj_other;
+    double* d_adj_r0;
+};
+
+struct mb_grid {
+    mb_grid_desc d;
+    int device;
+    int L, NC;          // cells per side, complex columns L/2 + 1
+    int64_t N;          // L^3
+    size_t fsz;         // bytes per scalar (8 or 4)
+    // FFT
+    mb::FFTPlan plan;
+    void* d_tw;         // twiddles W_L^k, k < L (cplx<T>)
+    void* d_dsym;       // D symbol per mode index: (1 - e^{-2 pi i m / L}) / h
+    void* d_d2;         // |D symbol|^2 per mode index (T)
+    void* d_spec;       // [3][L][L][NC] cplx<T>
+    int rows_x;         // rows per block in the x passes
+    int nblk_x;         // blocks of an x pass
+    int wy, wz;         // column chunk widths of the y and z passes
+    double* d_psum;     // [nblk_x][2] per-block sums of v and f (float64)
+    // binning
+    int* d_count;       // [N] (kept zeroed between uses)
+    int* d_offs;        // [N + 1]
+    int* d_bsum;        // scan block sums
+    int nscan;          // scan blocks
+    int* d_rank;        // [max_blobs]
+    int* d_perm;        // [max_blobs]
+    void* d_rec;        // [max_blobs] records
+    size_t rec_size;
+    mb::Tiles tiles;
+    void* d_f;             // [3][L][L][L] force density of the step
+    double* d_u;           // [max_blobs][3] blob velocities of the last step
+    double* d_tile_part;   // [tiles][4]  (sum v_a, max |Dv|)
+    double* d_force_part;  // [force blocks][3]
+    int force_blocks_cap;
+    // timing
+    uint32_t timing;    // bit mask of timed kernel ids
+    std::vector<mb::TimerPair> pending;
+    std::vector<hipEvent_t> free_events;
+    double acc_ms[mb::K_NUM];
+    int64_t acc_n[mb::K_NUM];
+};
+
+namespace mb {
+
+// Timer hooks around each launch (no-ops unless timing is enabled).
+void timer_begin(mb_grid* g, int id, hipStream_t s, hipEvent_t* ev);
+void timer_end(mb_grid* g, int id, hipStream_t s, hipEvent_t ev);
+
+// Launchers (templated on the field scalar type, float or double).  Each
+// returns hipSuccess or the launch error.
+template <typename T>
+hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s);
+template <typename T>
+hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
+                           const double* F, hipStream_t s);
+template <typename T>
+hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
+                           const double* q, const double* Fext, hipStream_t s);
+hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
+                         const double* Fext, double* F, hipStream_t s,
+                         mb_grid* timing_grid);
+template <typename T>
+hipError_t spread(mb_grid* g, T* f, hipStream_t s);
+template <typename T>
+hipError_t fluid_solve(mb_grid* g, const T* v_in, const T* f, T* v_out,
+                       hipStream_t s);
+template <typename T>
+hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
+                       double* q_update, int diag, hipStream_t s);
+hipError_t particle_means(mb_grid* g, int64_t P, int nb, const double* u,
+                          double* U0, hipStream_t s);
+hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,
+                       hipStream_t s);
+size_t record_size(int precision);
+
+}  // namespace mb

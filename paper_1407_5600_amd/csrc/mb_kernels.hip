@@ -1,0 +1,1011 @@
+// HIP kernels of the multiblob step for gfx950 and their launchers.
+//
+// Per step: blobs are counting-sorted by cell (count, scan, scatter with the
+// spring forces), spread tile by tile with LDS accumulation, the fluid is
+// solved by a hand-written 3-D FFT (x pass with the Crank-Nicolson
+// right-hand side fused in, y pass, z pass fused with the projection and
+// the viscous divide, inverse y, inverse x), and the new velocity is
+// interpolated tile by tile from an LDS copy of the field, moving the blobs.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mb_device.h"
+#include "mb_internal.h"
+
+namespace mb {
+
+// Sorted-blob record: kernel offsets for the cell-centred (tu) and the
+// component's own, half-cell shifted (ts) node sets, the force scaled by
+// h^-3, and the packed cell: bits 0-8 x, 9-17 y, 18-26 z, 27-29 the
+// "rounds up" bit per axis (node i0 = c + bit for the cell-centred set).
+template <typename T>
+struct __align__(16) Rec {
+    T tu[3];
+    T ts[3];
+    T F[3];
+    uint32_t cell;
+    uint32_t pad;
+};
+
+constexpr int BLK = 256;
+
+struct Geom {
+    int c[3];
+    int up[3];
+    double tu[3];
+    double ts[3];
+};
+
+// Cell, rounding bits and kernel offsets of a position (float64).  For the
+// node set of velocity component a along axis b the node coordinate is
+// x = q_b/h - (1/2) delta_ab; the nearest node is i0 = floor(x + 1/2) and
+// t = x - i0 in [-1/2, 1/2).
+__device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
+                                          int64_t i, double h, int L) {
+    Geom g;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const double x = q[3 * i + b] / h;
+        const double fl = floor(x);
+        const double s = x - fl;  // [0, 1)
+        long long c = (long long)fl % L;
+        if (c < 0) c += L;
+        g.c[b] = (int)c;
+        g.up[b] = s >= 0.5 ? 1 : 0;
+        g.tu[b] = s - (double)g.up[b];
+        g.ts[b] = s - 0.5;
+    }
+    return g;
+}
+
+__device__ __forceinline__ int cell_linear(const Geom& g, int L) {
+    return (g.c[2] * L + g.c[1]) * L + g.c[0];
+}
+
+__device__ __forceinline__ uint32_t cell_pack(const Geom& g) {
+    return (uint32_t)g.c[0] | ((uint32_t)g.c[1] << 9) | ((uint32_t)g.c[2] << 18) |
+           ((uint32_t)g.up[0] << 27) | ((uint32_t)g.up[1] << 28) |
+           ((uint32_t)g.up[2] << 29);
+}
+
+// ---------------------------------------------------------------------------
+// Binning: counting sort of blobs by cell.
+__global__ void __launch_bounds__(BLK)
+k_bin_count(const double* __restrict__ q, int64_t M, double h, int L,
+            int* __restrict__ count, int* __restrict__ rank) {
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i >= M) return;
+    const Geom g = blob_geom(q, i, h, L);
+    rank[i] = atomicAdd(&count[cell_linear(g, L)], 1);
+}
+
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = BLK * SCAN_ITEMS;  // 4096
+
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
+
+// Per-block sums of the counts.
+__global__ void __launch_bounds__(BLK)
+k_scan_reduce(const int* __restrict__ count, int64_t n, int* __restrict__ bsum) {
+    __shared__ double red[16];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + k * BLK + threadIdx.x;
+        if (i < n) s += count[i];
+    }
+    const double tot = block_reduce<false>((double)s, red);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (int)tot;
+}
+
+// Exclusive scan of `vals` (n entries) held in LDS tile `s` of SCAN_TILE
+// entries (padded indexing); returns the tile total.
+__device__ int scan_tile_lds(int* s, int* scratch) {
+    int local[SCAN_ITEMS];
+    int sum = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        local[k] = s[scan_pad(threadIdx.x * SCAN_ITEMS + k)];
+        sum += local[k];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, scratch, &total);
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        s[scan_pad(threadIdx.x * SCAN_ITEMS + k)] = run;
+        run += local[k];
+    }
+    __syncthreads();
+    return total;
+}
+
+// Exclusive scan of the block sums, in place (one block).
+__global__ void __launch_bounds__(BLK)
+k_scan_blocks(int* __restrict__ bsum, int nb) {
+    __shared__ int s[SCAN_TILE + SCAN_TILE / 32];
+    __shared__ int scratch[16];
+    int carry = 0;
+    for (int base = 0; base < nb; base += SCAN_TILE) {
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            const int i = k * BLK + threadIdx.x;
+            s[scan_pad(i)] = (base + i < nb) ? bsum[base + i] : 0;
+        }
+        __syncthreads();
+        const int total = scan_tile_lds(s, scratch);
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            const int i = k * BLK + threadIdx.x;
+            if (base + i < nb) bsum[base + i] = s[scan_pad(i)] + carry;
+        }
+        carry += total;
+        __syncthreads();
+    }
+}
+
+// offs[i] = exclusive prefix of count; offs[n] = total; count reset to 0.
+__global__ void __launch_bounds__(BLK)
+k_scan_apply(int* __restrict__ count, int64_t n, const int* __restrict__ bsum,
+             int* __restrict__ offs) {
+    __shared__ int s[SCAN_TILE + SCAN_TILE / 32];
+    __shared__ int scratch[16];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int i = k * BLK + threadIdx.x;
+        s[scan_pad(i)] = (base + i < n) ? count[base + i] : 0;
+    }
+    __syncthreads();
+    const int total = scan_tile_lds(s, scratch);
+    const int off = bsum[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int i = k * BLK + threadIdx.x;
+        if (base + i < n) {
+            offs[base + i] = s[scan_pad(i)] + off;
+            count[base + i] = 0;
+        }
+    }
+    if (base + SCAN_TILE >= n && threadIdx.x == 0) offs[n] = off + total;
+}
+
+template <typename T>
+__device__ __forceinline__ void write_record(Rec<T>* __restrict__ rec,
+                                             int* __restrict__ perm,
+                                             int64_t pos, int64_t i,
+                                             const Geom& g, const double F[3],
+                                             double inv_vol) {
+    Rec<T> r;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        r.tu[b] = (T)g.tu[b];
+        r.ts[b] = (T)g.ts[b];
+        r.F[b] = (T)(F[b] * inv_vol);
+    }
+    r.cell = cell_pack(g);
+    r.pad = 0;
+    rec[pos] = r;
+    perm[pos] = (int)i;
+}
+
+// Records in cell order for given forces (F may be null: interpolation).
+template <typename T>
+__global__ void __launch_bounds__(BLK)
+k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
+              int64_t M, double h, int L, double inv_vol,
+              const int* __restrict__ offs, const int* __restrict__ rank,
+              Rec<T>* __restrict__ rec, int* __restrict__ perm) {
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i >= M) return;
+    const Geom g = blob_geom(q, i, h, L);
+    double f[3] = {0.0, 0.0, 0.0};
+    if (F) {
+        f[0] = F[3 * i];
+        f[1] = F[3 * i + 1];
+        f[2] = F[3 * i + 2];
+    }
+    const int64_t pos = (int64_t)offs[cell_linear(g, L)] + rank[i];
+    write_record<T>(rec, perm, pos, i, g, f, inv_vol);
+}
+
+// Spring force on blob i (float64): sum over the template pairs of blob b
+// of k (|d| - r0) d / |d| with d = q_other - q_i, plus Fext_p / nb.
+__device__ __forceinline__ void spring_force(const SpringsDev& sp,
+                                             const double* __restrict__ q,
+                                             const double* __restrict__ Fext,
+                                             int64_t i, double F[3]) {
+    const int64_t p = i / sp.nb;
+    const int b = (int)(i - p * sp.nb);
+    const double qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (Fext) {
+        const double inv_nb = 1.0 / (double)sp.nb;
+        fx = Fext[3 * p] * inv_nb;
+        fy = Fext[3 * p + 1] * inv_nb;
+        fz = Fext[3 * p + 2] * inv_nb;
+    }
+    const int e1 = sp.adj_start[b + 1];
+    for (int e = sp.adj_start[b]; e < e1; ++e) {
+        const int64_t j = p * sp.nb + sp.adj_other[e];
+        const double dx = q[3 * j] - qx, dy = q[3 * j + 1] - qy,
+                     dz = q[3 * j + 2] - qz;
+        const double len = sqrt(dx * dx + dy * dy + dz * dz);
+        const double s = sp.k * (len - sp.adj_r0[e]) / len;
+        fx += s * dx;
+        fy += s * dy;
+        fz += s * dz;
+    }
+    F[0] = fx;
+    F[1] = fy;
+    F[2] = fz;
+}
+
+// Spring forces fused with the scatter of the records; also the per-block
+// float64 sums of the blob forces (momentum diagnostics).
+template <typename T>
+__global__ void __launch_bounds__(BLK)
+k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
+                  const double* __restrict__ Fext, int64_t M, double h, int L,
+                  double inv_vol, const int* __restrict__ offs,
+                  const int* __restrict__ rank, Rec<T>* __restrict__ rec,
+                  int* __restrict__ perm, double* __restrict__ fpart) {
+    __shared__ double red[16];
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    double F[3] = {0.0, 0.0, 0.0};
+    if (i < M) {
+        spring_force(sp, q, Fext, i, F);
+        const Geom g = blob_geom(q, i, h, L);
+        const int64_t pos = (int64_t)offs[cell_linear(g, L)] + rank[i];
+        write_record<T>(rec, perm, pos, i, g, F, inv_vol);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double s = block_reduce<false>(F[c], red);
+        if (threadIdx.x == 0) fpart[3 * blockIdx.x + c] = s;
+    }
+}
+
+__global__ void __launch_bounds__(BLK)
+k_springs(SpringsDev sp, const double* __restrict__ q,
+          const double* __restrict__ Fext, int64_t M, double* __restrict__ Fout) {
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i >= M) return;
+    double F[3];
+    spring_force(sp, q, Fext, i, F);
+    Fout[3 * i] = F[0];
+    Fout[3 * i + 1] = F[1];
+    Fout[3 * i + 2] = F[2];
+}
+
+// ---------------------------------------------------------------------------
+// Tile helpers shared by spreading and interpolation.
+struct TileBox {
+    int lo[3];
+    int full[3];
+};
+
+__device__ __forceinline__ TileBox tile_box(const Tiles& t, int L) {
+    int b = blockIdx.x;
+    if (t.remap) b = xcd_remap(b, t.n);
+    TileBox tb;
+    const int ix = b % t.ntx;
+    const int iy = (b / t.ntx) % t.nty;
+    const int iz = b / (t.ntx * t.nty);
+    tb.lo[0] = ix * t.tx;
+    tb.lo[1] = iy * t.ty;
+    tb.lo[2] = iz * t.tz;
+    tb.full[0] = t.tx == L;
+    tb.full[1] = t.ty == L;
+    tb.full[2] = t.tz == L;
+    return tb;
+}
+
+__device__ __forceinline__ int wrapL(int v, int L) {
+    v %= L;
+    return v < 0 ? v + L : v;
+}
+
+// Contiguous ranges of sorted records for the cells of a box of rows.
+// Rows y in [ylo, ylo + ny), z in [zlo, zlo + nz) (wrapped), x cells
+// [xlo, xlo + nx) (wrapped, split in at most two runs).  Fills seg_start /
+// seg_pre (exclusive prefix of lengths) and returns the record count.
+__device__ int gather_segments(const int* __restrict__ offs, int L, int xlo,
+                               int nx, int ylo, int ny, int zlo, int nz,
+                               int* seg_start, int* seg_pre, int* scratch,
+                               int* nseg_out) {
+    // x runs
+    int xs0 = wrapL(xlo, L), xe0, xs1 = 0, xe1 = -1, nxs = 1;
+    if (nx >= L) {
+        xs0 = 0;
+        xe0 = L - 1;
+    } else if (xs0 + nx - 1 < L) {
+        xe0 = xs0 + nx - 1;
+    } else {
+        xe0 = L - 1;
+        xs1 = 0;
+        xe1 = xs0 + nx - 1 - L;
+        nxs = 2;
+    }
+    const int nseg = ny * nz * nxs;
+    // one segment per thread per pass; nseg <= blockDim.x * passes
+    int carry = 0;
+    for (int base = 0; base < nseg; base += blockDim.x) {
+        const int s = base + threadIdx.x;
+        int len = 0;
+        if (s < nseg) {
+            const int xi = s % nxs;
+            const int r = s / nxs;
+            const int y = wrapL(ylo + r % ny, L);
+            const int z = wrapL(zlo + r / ny, L);
+            const int row = (z * L + y) * L;
+            const int a = row + (xi ? xs1 : xs0);
+            const int e = row + (xi ? xe1 : xe0);
+            const int st = offs[a];
+            len = offs[e + 1] - st;
+            seg_start[s] = st;
+        }
+        int total;
+        const int ex = block_exclusive_scan(len, scratch, &total);
+        if (s < nseg) seg_pre[s] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) seg_pre[nseg] = carry;
+    __syncthreads();
+    *nseg_out = nseg;
+    return carry;
+}
+
+__device__ __forceinline__ int find_segment(const int* seg_pre, int nseg, int k) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_pre[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Spreading: one block per tile; every record whose 3x3x3 support may reach
+// the tile (cells [lo-2, hi+1]) is expanded and its in-tile nodes are added
+// to an LDS copy of the tile (LDS atomics), which is then written out once.
+template <typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(BLK)
+k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
+         Tiles tl, T* __restrict__ f) {
+    constexpr int TV = TX * TY * TZ;
+    __shared__ T acc[3 * TV];
+    __shared__ int seg_start[2 * (TY + 3) * (TZ + 3)];
+    __shared__ int seg_pre[2 * (TY + 3) * (TZ + 3) + 1];
+    __shared__ int scratch[16];
+    const TileBox tb = tile_box(tl, L);
+    const int tdim[3] = {tl.tx, tl.ty, tl.tz};
+    for (int i = threadIdx.x; i < 3 * TV; i += BLK) acc[i] = T(0);
+    int nseg;
+    const int ext[3] = {tb.full[0] ? L : tl.tx + 3, tb.full[1] ? L : tl.ty + 3,
+                        tb.full[2] ? L : tl.tz + 3};
+    const int elo[3] = {tb.full[0] ? 0 : tb.lo[0] - 2, tb.full[1] ? 0 : tb.lo[1] - 2,
+                        tb.full[2] ? 0 : tb.lo[2] - 2};
+    const int total = gather_segments(offs, L, elo[0], ext[0], elo[1], ext[1],
+                                      elo[2], ext[2], seg_start, seg_pre,
+                                      scratch, &nseg);
+    for (int k = threadIdx.x; k < total; k += BLK) {
+        const int s = find_segment(seg_pre, nseg, k);
+        const Rec<T> r = rec[seg_start[s] + (k - seg_pre[s])];
+        const int c[3] = {(int)(r.cell & 511u), (int)((r.cell >> 9) & 511u),
+                          (int)((r.cell >> 18) & 511u)};
+        // per axis, per node set (0: cell-centred, 1: shifted): weights and
+        // tile-relative node indices (-1 when outside the tile)
+        T w[3][2][3];
+        int rel[3][2][3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            kernel_weights<T>(r.tu[b], w[b][0]);
+            kernel_weights<T>(r.ts[b], w[b][1]);
+            const int up = (r.cell >> (27 + b)) & 1u;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                int r0 = c[b] + (v == 0 ? up : 0) - 1 - tb.lo[b];
+                if (r0 < 0) r0 += L;
+                if (r0 >= L) r0 -= L;
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    int rr = r0 + o;
+                    if (rr >= L) rr -= L;
+                    rel[b][v][o] = rr < tdim[b] ? rr : -1;
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int vx = a == 0, vy = a == 1, vz = a == 2;
+            T* A = acc + a * TV;
+            const T Fa = r.F[a];
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz) {
+                const int rz = rel[2][vz][oz];
+                if (rz < 0) continue;
+                const T wz = w[2][vz][oz] * Fa;
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy) {
+                    const int ry = rel[1][vy][oy];
+                    if (ry < 0) continue;
+                    const T wyz = w[1][vy][oy] * wz;
+#pragma unroll
+                    for (int ox = 0; ox < 3; ++ox) {
+                        const int rx = rel[0][vx][ox];
+                        if (rx < 0) continue;
+                        atomicAdd(&A[(rz * TY + ry) * TX + rx], w[0][vx][ox] * wyz);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t N = (int64_t)L * L * L;
+    for (int i = threadIdx.x; i < 3 * TV; i += BLK) {
+        const int a = i / TV;
+        const int rem = i - a * TV;
+        const int x = rem % TX;
+        const int y = (rem / TX) % TY;
+        const int z = rem / (TX * TY);
+        f[a * N + ((int64_t)(tb.lo[2] + z) * L + tb.lo[1] + y) * L + tb.lo[0] + x] = acc[i];
+    }
+}
+
+// Interpolation: one block per tile; the field on nodes [lo-1, hi+2] of all
+// three components is staged in LDS, then every record of the tile's cells
+// gathers its 27 nodes per component.  With q_update the blob is moved by
+// dt*u; with diag the block also writes its float64 sum of each component
+// and the max |Dv| over its cells.
+template <typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(BLK)
+k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
+         const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
+         double* __restrict__ u_out, double* __restrict__ q, double dt,
+         double inv_h, double* __restrict__ part) {
+    constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
+    constexpr int EV = EX * EY * EZ;
+    __shared__ T vt[3 * EV];
+    __shared__ int seg_start[TY * TZ];
+    __shared__ int seg_pre[TY * TZ + 1];
+    __shared__ int scratch[16];
+    __shared__ double red[16];
+    const TileBox tb = tile_box(tl, L);
+    const int64_t N = (int64_t)L * L * L;
+    for (int i = threadIdx.x; i < 3 * EV; i += BLK) {
+        const int a = i / EV;
+        const int rem = i - a * EV;
+        const int ex = rem % EX;
+        const int ey = (rem / EX) % EY;
+        const int ez = rem / (EX * EY);
+        const int x = wrapL(tb.lo[0] - 1 + ex, L);
+        const int y = wrapL(tb.lo[1] - 1 + ey, L);
+        const int z = wrapL(tb.lo[2] - 1 + ez, L);
+        vt[i] = v[a * N + ((int64_t)z * L + y) * L + x];
+    }
+    __syncthreads();
+    int nseg;
+    const int total = gather_segments(offs, L, tb.lo[0], tl.tx, tb.lo[1], tl.ty,
+                                      tb.lo[2], tl.tz, seg_start, seg_pre,
+                                      scratch, &nseg);
+    for (int k = threadIdx.x; k < total; k += BLK) {
+        const int s = find_segment(seg_pre, nseg, k);
+        const int pos = seg_start[s] + (k - seg_pre[s]);
+        const Rec<T> r = rec[pos];
+        const int c[3] = {(int)(r.cell & 511u), (int)((r.cell >> 9) & 511u),
+                          (int)((r.cell >> 18) & 511u)};
+        T w[3][2][3];
+        int e0[3][2];  // extended-tile index of node i0 - 1
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            kernel_weights<T>(r.tu[b], w[b][0]);
+            kernel_weights<T>(r.ts[b], w[b][1]);
+            const int up = (r.cell >> (27 + b)) & 1u;
+            const int rc = c[b] - tb.lo[b];  // in [0, T)
+            e0[b][0] = rc + up;              // (i0 - 1) - (lo - 1)
+            e0[b][1] = rc;
+        }
+        double u[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int vx = a == 0, vy = a == 1, vz = a == 2;
+            const T* V = vt + a * EV;
+            T acc = T(0);
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz) {
+                const int z = e0[2][vz] + oz;
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy) {
+                    const int y = e0[1][vy] + oy;
+                    const T wyz = w[2][vz][oz] * w[1][vy][oy];
+                    const T* row = V + (z * EY + y) * EX + e0[0][vx];
+                    T sx = w[0][vx][0] * row[0] + w[0][vx][1] * row[1] + w[0][vx][2] * row[2];
+                    acc += wyz * sx;
+                }
+            }
+            u[a] = (double)acc;
+        }
+        const int64_t i = perm[pos];
+        if (u_out) {
+            u_out[3 * i] = u[0];
+            u_out[3 * i + 1] = u[1];
+            u_out[3 * i + 2] = u[2];
+        }
+        if (q) {
+            q[3 * i] += dt * u[0];
+            q[3 * i + 1] += dt * u[1];
+            q[3 * i + 2] += dt * u[2];
+        }
+    }
+    if (part) {
+        double sv[3] = {0.0, 0.0, 0.0};
+        double dmax = 0.0;
+        const int TV = TX * TY * TZ;
+        for (int i = threadIdx.x; i < TV; i += BLK) {
+            const int x = i % TX + 1;
+            const int y = (i / TX) % TY + 1;
+            const int z = i / (TX * TY) + 1;
+            const int c0 = (z * EY + y) * EX + x;
+            const T vxc = vt[c0], vyc = vt[EV + c0], vzc = vt[2 * EV + c0];
+            sv[0] += (double)vxc;
+            sv[1] += (double)vyc;
+            sv[2] += (double)vzc;
+            const double dv = ((double)(vxc - vt[c0 - 1]) +
+                               (double)(vyc - vt[EV + c0 - EX]) +
+                               (double)(vzc - vt[2 * EV + c0 - EX * EY])) * inv_h;
+            dmax = fmax(dmax, fabs(dv));
+        }
+        const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
+        for (int a = 0; a < 3; ++a) {
+            const double s = block_reduce<false>(sv[a], red);
+            if (threadIdx.x == 0) part[4 * tile + a] = s;
+        }
+        const double m = block_reduce<true>(dmax, red);
+        if (threadIdx.x == 0) part[4 * tile + 3] = m;
+    }
+}
+
+__global__ void __launch_bounds__(BLK)
+k_u0(const double* __restrict__ u, int64_t P, int nb, double* __restrict__ U0) {
+    const int64_t p = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (p >= P) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < nb; ++b)
+        for (int c = 0; c < 3; ++c) s[c] += u[3 * (p * nb + b) + c];
+    for (int c = 0; c < 3; ++c) U0[3 * p + c] = s[c] / (double)nb;
+}
+
+__global__ void __launch_bounds__(BLK)
+k_diag(const double* __restrict__ tile_part, int ntiles,
+       const double* __restrict__ force_part, int nfb, double mom_scale,
+       double* __restrict__ diag) {
+    __shared__ double red[16];
+    double s[3] = {0.0, 0.0, 0.0}, sf[3] = {0.0, 0.0, 0.0}, mx = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += BLK) {
+        for (int c = 0; c < 3; ++c) s[c] += tile_part[4 * i + c];
+        mx = fmax(mx, tile_part[4 * i + 3]);
+    }
+    for (int i = threadIdx.x; i < nfb; i += BLK)
+        for (int c = 0; c < 3; ++c) sf[c] += force_part[3 * i + c];
+    for (int c = 0; c < 3; ++c) {
+        const double a = block_reduce<false>(s[c], red);
+        const double b = block_reduce<false>(sf[c], red);
+        if (threadIdx.x == 0) {
+            diag[c] = mom_scale * a;
+            diag[3 + c] = b;
+        }
+    }
+    const double m = block_reduce<true>(mx, red);
+    if (threadIdx.x == 0) diag[6] = m;
+}
+
+// ---------------------------------------------------------------------------
+// FFT passes.  Spectrum layout [3][L(z)][L(y)][NC(kx)], NC = L/2 + 1.
+constexpr int EPT = 8;
+
+// Forward x pass.  Each block takes `rows` consecutive (component, z, y)
+// rows, forms the right-hand side r = a v + b (7-point Laplacian of v) + f
+// (Crank-Nicolson explicit half; r = f in steady mode), packs row pairs as
+// one complex line (z = r_even + i r_odd), transforms along x and unpacks
+// the two half spectra.  Also the block's float64 sums of v and f.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_fft_x_fwd(const T* __restrict__ v, const T* __restrict__ f, int L, int NC,
+            FFTPlan pl, const cplx<T>* __restrict__ tw, T a, T b, int steady,
+            int rows, cplx<T>* __restrict__ spec, double* __restrict__ psum) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    __shared__ double red[16];
+    const int nlines = rows / 2;
+    const int nthr = blockDim.x;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    const int64_t LL = (int64_t)L * L;
+    double sv = 0.0, sf = 0.0;
+    for (int e = tid; e < nlines * L; e += nthr) {
+        const int line = e / L;
+        const int x = e - line * L;
+        T val[2];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int64_t row = r0 + 2 * line + hh;
+            const int y = (int)(row % L);
+            const int64_t zc = row / L;  // c * L + z
+            const int z = (int)(zc % L);
+            const int64_t cbase = (zc - z) * LL;  // component offset
+            const int64_t idx = row * L + x;
+            const T fv = f[idx];
+            sf += (double)fv;
+            if (steady) {
+                val[hh] = fv;
+            } else {
+                const T vc = v[idx];
+                sv += (double)vc;
+                const int xm = x == 0 ? L - 1 : x - 1, xp = x == L - 1 ? 0 : x + 1;
+                const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+                const int zm = z == 0 ? L - 1 : z - 1, zp = z == L - 1 ? 0 : z + 1;
+                const int64_t rb = row * L;
+                const T lap = (v[rb + xm] + v[rb + xp]) +
+                              (v[cbase + ((int64_t)z * L + ym) * L + x] +
+                               v[cbase + ((int64_t)z * L + yp) * L + x]) +
+                              (v[cbase + ((int64_t)zm * L + y) * L + x] +
+                               v[cbase + ((int64_t)zp * L + y) * L + x]) -
+                              T(6) * vc;
+                val[hh] = a * vc + b * lap + fv;
+            }
+        }
+        buf[line * L + x] = cplx<T>{val[0], val[1]};
+    }
+    __syncthreads();
+    lds_fft<T, false, EPT, false>(buf, pl, nlines, 1, L, tw, tid, nthr);
+    for (int e = tid; e < nlines * NC; e += nthr) {
+        const int line = e / NC;
+        const int k = e - line * NC;
+        const cplx<T> Z = buf[line * L + k];
+        const cplx<T> Zc = cconj(buf[line * L + (k == 0 ? 0 : L - k)]);
+        const cplx<T> s = cadd(Z, Zc), d = csub(Z, Zc);
+        const int64_t row = r0 + 2 * line;
+        spec[row * NC + k] = cplx<T>{T(0.5) * s.x, T(0.5) * s.y};
+        spec[(row + 1) * NC + k] = cplx<T>{T(0.5) * d.y, T(-0.5) * d.x};
+    }
+    const double ts = block_reduce<false>(sv, red);
+    const double tf = block_reduce<false>(sf, red);
+    if (tid == 0) {
+        psum[2 * blockIdx.x] = ts;
+        psum[2 * blockIdx.x + 1] = tf;
+    }
+}
+
+// y pass (forward or inverse), in place: block = (component, z plane, chunk
+// of W kx columns); each column is one line of length L.
+template <typename T, bool INV>
+__global__ void __launch_bounds__(1024)
+k_fft_y(cplx<T>* __restrict__ spec, int L, int NC, int W, FFTPlan pl,
+        const cplx<T>* __restrict__ tw) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int nch = (NC + W - 1) / W;
+    const int ch = blockIdx.x % nch;
+    const int64_t plane = blockIdx.x / nch;
+    const int kx0 = ch * W;
+    const int wc = min(W, NC - kx0);
+    cplx<T>* base = spec + plane * L * NC + kx0;
+    for (int e = threadIdx.x; e < L * W; e += blockDim.x) {
+        const int y = e / W;
+        const int col = e - y * W;
+        if (col < wc) buf[e] = base[(int64_t)y * NC + col];
+    }
+    __syncthreads();
+    lds_fft<T, INV, EPT, true>(buf, pl, wc, W, 1, tw, threadIdx.x, blockDim.x);
+    for (int e = threadIdx.x; e < L * W; e += blockDim.x) {
+        const int y = e / W;
+        const int col = e - y * W;
+        if (col < wc) base[(int64_t)y * NC + col] = buf[e];
+    }
+}
+
+// z pass fused with the spectral solve: block = (y row, chunk of W kx
+// columns) for all three components; forward transform along z, then per
+// wavevector m != 0
+//   v^ = (r^ - conj(D) (D . r^) / |D|^2) / (den |D|^2-dependent * N)
+// (the solenoidal projection of eq. vf on the MAC grid, D the divergence
+// symbol), the mean mode set from the float64 sums, then the inverse
+// transform along z.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_fft_z_spectral(cplx<T>* __restrict__ spec, int L, int NC, int W, FFTPlan pl,
+                 const cplx<T>* __restrict__ tw,
+                 const cplx<T>* __restrict__ dsym, const T* __restrict__ d2,
+                 T c0, T c1, int steady, int zero_mean,
+                 const double* __restrict__ psum, int nblk_x, double mean_v_scale,
+                 double mean_f_scale) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    __shared__ double red[16];
+    __shared__ double mean_new[3];
+    const int nch = (NC + W - 1) / W;
+    const int ch = blockIdx.x % nch;
+    const int y = blockIdx.x / nch;
+    const int kx0 = ch * W;
+    const int wc = min(W, NC - kx0);
+    const int64_t LL = (int64_t)L * L;
+    const int W3 = 3 * W;
+    for (int e = threadIdx.x; e < L * W3; e += blockDim.x) {
+        const int z = e / W3;
+        const int rem = e - z * W3;
+        const int c = rem / W;
+        const int col = rem - c * W;
+        cplx<T> val = {T(0), T(0)};
+        if (col < wc) val = spec[((int64_t)c * L + z) * (int64_t)L * NC + (int64_t)y * NC + kx0 + col];
+        buf[e] = val;
+    }
+    const bool owns_mean = (y == 0 && ch == 0);
+    if (owns_mean) {
+        // float64 mean of the new velocity: mean(v) + (dt/rho) mean(f)
+        const int per_c = nblk_x / 3;
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int i = threadIdx.x; i < per_c; i += blockDim.x) {
+                const double* p = psum + 2 * (c * per_c + i);
+                s += mean_v_scale * p[0] + mean_f_scale * p[1];
+            }
+            s = block_reduce<false>(s, red);
+            if (threadIdx.x == 0) mean_new[c] = (steady || zero_mean) ? 0.0 : s;
+        }
+    }
+    __syncthreads();
+    lds_fft<T, false, EPT, true>(buf, pl, W3, W3, 1, tw, threadIdx.x, blockDim.x);
+    for (int e = threadIdx.x; e < L * W; e += blockDim.x) {
+        const int kz = e / W;
+        const int col = e - kz * W;
+        if (col >= wc) continue;
+        const int kx = kx0 + col;
+        cplx<T>* X = buf + kz * W3 + col;
+        if (kx == 0 && y == 0 && kz == 0) {
+            X[0] = cplx<T>{(T)mean_new[0], T(0)};
+            X[W] = cplx<T>{(T)mean_new[1], T(0)};
+            X[2 * W] = cplx<T>{(T)mean_new[2], T(0)};
+            continue;
+        }
+        const cplx<T> Dx = dsym[kx], Dy = dsym[y], Dz = dsym[kz];
+        const T D2 = d2[kx] + d2[y] + d2[kz];
+        const cplx<T> rx = X[0], ry = X[W], rz = X[2 * W];
+        const cplx<T> div = cadd(cadd(cmul(Dx, rx), cmul(Dy, ry)), cmul(Dz, rz));
+        const T inv_d2 = T(1) / D2;
+        // scale = 1 / ((c0 + c1 |D|^2) N); steady: c0 = 0, c1 = eta N
+        const T scale = T(1) / (c0 + c1 * D2);
+        const cplx<T> g = {div.x * inv_d2, div.y * inv_d2};
+        const cplx<T> px = csub(rx, cmul(cconj(Dx), g));
+        const cplx<T> py = csub(ry, cmul(cconj(Dy), g));
+        const cplx<T> pz = csub(rz, cmul(cconj(Dz), g));
+        X[0] = cplx<T>{px.x * scale, px.y * scale};
+        X[W] = cplx<T>{py.x * scale, py.y * scale};
+        X[2 * W] = cplx<T>{pz.x * scale, pz.y * scale};
+    }
+    __syncthreads();
+    lds_fft<T, true, EPT, true>(buf, pl, W3, W3, 1, tw, threadIdx.x, blockDim.x);
+    for (int e = threadIdx.x; e < L * W3; e += blockDim.x) {
+        const int z = e / W3;
+        const int rem = e - z * W3;
+        const int c = rem / W;
+        const int col = rem - c * W;
+        if (col < wc)
+            spec[((int64_t)c * L + z) * (int64_t)L * NC + (int64_t)y * NC + kx0 + col] = buf[e];
+    }
+    (void)LL;
+}
+
+// Inverse x pass: row pairs of half spectra are combined into one complex
+// line Z = X_even + i X_odd (Hermitian extension for kx > L/2, imaginary
+// parts of kx = 0 and L/2 dropped), transformed, and the real and imaginary
+// parts written as the two velocity rows.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_fft_x_inv(const cplx<T>* __restrict__ spec, int L, int NC, FFTPlan pl,
+            const cplx<T>* __restrict__ tw, int rows, T* __restrict__ vout) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int nlines = rows / 2;
+    const int nthr = blockDim.x;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    const int half = L / 2;
+    for (int e = tid; e < nlines * L; e += nthr) {
+        const int line = e / L;
+        const int k = e - line * L;
+        const int64_t row = r0 + 2 * line;
+        cplx<T> X1, X2;
+        if (k <= half) {
+            X1 = spec[row * NC + k];
+            X2 = spec[(row + 1) * NC + k];
+            if (k == 0 || k == half) {
+                X1.y = T(0);
+                X2.y = T(0);
+            }
+        } else {
+            X1 = cconj(spec[row * NC + (L - k)]);
+            X2 = cconj(spec[(row + 1) * NC + (L - k)]);
+        }
+        buf[e] = cplx<T>{X1.x - X2.y, X1.y + X2.x};
+    }
+    __syncthreads();
+    lds_fft<T, true, EPT, false>(buf, pl, nlines, 1, L, tw, tid, nthr);
+    for (int e = tid; e < nlines * L; e += nthr) {
+        const int line = e / L;
+        const int x = e - line * L;
+        const int64_t row = r0 + 2 * line;
+        const cplx<T> z = buf[e];
+        vout[row * L + x] = z.x;
+        vout[(row + 1) * L + x] = z.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+#define MB_LAUNCH(g, id, s, kern, grid, block, shm, ...)                 \
+    do {                                                                 \
+        hipEvent_t ev_ = nullptr;                                        \
+        timer_begin((g), (id), (s), &ev_);                               \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), (shm), (s),    \
+                           __VA_ARGS__);                                 \
+        timer_end((g), (id), (s), ev_);                                  \
+    } while (0)
+
+static inline unsigned blocks_for(int64_t n) {
+    return (unsigned)((n + BLK - 1) / BLK);
+}
+
+template <typename T>
+hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
+    if (M > 0)
+        MB_LAUNCH(g, K_BIN_COUNT, s, k_bin_count, blocks_for(M), BLK, 0, q, M,
+                  g->d.h, g->L, g->d_count, g->d_rank);
+    MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
+              g->N, g->d_bsum);
+    MB_LAUNCH(g, K_SCAN_BLOCKS, s, k_scan_blocks, 1, BLK, 0, g->d_bsum, g->nscan);
+    MB_LAUNCH(g, K_SCAN_APPLY, s, k_scan_apply, g->nscan, BLK, 0, g->d_count,
+              g->N, g->d_bsum, g->d_offs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
+                           const double* F, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    const double h = g->d.h;
+    MB_LAUNCH(g, K_BIN_SCATTER, s, k_bin_scatter<T>, blocks_for(M), BLK, 0, q, F,
+              M, h, g->L, 1.0 / (h * h * h), g->d_offs, g->d_rank,
+              (Rec<T>*)g->d_rec, g->d_perm);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
+                           const double* q, const double* Fext, hipStream_t s) {
+    const int64_t M = P * sp.nb;
+    if (M == 0) return hipSuccess;
+    const double h = g->d.h;
+    MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, blocks_for(M), BLK, 0,
+              sp, q, Fext, M, h, g->L, 1.0 / (h * h * h), g->d_offs, g->d_rank,
+              (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part);
+    return hipGetLastError();
+}
+
+hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
+                         const double* Fext, double* F, hipStream_t s,
+                         mb_grid* tg) {
+    const int64_t M = P * sp.nb;
+    if (M == 0) return hipSuccess;
+    MB_LAUNCH(tg, K_SPRINGS, s, k_springs, blocks_for(M), BLK, 0, sp, q, Fext, M, F);
+    return hipGetLastError();
+}
+
+template <typename T, int TX>
+static void launch_spread(mb_grid* g, T* f, hipStream_t s) {
+    MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, TX, 8, 8>), g->tiles.n, BLK, 0,
+              (const Rec<T>*)g->d_rec, g->d_offs, g->L, g->tiles, f);
+}
+
+template <typename T>
+hipError_t spread(mb_grid* g, T* f, hipStream_t s) {
+    switch (g->tiles.tx) {
+        case 32: launch_spread<T, 32>(g, f, s); break;
+        case 16: launch_spread<T, 16>(g, f, s); break;
+        default: launch_spread<T, 8>(g, f, s); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int TX>
+static void launch_interp(mb_grid* g, const T* v, double* u_out, double* q,
+                          double* part, int kid, hipStream_t s) {
+    MB_LAUNCH(g, kid, s, (k_interp<T, TX, 8, 8>), g->tiles.n, BLK, 0,
+              (const Rec<T>*)g->d_rec, g->d_perm, g->d_offs, g->L, g->tiles, v,
+              u_out, q, g->d.dt, 1.0 / g->d.h, part);
+}
+
+template <typename T>
+hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
+                       double* q_update, int diag, hipStream_t s) {
+    (void)M;
+    double* part = diag ? g->d_tile_part : nullptr;
+    const int kid = q_update ? K_INTERP_STEP : K_INTERP;
+    switch (g->tiles.tx) {
+        case 32: launch_interp<T, 32>(g, v, u_out, q_update, part, kid, s); break;
+        case 16: launch_interp<T, 16>(g, v, u_out, q_update, part, kid, s); break;
+        default: launch_interp<T, 8>(g, v, u_out, q_update, part, kid, s); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fluid_solve(mb_grid* g, const T* v_in, const T* f, T* v_out,
+                       hipStream_t s) {
+    const int L = g->L, NC = g->NC;
+    const bool steady = g->d.mode == MB_STEADY_STOKES;
+    const double h = g->d.h;
+    const double N = (double)g->N;
+    cplx<T>* spec = (cplx<T>*)g->d_spec;
+    const cplx<T>* tw = (const cplx<T>*)g->d_tw;
+    // explicit half of Crank-Nicolson: r = (rho/dt) v + (eta/2) L_h v + f
+    const T a = steady ? T(0) : (T)(g->d.rho / g->d.dt);
+    const T b = steady ? T(0) : (T)(0.5 * g->d.eta / (h * h));
+    const int rows = g->rows_x;
+    const int tx = (rows / 2) * L / EPT;
+    const size_t shx = (size_t)(rows / 2) * L * sizeof(cplx<T>);
+    MB_LAUNCH(g, K_FFT_X_FWD, s, k_fft_x_fwd<T>, g->nblk_x, tx, shx, v_in, f, L,
+              NC, g->plan, tw, a, b, (int)steady, rows, spec, g->d_psum);
+    const int nchy = (NC + g->wy - 1) / g->wy;
+    const int ty = L * g->wy / EPT;
+    const size_t shy = (size_t)L * g->wy * sizeof(cplx<T>);
+    MB_LAUNCH(g, K_FFT_Y_FWD, s, (k_fft_y<T, false>), 3 * L * nchy, ty, shy, spec,
+              L, NC, g->wy, g->plan, tw);
+    const int nchz = (NC + g->wz - 1) / g->wz;
+    const int tz = 3 * L * g->wz / EPT;
+    const size_t shz = (size_t)3 * L * g->wz * sizeof(cplx<T>);
+    // implicit half: 1 / ((rho/dt + (eta/2)|D|^2) N); steady: 1 / (eta |D|^2 N)
+    const T c0 = steady ? T(0) : (T)(g->d.rho / g->d.dt * N);
+    const T c1 = steady ? (T)(g->d.eta * N) : (T)(0.5 * g->d.eta * N);
+    const double mv = steady ? 0.0 : 1.0 / N;
+    const double mf = steady ? 0.0 : g->d.dt / g->d.rho / N;
+    MB_LAUNCH(g, K_FFT_Z_SPECTRAL, s, k_fft_z_spectral<T>, L * nchz, tz, shz, spec,
+              L, NC, g->wz, g->plan, tw, (const cplx<T>*)g->d_dsym,
+              (const T*)g->d_d2, c0, c1, (int)steady, g->d.zero_mean, g->d_psum,
+              g->nblk_x, mv, mf);
+    MB_LAUNCH(g, K_FFT_Y_INV, s, (k_fft_y<T, true>), 3 * L * nchy, ty, shy, spec, L,
+              NC, g->wy, g->plan, tw);
+    MB_LAUNCH(g, K_FFT_X_INV, s, k_fft_x_inv<T>, g->nblk_x, tx, shx, spec, L, NC,
+              g->plan, tw, rows, v_out);
+    return hipGetLastError();
+}
+
+hipError_t particle_means(mb_grid* g, int64_t P, int nb, const double* u,
+                          double* U0, hipStream_t s) {
+    if (P == 0) return hipSuccess;
+    MB_LAUNCH(g, K_U0, s, k_u0, blocks_for(P), BLK, 0, u, P, nb, U0);
+    return hipGetLastError();
+}
+
+hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,
+                       hipStream_t s) {
+    const double h = g->d.h;
+    const double scale = g->d.rho * h * h * h;
+    MB_LAUNCH(g, K_DIAG, s, k_diag, 1, BLK, 0, g->d_tile_part, g->tiles.n,
+              g->d_force_part, force_blocks, scale, diag);
+    return hipGetLastError();
+}
+
+// Explicit instantiations.
+template hipError_t bin_blobs<float>(mb_grid*, int64_t, const double*, hipStream_t);
+template hipError_t bin_blobs<double>(mb_grid*, int64_t, const double*, hipStream_t);
+template hipError_t scatter_records<float>(mb_grid*, int64_t, const double*, const double*, hipStream_t);
+template hipError_t scatter_records<double>(mb_grid*, int64_t, const double*, const double*, hipStream_t);
+template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t);
+template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t);
+template hipError_t spread<float>(mb_grid*, float*, hipStream_t);
+template hipError_t spread<double>(mb_grid*, double*, hipStream_t);
+template hipError_t fluid_solve<float>(mb_grid*, const float*, const float*, float*, hipStream_t);
+template hipError_t fluid_solve<double>(mb_grid*, const double*, const double*, double*, hipStream_t);
+template hipError_t interpolate<float>(mb_grid*, int64_t, const float*, double*, double*, int, hipStream_t);
+template hipError_t interpolate<double>(mb_grid*, int64_t, const double*, double*, double*, int, hipStream_t);
+
+size_t record_size(int precision) {
+    return precision == MB_MIXED ? sizeof(Rec<float>) : sizeof(Rec<double>);
+}
+
+}  // namespace mb

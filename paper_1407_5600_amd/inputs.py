@@ -334,3 +334,38 @@ def random_field(seed: int, L: int, scale: float = 1.0) -> np.ndarray:
     """A (3, L, L, L) Gaussian staggered field."""
     rng = np.random.default_rng(seed)
     return scale * rng.standard_normal((3, L, L, L))
+
+
+_GENERATORS = {"single": single, "dense": dense, "large": large, "pair": pair,
+               "diff": diff}
+
+
+def cached(name: str, **kw) -> Workload:
+    """A named workload, generated once and kept as .npz under the directory
+    in $MB_INPUT_CACHE (default: the system temporary directory).  The file
+    holds exactly what the generator returned, so cached and fresh inputs
+    are identical."""
+    import hashlib
+    import os
+    import tempfile
+    key = hashlib.sha1(repr((name, sorted(kw.items()))).encode()).hexdigest()[:16]
+    root = os.environ.get("MB_INPUT_CACHE",
+                          os.path.join(tempfile.gettempdir(), "mb_input_cache"))
+    path = os.path.join(root, f"{name}_{key}.npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        tmpl = z["template"]
+        pa, pb, r0 = z["pa"], z["pb"], z["r0"]
+        sc = z["scalars"]
+        return Workload(name, int(sc[0]), float(sc[1]), float(sc[2]), float(sc[3]),
+                        float(sc[4]), int(sc[5]), z["q"], z["Fext"], int(sc[6]),
+                        pa, pb, r0, float(sc[7]), tmpl,
+                        {k[6:]: float(z[k]) for k in z.files if k.startswith("extra_")})
+    w = _GENERATORS[name](**kw)
+    os.makedirs(root, exist_ok=True)
+    tmp = path + f".{os.getpid()}.tmp.npz"
+    np.savez(tmp, q=w.q, Fext=w.Fext, template=w.template, pa=w.pa, pb=w.pb, r0=w.r0,
+             scalars=np.array([w.L, w.h, w.rho, w.eta, w.dt, w.steps, w.nb, w.k]),
+             **{f"extra_{k}": v for k, v in w.extra.items()})
+    os.replace(tmp, path)
+    return w

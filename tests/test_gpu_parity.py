@@ -1,0 +1,296 @@
+"""GPU parity: every call of the HIP library against the oracle on the same
+seeded inputs.  Tolerances are norm-wise relative per output array,
+||x - x_ref||_2 / ||x_ref||_2: 1e-12 for the float64 path and 1e-5 for the
+mixed path (float32 fields), the targets the method's precision variants
+are held to; element-wise bounds are checked against the array maximum."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1407_5600_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1407_5600_amd  # noqa: F401  (loads the library, fails loudly)
+    return torch
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b.ravel())
+    return np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0)
+
+
+def check(name, got, ref, prec, factor=1.0, floor=0.0):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    r = np.linalg.norm((got - ref).ravel()) / max(np.linalg.norm(ref.ravel()), floor, 1e-300)
+    tol = TOL[prec] * factor
+    say(f"{name}: rel err {r:.3e} (tol {tol:.0e})")
+    assert r <= tol, f"{name}: relative error {r:.3e} > {tol:.0e}"
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    assert np.max(np.abs(got - ref)) <= 10 * tol * max(scale, floor)
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def grid(L, prec, max_blobs=0, **kw):
+    from paper_1407_5600_amd import Grid
+    return Grid(L, precision=prec, max_blobs=max_blobs, **kw)
+
+
+def blobs(seed, M, L, mode):
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(0, L, size=(M, 3))
+    if mode == "seam":
+        q[: M // 2] = rng.choice([0.0, L - 1e-9, 1e-12, L / 2.0], size=(M // 2, 3)) + \
+            rng.uniform(-0.6, 0.6, size=(M // 2, 3))
+    elif mode == "unwrapped":
+        q += rng.integers(-40, 40, size=(M, 3)) * L
+    elif mode == "one_cell":
+        q = 5.0 + rng.uniform(0.0, 1.0, size=(M, 3))
+    return q
+
+
+SIZES = [8, 16, 24, 32, 48, 64]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("L", SIZES)
+@pytest.mark.parametrize("mode", ["uniform", "seam", "unwrapped", "one_cell"])
+def test_spread(torch_cuda, prec, L, mode):
+    torch = torch_cuda
+    say("spread", prec, L, mode)
+    M = 700
+    q = blobs(L * 7 + len(mode), M, L, mode)
+    F = np.random.default_rng(L).standard_normal((M, 3))
+    g = grid(L, prec, M)
+    f = g.spread(dev(torch, q), dev(torch, F))
+    torch.cuda.synchronize()
+    ref = oracle.spread(oracle.params(L), q, F)
+    check(f"spread {prec} L={L} {mode}", f.double().cpu().numpy(), ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_spread_h_and_empty(torch_cuda, prec):
+    torch = torch_cuda
+    say("spread h/empty", prec)
+    L, h = 32, 0.7
+    q = blobs(3, 400, L * h, "uniform")
+    F = np.random.default_rng(4).standard_normal((400, 3))
+    g = grid(L, prec, 400, h=h)
+    f = g.spread(dev(torch, q), dev(torch, F))
+    ref = oracle.spread(oracle.params(L, h=h), q, F)
+    check(f"spread h={h}", f.double().cpu().numpy(), ref, prec)
+    z = g.spread(dev(torch, np.zeros((0, 3))), dev(torch, np.zeros((0, 3))))
+    torch.cuda.synchronize()
+    assert float(z.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("L", SIZES)
+@pytest.mark.parametrize("mode", ["uniform", "seam", "unwrapped", "one_cell"])
+def test_interpolate(torch_cuda, prec, L, mode):
+    torch = torch_cuda
+    say("interp", prec, L, mode)
+    M = 700
+    q = blobs(L * 11 + len(mode), M, L, mode)
+    v = np.random.default_rng(L + 1).standard_normal((3, L, L, L))
+    g = grid(L, prec, M)
+    vt = torch.from_numpy(v).to(g.field_dtype).cuda()
+    u = g.interpolate(dev(torch, q), vt)
+    torch.cuda.synchronize()
+    vin = vt.double().cpu().numpy()  # the field as the GPU sees it
+    ref = oracle.interpolate(oracle.params(L), q, vin)
+    check(f"interp {prec} L={L} {mode}", u.cpu().numpy(), ref, prec)
+
+
+def test_spring_forces(torch_cuda):
+    torch = torch_cuda
+    from paper_1407_5600_amd import Springs, spring_forces
+    say("springs")
+    w = inputs.random_suspension(21, 24, 30)
+    rng = np.random.default_rng(0)
+    q = w.q + 0.03 * rng.standard_normal(w.q.shape)
+    sp = Springs(13, w.pa, w.pb, w.r0, w.k)
+    F = spring_forces(sp, dev(torch, q), dev(torch, w.Fext))
+    torch.cuda.synchronize()
+    ref = oracle.spring_forces(w.P, 13, w.pa, w.pb, w.r0, w.k, q, w.Fext)
+    check("springs", F.cpu().numpy(), ref, "fp64")
+    F0 = spring_forces(sp, dev(torch, q), None)
+    ref0 = oracle.spring_forces(w.P, 13, w.pa, w.pb, w.r0, w.k, q, None)
+    check("springs no Fext", F0.cpu().numpy(), ref0, "fp64")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("L", SIZES + [96])
+@pytest.mark.parametrize("mode", ["unsteady", "unsteady0", "steady", "ideal"])
+def test_fluid_solve(torch_cuda, prec, L, mode):
+    torch = torch_cuda
+    say("solve", prec, L, mode)
+    rng = np.random.default_rng(L + len(mode))
+    v = rng.standard_normal((3, L, L, L))
+    f = rng.standard_normal((3, L, L, L)) + 0.3
+    kw = dict(rho=1.3, eta=0.7, dt=0.05)
+    if mode == "unsteady0":
+        kw["zero_mean"] = True
+    if mode == "steady":
+        kw.update(mode="steady", zero_mean=True)
+    if mode == "ideal":
+        kw["eta"] = 0.0
+    g = grid(L, prec, 0, **kw)
+    vt = torch.from_numpy(v).to(g.field_dtype).cuda()
+    ft = torch.from_numpy(f).to(g.field_dtype).cuda()
+    out = g.fluid_solve(vt, ft)
+    torch.cuda.synchronize()
+    prm = oracle.params(L, rho=kw["rho"], eta=kw["eta"], dt=kw["dt"],
+                        steady=mode == "steady", zero_mean=kw.get("zero_mean", False))
+    ref = oracle.fluid_solve(prm, vt.double().cpu().numpy(), ft.double().cpu().numpy())
+    check(f"solve {prec} L={L} {mode}", out.double().cpu().numpy(), ref, prec)
+    # in place (v_in == v_out)
+    g.fluid_solve(vt, ft, vt)
+    torch.cuda.synchronize()
+    check(f"solve in place {prec} L={L} {mode}", vt.double().cpu().numpy(), ref, prec)
+
+
+@pytest.mark.parametrize("prec,L", [("fp64", 256), ("mixed", 256), ("mixed", 512)])
+def test_fluid_solve_large_shear_mode(torch_cuda, prec, L):
+    """Largest grids, checked by a property that holds at any size: a shear
+    mode v_x = sin(2 pi m y / L) decays by exactly g = (1 - nu dt lam/2) /
+    (1 + nu dt lam/2) per Crank-Nicolson step, lam = 4 sin^2(pi m/L)/h^2."""
+    torch = torch_cuda
+    say("solve shear", prec, L)
+    rho, eta, dt, m = 1.0, 1.0, 0.5, 3
+    g = grid(L, prec, 0, rho=rho, eta=eta, dt=dt)
+    v = g.field()
+    y = torch.arange(L, dtype=torch.float64, device="cuda")
+    prof = torch.sin(2 * math.pi * m * y / L)
+    v[0] = prof[None, :, None].to(g.field_dtype)
+    f = g.field()
+    out = g.fluid_solve(v, f)
+    torch.cuda.synchronize()
+    lam = 4 * math.sin(math.pi * m / L) ** 2
+    gg = (1 - eta / rho * dt * lam / 2) / (1 + eta / rho * dt * lam / 2)
+    err = (out[0].double() - gg * prof[None, :, None]).abs().max().item()
+    err_rest = out[1:].double().abs().max().item()
+    tol = 50 * TOL[prec]
+    say(f"shear L={L} {prec}: err {err:.2e} rest {err_rest:.2e}")
+    assert err < tol and err_rest < tol
+
+
+def _step_case(torch, w, prec, nsteps, v0=None, check_factor=1.0, **kw):
+    from paper_1407_5600_amd import Springs
+    g = grid(w.L, prec, w.M, rho=w.rho, eta=w.eta, dt=w.dt, **kw)
+    sp = Springs(w.nb, w.pa, w.pb, w.r0, w.k)
+    q = dev(torch, w.q)
+    v = g.field() if v0 is None else torch.from_numpy(v0).to(g.field_dtype).cuda()
+    vstart = v.double().cpu().numpy()
+    Fe = dev(torch, w.Fext)
+    u = torch.zeros_like(q)
+    U0 = torch.zeros((w.P, 3), dtype=torch.float64, device="cuda")
+    diag = torch.zeros(7, dtype=torch.float64, device="cuda")
+    g.step(sp, q, v, Fe, nsteps, u, U0, diag)
+    torch.cuda.synchronize()
+    prm = oracle.params(w.L, rho=w.rho, eta=w.eta, dt=w.dt,
+                        steady=kw.get("mode") == "steady",
+                        zero_mean=kw.get("zero_mean", False))
+    r = oracle.step(prm, w.springs(), w.q, vstart, w.Fext, nsteps)
+    name = f"step {w.name} {prec} n={nsteps}"
+    check(name + " dq", q.cpu().numpy() - w.q, r["q"] - w.q, prec, check_factor)
+    check(name + " v", v.double().cpu().numpy(), r["v"], prec, check_factor)
+    check(name + " u", u.cpu().numpy(), r["u"], prec, check_factor)
+    check(name + " U0", U0.cpu().numpy(), r["U0"], prec, check_factor)
+    d = diag.cpu().numpy()
+    # momentum is zero up to rounding when the mean mode is held at zero
+    pscale = w.rho * w.h ** 3 * np.abs(r["v"]).sum(axis=(1, 2, 3))
+    check(name + " momentum", d[:3], r["diag"][:3], prec, check_factor,
+          floor=1e-3 * np.linalg.norm(pscale))
+    check(name + " sumF", d[3:6], r["diag"][3:6], prec, check_factor)
+    assert d[6] < (1e-10 if prec == "fp64" else 1e-3) * max(1.0, np.abs(r["v"]).max())
+    return g, r
+
+
+def test_step_single_particle_fp64(torch_cuda):
+    """The single-particle workload: 200 steps in float64 against the oracle."""
+    torch = torch_cuda
+    say("step single fp64 200")
+    w = inputs.single()
+    _step_case(torch, w, "fp64", 200)
+
+
+def test_step_single_particle_mixed(torch_cuda):
+    torch = torch_cuda
+    say("step single mixed 20")
+    w = inputs.single()
+    _step_case(torch, w, "mixed", 20)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("L,P", [(24, 20), (32, 60), (48, 150)])
+def test_step_suspension(torch_cuda, prec, L, P):
+    torch = torch_cuda
+    say("step suspension", prec, L, P)
+    w = inputs.random_suspension(100 + L, L, P)
+    v0 = oracle.fluid_solve(oracle.params(L, eta=0.0), np.random.default_rng(L).standard_normal((3, L, L, L)) * 0.1,
+                            np.zeros((3, L, L, L)))
+    _step_case(torch, w, prec, 3, v0=v0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_step_steady_stokes(torch_cuda, prec):
+    torch = torch_cuda
+    say("step steady", prec)
+    w = inputs.random_suspension(7, 32, 25)
+    _step_case(torch, w, prec, 3, mode="steady", zero_mean=True)
+
+
+def test_step_zero_mean_and_no_external_force(torch_cuda):
+    torch = torch_cuda
+    say("step zero_mean")
+    w = inputs.random_suspension(8, 24, 10)
+    w.Fext[:] = 0.0
+    _step_case(torch, w, "fp64", 2, zero_mean=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_step_dense_full_size(torch_cuda, prec):
+    """The 128^3, phi = 0.3 suspension (36,669 particles, 476,697 blobs), one
+    step in the launch configuration the benchmark times, every output
+    compared with the oracle."""
+    torch = torch_cuda
+    say("step dense 128^3", prec)
+    w = inputs.cached("dense")
+    _step_case(torch, w, prec, 1)
+
+
+def test_repeat_runs_agree(torch_cuda):
+    """LDS float atomics may add in a different order on each run; two runs
+    agree to rounding."""
+    torch = torch_cuda
+    say("repeat")
+    L, M = 32, 3000
+    q = blobs(1, M, L, "uniform")
+    F = np.random.default_rng(2).standard_normal((M, 3))
+    g = grid(L, "fp64", M)
+    a = g.spread(dev(torch, q), dev(torch, F)).cpu().numpy()
+    b = g.spread(dev(torch, q), dev(torch, F)).cpu().numpy()
+    assert rel(a, b) < 1e-14
