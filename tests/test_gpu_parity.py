@@ -215,16 +215,31 @@ def _step_case(torch, w, prec, nsteps, v0=None, check_factor=1.0, **kw):
                         zero_mean=kw.get("zero_mean", False))
     r = oracle.step(prm, w.springs(), w.q, vstart, w.Fext, nsteps)
     name = f"step {w.name} {prec} n={nsteps}"
-    check(name + " dq", q.cpu().numpy() - w.q, r["q"] - w.q, prec, check_factor)
-    check(name + " v", v.double().cpu().numpy(), r["v"], prec, check_factor)
     check(name + " u", u.cpu().numpy(), r["u"], prec, check_factor)
     check(name + " U0", U0.cpu().numpy(), r["U0"], prec, check_factor)
+    check(name + " v", v.double().cpu().numpy(), r["v"], prec, check_factor)
+    # Positions: q + dt u is rounded to the ulp of |q| on both sides (one
+    # rounding with a fused multiply-add on the GPU, two on the CPU), so the
+    # displacement agrees to the tolerance plus a few position ulps per step.
+    qg = q.cpu().numpy()
+    dq_ref = r["q"] - w.q
+    ulp = np.spacing(np.abs(r["q"]).max())
+    bound = TOL[prec] * check_factor * np.abs(dq_ref).max() * nsteps + 2 * nsteps * ulp
+    err = np.abs(qg - r["q"]).max()
+    say(f"{name} dq: max err {err:.3e} (bound {bound:.3e}), rel "
+        f"{np.linalg.norm(qg - w.q - dq_ref) / np.linalg.norm(dq_ref):.3e}")
+    assert err <= bound
     d = diag.cpu().numpy()
-    # momentum is zero up to rounding when the mean mode is held at zero
+    # momentum is zero up to rounding when the mean mode is held at zero;
+    # its error is measured against the summed magnitude of the field
     pscale = w.rho * w.h ** 3 * np.abs(r["v"]).sum(axis=(1, 2, 3))
     check(name + " momentum", d[:3], r["diag"][:3], prec, check_factor,
-          floor=1e-3 * np.linalg.norm(pscale))
-    check(name + " sumF", d[3:6], r["diag"][3:6], prec, check_factor)
+          floor=np.linalg.norm(pscale))
+    # the net force is a cancelling sum; its error is measured against the
+    # summed magnitude of the blob forces (evaluated at the final positions)
+    Fmag = np.abs(oracle.spring_forces(w.P, w.nb, w.pa, w.pb, w.r0, w.k, r["q"], w.Fext)).sum(0)
+    check(name + " sumF", d[3:6], r["diag"][3:6], prec, check_factor,
+          floor=np.linalg.norm(Fmag))
     assert d[6] < (1e-10 if prec == "fp64" else 1e-3) * max(1.0, np.abs(r["v"]).max())
     return g, r
 
@@ -268,7 +283,12 @@ def test_step_zero_mean_and_no_external_force(torch_cuda):
     say("step zero_mean")
     w = inputs.random_suspension(8, 24, 10)
     w.Fext[:] = 0.0
-    _step_case(torch, w, "fp64", 2, zero_mean=True)
+    # a decaying divergence-free flow carries the blobs; no force acts
+    L = w.L
+    v0 = oracle.fluid_solve(oracle.params(L, eta=0.0), np.random.default_rng(3).standard_normal((3, L, L, L)),
+                            np.zeros((3, L, L, L)))
+    for prec in ("fp64", "mixed"):
+        _step_case(torch, w, prec, 2, v0=v0, zero_mean=True)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
