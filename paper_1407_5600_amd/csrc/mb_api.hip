@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -34,25 +35,6 @@ bool size_ok(int L) {
     while (n % 2 == 0) n /= 2;
     while (n % 3 == 0) n /= 3;
     return n == 1;
-}
-
-FFTPlan make_plan(int n) {
-    FFTPlan p{};
-    p.n = n;
-    int m = n;
-    while (m % 8 == 0) { p.rad[p.nst++] = 8; m /= 8; }
-    while (m % 4 == 0) { p.rad[p.nst++] = 4; m /= 4; }
-    while (m % 2 == 0) { p.rad[p.nst++] = 2; m /= 2; }
-    while (m % 3 == 0) { p.rad[p.nst++] = 3; m /= 3; }
-    return p;
-}
-
-// largest even divisor of L not above cap (at least 2)
-int even_divisor(int L, int cap) {
-    int best = 2;
-    for (int d = 2; d <= L && d <= cap; d += 2)
-        if (L % d == 0) best = d;
-    return best;
 }
 
 bool device_ok(int* dev) {
@@ -100,7 +82,7 @@ void free_grid(mb_grid* g) {
     void* ptrs[] = {g->d_tw,    g->d_dsym,  g->d_d2,   g->d_spec,
                     g->d_psum,  g->d_count, g->d_offs, g->d_bsum,
                     g->d_rank,  g->d_perm,  g->d_rec,  g->d_tile_part,
-                    g->d_force_part, g->d_f, g->d_u};
+                    g->d_force_part, g->d_f, g->d_u, g->d_fmax};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& tp : g->pending) {
@@ -210,17 +192,16 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     g->NC = d.L / 2 + 1;
     g->N = (int64_t)d.L * d.L * d.L;
     g->fsz = d.precision == MB_MIXED ? 4 : 8;
-    g->plan = make_plan(d.L);
     const int L = d.L;
-    // x passes: row pairs per block so that a block has about 256 threads
-    g->rows_x = even_divisor(L, std::max(2, 4096 / L));
-    g->nblk_x = (int)(3 * (int64_t)L * L / g->rows_x);
-    g->wy = std::max(1, std::min(16, 2048 / L));
-    g->wz = std::max(1, std::min(8, 2048 / L));
-    // tiles: x extent 32, 16 or 8 (dividing L), y and z extent 8
+    g->nblk_x = fft_x_blocks(L, d.precision);
+    // tiles: x extent 16 or 8 (dividing L), y and z extent 8
     Tiles t{};
-    t.tx = (L % 32 == 0) ? 32 : (L % 16 == 0) ? 16 : 8;
-    if (d.precision == MB_FP64 && t.tx == 32) t.tx = 16;  // LDS budget
+    t.tx = (L % 16 == 0) ? 16 : 8;
+    // tuning override: MB_TILE_X = 8, 16 or 32 (must divide L)
+    if (const char* e = std::getenv("MB_TILE_X")) {
+        const int v = std::atoi(e);
+        if ((v == 8 || v == 16 || v == 32) && L % v == 0) t.tx = v;
+    }
     t.ty = 8;
     t.tz = 8;
     t.ntx = L / t.tx;
@@ -253,6 +234,8 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     alloc(&g->d_f, (size_t)3 * g->N * g->fsz);
     alloc((void**)&g->d_u, (size_t)std::max<int64_t>(d.max_blobs, 1) * 3 * sizeof(double));
     alloc((void**)&g->d_force_part, (size_t)g->force_blocks_cap * 3 * sizeof(double));
+    alloc(&g->d_fmax, 256);
+    if (e == hipSuccess) e = hipMemset(g->d_fmax, 0, 256);
     if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)g->N * sizeof(int));
     if (e == hipSuccess) e = hipMemset(g->d_force_part, 0, (size_t)g->force_blocks_cap * 3 * sizeof(double));
     if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)t.n * 4 * sizeof(double));

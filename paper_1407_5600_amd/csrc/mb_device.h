@@ -129,96 +129,6 @@ __device__ __forceinline__ void dftR(cplx<T>* v) {
 }
 
 // ---------------------------------------------------------------------------
-// One Stockham stage of radix R over `nlines` independent lines of length n
-// stored in LDS: element e of line l at buf[l * ls + e * es].  Stage with
-// Ns = product of the earlier radices: butterfly j reads elements
-// j + r n/R, multiplies input r by W_n^{r (j mod Ns) n/(Ns R)}, applies the
-// R-point DFT and writes output r to (j/Ns) Ns R + (j mod Ns) + r Ns.
-// Every thread first loads all of its butterflies into registers, so one
-// barrier separates all reads from all writes and the stage runs in place.
-// LINES_FAST: consecutive threads take consecutive lines (column tiles);
-// otherwise consecutive butterflies of one line (row tiles).
-template <typename T, int R, bool INV, int MAXB, bool LINES_FAST>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int n, int nlines,
-                                          int es, int ls, int Ns,
-                                          const cplx<T>* __restrict__ tw,
-                                          int tid, int nthr) {
-    const int nb = n / R;
-    const int total = nb * nlines;
-    const int tstep = n / (Ns * R);
-    cplx<T> v[MAXB][R];
-#pragma unroll
-    for (int it = 0; it < MAXB; ++it) {
-        const int w = tid + it * nthr;
-        if (w < total) {
-            int line, j;
-            if (LINES_FAST) {
-                j = w / nlines;
-                line = w - j * nlines;
-            } else {
-                line = w / nb;
-                j = w - line * nb;
-            }
-            const cplx<T>* base = buf + line * ls;
-            const int k = j % Ns;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                cplx<T> a = base[(j + r * nb) * es];
-                if (r > 0 && k > 0) {
-                    cplx<T> t = tw[r * k * tstep];
-                    if (INV) t.y = -t.y;
-                    a = cmul(a, t);
-                }
-                v[it][r] = a;
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < MAXB; ++it) {
-        const int w = tid + it * nthr;
-        if (w < total) {
-            int line, j;
-            if (LINES_FAST) {
-                j = w / nlines;
-                line = w - j * nlines;
-            } else {
-                line = w / nb;
-                j = w - line * nb;
-            }
-            dftR<T, R, INV>(v[it]);
-            cplx<T>* base = buf + line * ls;
-            const int jm = j % Ns;
-            const int dst = (j - jm) * R + jm;
-#pragma unroll
-            for (int r = 0; r < R; ++r) base[(dst + r * Ns) * es] = v[it][r];
-        }
-    }
-    __syncthreads();
-}
-
-// Full line transform (all stages of the plan); EPT = elements per thread
-// (nlines * n <= nthr * EPT).  Unnormalised in both directions.
-template <typename T, bool INV, int EPT, bool LINES_FAST>
-__device__ void lds_fft(cplx<T>* buf, const FFTPlan& pl, int nlines, int es,
-                        int ls, const cplx<T>* __restrict__ tw, int tid,
-                        int nthr) {
-    int Ns = 1;
-    for (int s = 0; s < pl.nst; ++s) {
-        const int R = pl.rad[s];
-        if (R == 8)
-            fft_stage<T, 8, INV, (EPT + 7) / 8, LINES_FAST>(buf, pl.n, nlines, es, ls, Ns, tw, tid, nthr);
-        else if (R == 4)
-            fft_stage<T, 4, INV, (EPT + 3) / 4, LINES_FAST>(buf, pl.n, nlines, es, ls, Ns, tw, tid, nthr);
-        else if (R == 2)
-            fft_stage<T, 2, INV, (EPT + 1) / 2, LINES_FAST>(buf, pl.n, nlines, es, ls, Ns, tw, tid, nthr);
-        else
-            fft_stage<T, 3, INV, (EPT + 2) / 3, LINES_FAST>(buf, pl.n, nlines, es, ls, Ns, tw, tid, nthr);
-        Ns *= R;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Block reductions (blockDim.x a multiple of 64, at most 1024).
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);

@@ -1,0 +1,468 @@
+// Fluid solve on the MAC grid by a hand-written 3-D FFT for gfx950.
+//
+// Kernels are compiled per grid size L (all L = 2^a 3^b, 8 <= L <= 512,
+// L a multiple of 8) and per precision, so every radix, stride, twiddle step
+// and index division is a compile-time constant.  Spectrum layout
+// A[c][z][kx][ky] (kx < L/2 + 1, ky fastest): the x passes transpose through
+// LDS, the y pass reads and writes contiguous [kx][ky] blocks, and the z
+// pass reads aligned ky segments.
+//
+//   x forward : right-hand side r = a v + b (7-point Laplacian of v) + f
+//               (Crank-Nicolson explicit half; r = f in steady mode), two
+//               real rows packed as one complex line, transform along x,
+//               unpack the half spectra, transposed store; float64 partial
+//               sums of v and f for the mean mode.
+//   y         : transform along y (forward or inverse), in place.
+//   z+solve   : transform along z, projection and viscous divide per
+//               wavevector, mean mode, inverse transform along z.
+//   x inverse : rebuild complex lines from row pairs of half spectra
+//               (Hermitian extension), inverse transform, store real rows.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mb_device.h"
+#include "mb_internal.h"
+
+namespace mb {
+namespace fft {
+
+constexpr int EPT = 8;  // elements per thread in a line transform
+
+// Radix plan: 8s, then 4, then 2, then 3s.
+constexpr int nstages(int n) {
+    int s = 0;
+    while (n % 8 == 0) { n /= 8; ++s; }
+    while (n % 4 == 0) { n /= 4; ++s; }
+    while (n % 2 == 0) { n /= 2; ++s; }
+    while (n % 3 == 0) { n /= 3; ++s; }
+    return s;
+}
+constexpr int radix_at(int n, int k) {
+    int s = 0;
+    while (n % 8 == 0) { if (s == k) return 8; n /= 8; ++s; }
+    while (n % 4 == 0) { if (s == k) return 4; n /= 4; ++s; }
+    while (n % 2 == 0) { if (s == k) return 2; n /= 2; ++s; }
+    while (n % 3 == 0) { if (s == k) return 3; n /= 3; ++s; }
+    return 1;
+}
+constexpr int ns_at(int n, int k) {
+    int p = 1;
+    for (int i = 0; i < k; ++i) p *= radix_at(n, i);
+    return p;
+}
+
+// One Stockham stage of radix R on NLINES lines of length N held in LDS
+// (element e of line l at buf[l * LS + e]).  Butterfly j of a line reads
+// elements j + r N/R, multiplies input r by W_N^{r (j mod NS) N/(NS R)},
+// applies the R-point DFT and writes output r to (j - j mod NS) R +
+// (j mod NS) + r NS.  All loads of a stage precede a barrier and all stores,
+// so the stage runs in place.  Consecutive threads take consecutive
+// butterflies of a line.
+template <typename T, int N, int R, int NS, bool INV, int NLINES, int LS, int NTHR>
+__device__ __forceinline__ void stage(cplx<T>* buf, const cplx<T>* tw, int tid) {
+    constexpr int NB = N / R;
+    constexpr int TOTAL = NB * NLINES;
+    constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
+    constexpr int TSTEP = N / (NS * R);
+    cplx<T> v[MAXB][R];
+#pragma unroll
+    for (int it = 0; it < MAXB; ++it) {
+        const int w = tid + it * NTHR;
+        if (TOTAL % NTHR == 0 || w < TOTAL) {
+            const int line = w / NB;
+            const int j = w - line * NB;
+            const cplx<T>* base = buf + line * LS;
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cplx<T> a = base[j + r * NB];
+                if (NS > 1 && r > 0) {
+                    cplx<T> t = tw[r * k * TSTEP];
+                    if (INV) t.y = -t.y;
+                    a = cmul(a, t);
+                }
+                v[it][r] = a;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXB; ++it) {
+        const int w = tid + it * NTHR;
+        if (TOTAL % NTHR == 0 || w < TOTAL) {
+            const int line = w / NB;
+            const int j = w - line * NB;
+            cplx<T>* base = buf + line * LS;
+            const int k = j % NS;
+            dftR<T, R, INV>(v[it]);
+            const int dst = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) base[dst + r * NS] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int N, bool INV, int NLINES, int LS, int NTHR, int S = 0>
+__device__ __forceinline__ void line_fft(cplx<T>* buf, const cplx<T>* tw, int tid) {
+    if constexpr (S < nstages(N)) {
+        stage<T, N, radix_at(N, S), ns_at(N, S), INV, NLINES, LS, NTHR>(buf, tw, tid);
+        line_fft<T, N, INV, NLINES, LS, NTHR, S + 1>(buf, tw, tid);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch geometry per size.
+constexpr int largest_even_divisor(int L, int cap) {
+    int best = 2;
+    for (int d = 2; d <= L && d <= cap; d += 2)
+        if (L % d == 0) best = d;
+    return best;
+}
+// rows per block of the x passes (about 256 threads per block)
+constexpr int rows_x(int L) { return largest_even_divisor(L, 4096 / L > 2 ? 4096 / L : 2); }
+// kx columns per block of the y pass (at least 128 B contiguous per row)
+template <typename T>
+constexpr int cols_y(int L) {
+    int w = 2048 / L;
+    if (w < 1) w = 1;
+    const int nc = L / 2 + 1;
+    return w < nc ? w : nc;
+}
+// ky columns per block of the z pass (a divisor of L; LDS <= 64 KB)
+template <typename T>
+constexpr int cols_z(int L) {
+    int w = 16;
+    while (w > 1 && (L % w != 0 || 3 * L * w * 2 * (int)sizeof(T) > 65536 ||
+                     3 * w * L / EPT > 1024))
+        w /= 2;
+    return w;
+}
+
+template <typename T, int L>
+struct Geo {
+    static constexpr int NC = L / 2 + 1;
+    static constexpr int R = rows_x(L);
+    static constexpr int NL = R / 2;
+    static constexpr int TX = NL * L / EPT;  // threads of an x pass
+    static constexpr int LS = L + 1;         // LDS line stride (complex)
+    static constexpr int WY = cols_y<T>(L);
+    static constexpr int NCHY = (NC + WY - 1) / WY;
+    static constexpr int TY = WY * L / EPT;
+    static constexpr int WZ = cols_z<T>(L);
+    static constexpr int TZ = 3 * WZ * L / EPT;
+    static constexpr int NBX = 3 * L * (L / R);  // blocks of an x pass
+};
+
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ void __launch_bounds__((Geo<T, L>::TX))
+k_x_fwd(const T* __restrict__ v, const T* __restrict__ f,
+        const cplx<T>* __restrict__ tw, T a, T b, int steady,
+        cplx<T>* __restrict__ A, double* __restrict__ psum) {
+    using G = Geo<T, L>;
+    constexpr int NC = G::NC, R = G::R, NL = G::NL, NTHR = G::TX, LS = G::LS;
+    __shared__ cplx<T> buf[NL * LS];
+    __shared__ cplx<T> tws[L];
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    const int yb = blockIdx.x % (L / R);
+    const int cz = blockIdx.x / (L / R);  // c * L + z
+    const int z = cz % L;
+    const int cbase = (cz - z) * L * L;   // component offset (elements)
+    const int y0 = yb * R;
+    for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
+    double sv = 0.0, sf = 0.0;
+    const int zm = (z == 0 ? L - 1 : z - 1), zp = (z == L - 1 ? 0 : z + 1);
+#pragma unroll
+    for (int kk = 0; kk < EPT; ++kk) {
+        const int e = tid + kk * NTHR;
+        const int line = e / L;
+        const int x = e - line * L;
+        T val[2];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int y = y0 + 2 * line + hh;
+            const int idx = cbase + (z * L + y) * L + x;
+            const T fv = f[idx];
+            sf += (double)fv;
+            if (steady) {
+                val[hh] = fv;
+            } else {
+                const T vc = v[idx];
+                sv += (double)vc;
+                const int xm = x == 0 ? L - 1 : x - 1, xp = x == L - 1 ? 0 : x + 1;
+                const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+                const int row = cbase + (z * L + y) * L;
+                const T lap = (v[row + xm] + v[row + xp]) +
+                              (v[cbase + (z * L + ym) * L + x] + v[cbase + (z * L + yp) * L + x]) +
+                              (v[cbase + (zm * L + y) * L + x] + v[cbase + (zp * L + y) * L + x]) -
+                              T(6) * vc;
+                val[hh] = a * vc + b * lap + fv;
+            }
+        }
+        buf[line * LS + x] = cplx<T>{val[0], val[1]};
+    }
+    __syncthreads();
+    line_fft<T, L, false, NL, LS, NTHR>(buf, tws, tid);
+    // unpack the two half spectra of each line; store A[c][z][kx][y]
+    cplx<T>* out = A + (size_t)cz * NC * L + y0;
+    for (int e = tid; e < NC * R; e += NTHR) {
+        const int kx = e / R;
+        const int rl = e - kx * R;
+        const int line = rl >> 1;
+        const cplx<T> Z = buf[line * LS + kx];
+        const cplx<T> Zc = cconj(buf[line * LS + (kx == 0 ? 0 : L - kx)]);
+        cplx<T> o;
+        if (rl & 1) {  // (Z - Zc) / 2i
+            o = cplx<T>{T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
+        } else {       // (Z + Zc) / 2
+            o = cplx<T>{T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
+        }
+        out[kx * L + rl] = o;
+    }
+    const double ts = block_reduce<false>(sv, red);
+    const double tf = block_reduce<false>(sf, red);
+    if (tid == 0) {
+        psum[2 * blockIdx.x] = ts;
+        psum[2 * blockIdx.x + 1] = tf;
+    }
+}
+
+// y pass: block = (component, z plane, WY consecutive kx); the kx rows of
+// length L (along ky) are contiguous in A.
+template <typename T, int L, bool INV>
+__global__ void __launch_bounds__((Geo<T, L>::TY))
+k_y(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw) {
+    using G = Geo<T, L>;
+    constexpr int NC = G::NC, W = G::WY, NTHR = G::TY, LS = G::LS;
+    __shared__ cplx<T> buf[W * LS];
+    __shared__ cplx<T> tws[L];
+    const int tid = threadIdx.x;
+    const int ch = blockIdx.x % G::NCHY;
+    const int cz = blockIdx.x / G::NCHY;
+    const int kx0 = ch * W;
+    const int wc = NC - kx0 < W ? NC - kx0 : W;
+    cplx<T>* base = A + ((size_t)cz * NC + kx0) * L;
+    for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
+#pragma unroll
+    for (int kk = 0; kk < EPT; ++kk) {
+        const int e = tid + kk * NTHR;
+        const int w = e / L;
+        const int y = e - w * L;
+        if (w < wc) buf[w * LS + y] = base[e];
+    }
+    __syncthreads();
+    line_fft<T, L, INV, W, LS, NTHR>(buf, tws, tid);
+#pragma unroll
+    for (int kk = 0; kk < EPT; ++kk) {
+        const int e = tid + kk * NTHR;
+        const int w = e / L;
+        const int y = e - w * L;
+        if (w < wc) base[e] = buf[w * LS + y];
+    }
+}
+
+// z pass fused with the solve: block = (kx, WZ consecutive ky), all three
+// components.  Per wavevector m != 0, with D the divergence symbol
+// (D_b = (1 - e^{-2 pi i m_b / L}) / h, |D|^2 = sum_b 4 sin^2(pi m_b/L)/h^2):
+//   v^ = (r^ - conj(D) (D . r^) / |D|^2) / ((c0 + c1 |D|^2))
+// which is the solenoidal projection of eq. vf on the MAC grid followed by
+// the Crank-Nicolson (c0 = N rho/dt, c1 = N eta/2) or steady (c0 = 0,
+// c1 = N eta) divide, N = L^3 folding in the inverse normalisation.  The
+// mean mode is set from float64 sums: mean(v) + (dt/rho) mean(f), or zero.
+template <typename T, int L>
+__global__ void __launch_bounds__((Geo<T, L>::TZ))
+k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
+          const cplx<T>* __restrict__ dsym, const T* __restrict__ d2, T c0, T c1,
+          int zero_mean_mode, const double* __restrict__ psum, double mv,
+          double mf) {
+    using G = Geo<T, L>;
+    constexpr int NC = G::NC, W = G::WZ, NTHR = G::TZ, LS = G::LS;
+    constexpr int NLN = 3 * W;
+    __shared__ cplx<T> buf[NLN * LS];
+    __shared__ cplx<T> tws[L];
+    __shared__ double red[16];
+    __shared__ double mean_new[3];
+    const int tid = threadIdx.x;
+    const int ch = blockIdx.x % (L / W);
+    const int kx = blockIdx.x / (L / W);
+    const int ky0 = ch * W;
+    for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
+    // load: e -> (c, z, w), w fastest (contiguous ky segments)
+    for (int e = tid; e < 3 * L * W; e += NTHR) {
+        const int w = e % W;
+        const int cz = e / W;
+        const int c = cz / L;
+        const int z = cz - c * L;
+        buf[(c * W + w) * LS + z] = A[((size_t)cz * NC + kx) * L + ky0 + w];
+    }
+    if (kx == 0 && ch == 0) {
+        constexpr int per_c = G::NBX / 3;
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int i = tid; i < per_c; i += NTHR) {
+                const double* p = psum + 2 * (c * per_c + i);
+                s += mv * p[0] + mf * p[1];
+            }
+            s = block_reduce<false>(s, red);
+            if (tid == 0) mean_new[c] = zero_mean_mode ? 0.0 : s;
+        }
+    }
+    __syncthreads();
+    line_fft<T, L, false, NLN, LS, NTHR>(buf, tws, tid);
+    const cplx<T> Dx = dsym[kx];
+    const T d2x = d2[kx];
+    for (int e = tid; e < L * W; e += NTHR) {
+        const int w = e % W;
+        const int kz = e / W;
+        const int ky = ky0 + w;
+        cplx<T>* X = buf + w * LS + kz;
+        if (kx == 0 && ky == 0 && kz == 0) {
+            X[0] = cplx<T>{(T)mean_new[0], T(0)};
+            X[W * LS] = cplx<T>{(T)mean_new[1], T(0)};
+            X[2 * W * LS] = cplx<T>{(T)mean_new[2], T(0)};
+            continue;
+        }
+        const cplx<T> Dy = dsym[ky], Dz = dsym[kz];
+        const T D2 = d2x + d2[ky] + d2[kz];
+        const cplx<T> rx = X[0], ry = X[W * LS], rz = X[2 * W * LS];
+        const cplx<T> div = cadd(cadd(cmul(Dx, rx), cmul(Dy, ry)), cmul(Dz, rz));
+        const T inv_d2 = T(1) / D2;
+        const T scale = T(1) / (c0 + c1 * D2);
+        const cplx<T> g = {div.x * inv_d2, div.y * inv_d2};
+        const cplx<T> px = csub(rx, cmul(cconj(Dx), g));
+        const cplx<T> py = csub(ry, cmul(cconj(Dy), g));
+        const cplx<T> pz = csub(rz, cmul(cconj(Dz), g));
+        X[0] = cplx<T>{px.x * scale, px.y * scale};
+        X[W * LS] = cplx<T>{py.x * scale, py.y * scale};
+        X[2 * W * LS] = cplx<T>{pz.x * scale, pz.y * scale};
+    }
+    __syncthreads();
+    line_fft<T, L, true, NLN, LS, NTHR>(buf, tws, tid);
+    for (int e = tid; e < 3 * L * W; e += NTHR) {
+        const int w = e % W;
+        const int cz = e / W;
+        const int c = cz / L;
+        const int z = cz - c * L;
+        A[((size_t)cz * NC + kx) * L + ky0 + w] = buf[(c * W + w) * LS + z];
+    }
+}
+
+// Inverse x pass: the half spectra of a row pair are staged, combined into
+// one complex line Z = X_even + i X_odd (Hermitian extension for kx > L/2,
+// imaginary parts of kx = 0 and L/2 dropped), transformed, and the real and
+// imaginary parts stored as the two velocity rows.
+template <typename T, int L>
+__global__ void __launch_bounds__((Geo<T, L>::TX))
+k_x_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
+        T* __restrict__ vout) {
+    using G = Geo<T, L>;
+    constexpr int NC = G::NC, R = G::R, NL = G::NL, NTHR = G::TX, LS = G::LS;
+    constexpr int SS = NC + 1;  // staging row stride
+    __shared__ cplx<T> stg[R * SS];
+    __shared__ cplx<T> buf[NL * LS];
+    __shared__ cplx<T> tws[L];
+    const int tid = threadIdx.x;
+    const int yb = blockIdx.x % (L / R);
+    const int cz = blockIdx.x / (L / R);
+    const int y0 = yb * R;
+    for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
+    const cplx<T>* in = A + (size_t)cz * NC * L + y0;
+    for (int e = tid; e < NC * R; e += NTHR) {
+        const int kx = e / R;
+        const int rl = e - kx * R;
+        cplx<T> X = in[kx * L + rl];
+        if (kx == 0 || kx == L / 2) X.y = T(0);
+        stg[rl * SS + kx] = X;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < EPT; ++kk) {
+        const int e = tid + kk * NTHR;
+        const int line = e / L;
+        const int k = e - line * L;
+        cplx<T> X1, X2;
+        if (k <= L / 2) {
+            X1 = stg[(2 * line) * SS + k];
+            X2 = stg[(2 * line + 1) * SS + k];
+        } else {
+            X1 = cconj(stg[(2 * line) * SS + (L - k)]);
+            X2 = cconj(stg[(2 * line + 1) * SS + (L - k)]);
+        }
+        buf[line * LS + k] = cplx<T>{X1.x - X2.y, X1.y + X2.x};
+    }
+    __syncthreads();
+    line_fft<T, L, true, NL, LS, NTHR>(buf, tws, tid);
+    T* out = vout + ((size_t)cz * L + y0) * L;
+#pragma unroll
+    for (int kk = 0; kk < EPT; ++kk) {
+        const int e = tid + kk * NTHR;
+        const int line = e / L;
+        const int x = e - line * L;
+        const cplx<T> zz = buf[line * LS + x];
+        out[(2 * line) * L + x] = zz.x;
+        out[(2 * line + 1) * L + x] = zz.y;
+    }
+}
+
+template <typename T, int L>
+hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, T* v_out,
+                       hipStream_t s) {
+    using G = Geo<T, L>;
+    const bool steady = g->d.mode == MB_STEADY_STOKES;
+    const double h = g->d.h;
+    const double N = (double)g->N;
+    cplx<T>* A = (cplx<T>*)g->d_spec;
+    const cplx<T>* tw = (const cplx<T>*)g->d_tw;
+    const T a = steady ? T(0) : (T)(g->d.rho / g->d.dt);
+    const T b = steady ? T(0) : (T)(0.5 * g->d.eta / (h * h));
+    MB_LAUNCH(g, K_FFT_X_FWD, s, (k_x_fwd<T, L>), G::NBX, G::TX, 0, v_in, f, tw, a,
+              b, (int)steady, A, g->d_psum);
+    MB_LAUNCH(g, K_FFT_Y_FWD, s, (k_y<T, L, false>), 3 * L * G::NCHY, G::TY, 0, A, tw);
+    const T c0 = steady ? T(0) : (T)(g->d.rho / g->d.dt * N);
+    const T c1 = steady ? (T)(g->d.eta * N) : (T)(0.5 * g->d.eta * N);
+    const double mv = steady ? 0.0 : 1.0 / N;
+    const double mf = steady ? 0.0 : g->d.dt / g->d.rho / N;
+    const int zm = (steady || g->d.zero_mean) ? 1 : 0;
+    MB_LAUNCH(g, K_FFT_Z_SPECTRAL, s, (k_z_solve<T, L>), G::NC * (L / G::WZ), G::TZ, 0,
+              A, tw, (const cplx<T>*)g->d_dsym, (const T*)g->d_d2, c0, c1, zm,
+              g->d_psum, mv, mf);
+    MB_LAUNCH(g, K_FFT_Y_INV, s, (k_y<T, L, true>), 3 * L * G::NCHY, G::TY, 0, A, tw);
+    MB_LAUNCH(g, K_FFT_X_INV, s, (k_x_inv<T, L>), G::NBX, G::TX, 0, A, tw, v_out);
+    return hipGetLastError();
+}
+
+}  // namespace fft
+
+#define MB_FFT_SIZES(X) \
+    X(8) X(16) X(24) X(32) X(48) X(64) X(72) X(96) X(128) X(144) X(192) \
+    X(216) X(256) X(288) X(384) X(432) X(512)
+
+template <typename T>
+hipError_t fluid_solve(mb_grid* g, const T* v_in, const T* f, T* v_out,
+                       hipStream_t s) {
+    switch (g->L) {
+#define MB_CASE(n) \
+    case n: return fft::solve_sized<T, n>(g, v_in, f, v_out, s);
+        MB_FFT_SIZES(MB_CASE)
+#undef MB_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+int fft_x_blocks(int L, int precision) {
+    switch (L) {
+#define MB_CASE(n) \
+    case n: return precision == MB_MIXED ? fft::Geo<float, n>::NBX : fft::Geo<double, n>::NBX;
+        MB_FFT_SIZES(MB_CASE)
+#undef MB_CASE
+    }
+    return 0;
+}
+
+template hipError_t fluid_solve<float>(mb_grid*, const float*, const float*, float*, hipStream_t);
+template hipError_t fluid_solve<double>(mb_grid*, const double*, const double*, double*, hipStream_t);
+
+}  // namespace mb

@@ -33,13 +33,6 @@ enum KernelId : int {
     K_NUM
 };
 
-// Radix plan of a length-n line transform (product of rad[] = n).
-struct FFTPlan {
-    int n;
-    int nst;
-    int rad[12];
-};
-
 // Spring table on the device, as per-blob adjacency lists of the particle
 // template (each pair appears in the lists of both of its blobs).
 struct SpringsDev {
@@ -82,14 +75,11 @@ struct mb_grid {
     int64_t N;          // L^3
     size_t fsz;         // bytes per scalar (8 or 4)
     // FFT
-    mb::FFTPlan plan;
     void* d_tw;         // twiddles W_L^k, k < L (cplx<T>)
     void* d_dsym;       // D symbol per mode index: (1 - e^{-2 pi i m / L}) / h
     void* d_d2;         // |D symbol|^2 per mode index (T)
-    void* d_spec;       // [3][L][L][NC] cplx<T>
-    int rows_x;         // rows per block in the x passes
+    void* d_spec;       // [3][L(z)][NC(kx)][L(ky)] cplx<T>
     int nblk_x;         // blocks of an x pass
-    int wy, wz;         // column chunk widths of the y and z passes
     double* d_psum;     // [nblk_x][2] per-block sums of v and f (float64)
     // binning
     int* d_count;       // [N] (kept zeroed between uses)
@@ -101,6 +91,7 @@ struct mb_grid {
     void* d_rec;        // [max_blobs] records
     size_t rec_size;
     mb::Tiles tiles;
+    void* d_fmax;          // float bits: max |F h^-3| of the last scatter
     void* d_f;             // [3][L][L][L] force density of the step
     double* d_u;           // [max_blobs][3] blob velocities of the last step
     double* d_tile_part;   // [tiles][4]  (sum v_a, max |Dv|)
@@ -119,6 +110,18 @@ namespace mb {
 // Timer hooks around each launch (no-ops unless timing is enabled).
 void timer_begin(mb_grid* g, int id, hipStream_t s, hipEvent_t* ev);
 void timer_end(mb_grid* g, int id, hipStream_t s, hipEvent_t ev);
+
+#define MB_LAUNCH(g, id, s, kern, grid, block, shm, ...)              \
+    do {                                                              \
+        hipEvent_t ev_ = nullptr;                                     \
+        ::mb::timer_begin((g), (id), (s), &ev_);                      \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), (shm), (s), \
+                           __VA_ARGS__);                              \
+        ::mb::timer_end((g), (id), (s), ev_);                         \
+    } while (0)
+
+// Blocks of an x pass of the FFT solve (one float64 partial sum pair each).
+int fft_x_blocks(int L, int precision);
 
 // Launchers (templated on the field scalar type, float or double).  Each
 // returns hipSuccess or the launch error.

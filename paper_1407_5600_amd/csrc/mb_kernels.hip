@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "mb_device.h"
 #include "mb_internal.h"
@@ -73,8 +74,10 @@ __device__ __forceinline__ uint32_t cell_pack(const Geom& g) {
 // Binning: counting sort of blobs by cell.
 __global__ void __launch_bounds__(BLK)
 k_bin_count(const double* __restrict__ q, int64_t M, double h, int L,
-            int* __restrict__ count, int* __restrict__ rank) {
+            int* __restrict__ count, int* __restrict__ rank,
+            unsigned int* __restrict__ fmax) {
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i == 0) *fmax = 0u;  // max |F h^-3| of this step, set by the scatter
     if (i >= M) return;
     const Geom g = blob_geom(q, i, h, L);
     rank[i] = atomicAdd(&count[cell_linear(g, L)], 1);
@@ -164,23 +167,35 @@ k_scan_apply(int* __restrict__ count, int64_t n, const int* __restrict__ bsum,
     if (base + SCAN_TILE >= n && threadIdx.x == 0) offs[n] = off + total;
 }
 
+// Writes the record and returns the largest |F h^-3| it stores (as float).
 template <typename T>
-__device__ __forceinline__ void write_record(Rec<T>* __restrict__ rec,
-                                             int* __restrict__ perm,
-                                             int64_t pos, int64_t i,
-                                             const Geom& g, const double F[3],
-                                             double inv_vol) {
+__device__ __forceinline__ float write_record(Rec<T>* __restrict__ rec,
+                                              int* __restrict__ perm,
+                                              int64_t pos, int64_t i,
+                                              const Geom& g, const double F[3],
+                                              double inv_vol) {
     Rec<T> r;
+    float m = 0.f;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         r.tu[b] = (T)g.tu[b];
         r.ts[b] = (T)g.ts[b];
         r.F[b] = (T)(F[b] * inv_vol);
+        m = fmaxf(m, fabsf((float)r.F[b]));
     }
     r.cell = cell_pack(g);
     r.pad = 0;
     rec[pos] = r;
     perm[pos] = (int)i;
+    return m;
+}
+
+// Block maximum of non-negative floats folded into *fmax (bit patterns of
+// non-negative floats order like the values).
+__device__ __forceinline__ void fold_fmax(float m, double* red,
+                                          unsigned int* __restrict__ fmax) {
+    const double bm = block_reduce<true>((double)m, red);
+    if (threadIdx.x == 0) atomicMax(fmax, __float_as_uint((float)bm));
 }
 
 // Records in cell order for given forces (F may be null: interpolation).
@@ -189,18 +204,23 @@ __global__ void __launch_bounds__(BLK)
 k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
               int64_t M, double h, int L, double inv_vol,
               const int* __restrict__ offs, const int* __restrict__ rank,
-              Rec<T>* __restrict__ rec, int* __restrict__ perm) {
+              Rec<T>* __restrict__ rec, int* __restrict__ perm,
+              unsigned int* __restrict__ fmax) {
+    __shared__ double red[16];
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    if (i >= M) return;
-    const Geom g = blob_geom(q, i, h, L);
-    double f[3] = {0.0, 0.0, 0.0};
-    if (F) {
-        f[0] = F[3 * i];
-        f[1] = F[3 * i + 1];
-        f[2] = F[3 * i + 2];
+    float m = 0.f;
+    if (i < M) {
+        const Geom g = blob_geom(q, i, h, L);
+        double f[3] = {0.0, 0.0, 0.0};
+        if (F) {
+            f[0] = F[3 * i];
+            f[1] = F[3 * i + 1];
+            f[2] = F[3 * i + 2];
+        }
+        const int64_t pos = (int64_t)offs[cell_linear(g, L)] + rank[i];
+        m = write_record<T>(rec, perm, pos, i, g, f, inv_vol);
     }
-    const int64_t pos = (int64_t)offs[cell_linear(g, L)] + rank[i];
-    write_record<T>(rec, perm, pos, i, g, f, inv_vol);
+    fold_fmax(m, red, fmax);
 }
 
 // Spring force on blob i (float64): sum over the template pairs of blob b
@@ -243,16 +263,19 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
                   const double* __restrict__ Fext, int64_t M, double h, int L,
                   double inv_vol, const int* __restrict__ offs,
                   const int* __restrict__ rank, Rec<T>* __restrict__ rec,
-                  int* __restrict__ perm, double* __restrict__ fpart) {
+                  int* __restrict__ perm, double* __restrict__ fpart,
+                  unsigned int* __restrict__ fmax) {
     __shared__ double red[16];
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     double F[3] = {0.0, 0.0, 0.0};
+    float m = 0.f;
     if (i < M) {
         spring_force(sp, q, Fext, i, F);
         const Geom g = blob_geom(q, i, h, L);
         const int64_t pos = (int64_t)offs[cell_linear(g, L)] + rank[i];
-        write_record<T>(rec, perm, pos, i, g, F, inv_vol);
+        m = write_record<T>(rec, perm, pos, i, g, F, inv_vol);
     }
+    fold_fmax(m, red, fmax);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double s = block_reduce<false>(F[c], red);
@@ -295,9 +318,11 @@ __device__ __forceinline__ TileBox tile_box(const Tiles& t, int L) {
     return tb;
 }
 
+// Periodic wrap of an index known to lie in [-L, 2L).
 __device__ __forceinline__ int wrapL(int v, int L) {
-    v %= L;
-    return v < 0 ? v + L : v;
+    if (v < 0) v += L;
+    if (v >= L) v -= L;
+    return v;
 }
 
 // Contiguous ranges of sorted records for the cells of a box of rows.
@@ -360,21 +385,101 @@ __device__ __forceinline__ int find_segment(const int* seg_pre, int nseg, int k)
     return lo;
 }
 
+// Adds one record's contributions to the in-tile nodes of all three
+// components.  ACC = double: float64 LDS atomics on the float64 path.
+// ACC = unsigned long long (mixed path): each float32 contribution, already
+// scaled by 2^e, is rounded to int32 and added to a 64-bit integer sum.
+template <typename T, typename ACC, int TX, int TY, int TZ>
+__device__ __forceinline__ void spread_record(const Rec<T>& r, const TileBox& tb,
+                                              const int* tdim, int L, int e,
+                                              ACC* acc) {
+    constexpr int TV = TX * TY * TZ;
+    T w[3][2][3];     // per axis, node set (0 cell-centred, 1 shifted), node
+    int rel[3][2][3]; // tile-relative node index, -1 outside the tile
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        kernel_weights<T>(r.tu[b], w[b][0]);
+        kernel_weights<T>(r.ts[b], w[b][1]);
+        const int cb = (int)((r.cell >> (9 * b)) & 511u);
+        const int up = (int)((r.cell >> (27 + b)) & 1u);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            int r0 = cb + (v == 0 ? up : 0) - 1 - tb.lo[b];
+            if (r0 < 0) r0 += L;
+            if (r0 >= L) r0 -= L;
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                int rr = r0 + o;
+                if (rr >= L) rr -= L;
+                rel[b][v][o] = rr < tdim[b] ? rr : -1;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int vx = a == 0, vy = a == 1, vz = a == 2;
+        T Fa = r.F[a];
+        if constexpr (!std::is_same<ACC, double>::value) Fa = ldexp(Fa, e);
+        ACC* A = acc + a * TV;
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+            const int rz = rel[2][vz][oz];
+            if (rz < 0) continue;
+            const T wz = w[2][vz][oz] * Fa;
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+                const int ry = rel[1][vy][oy];
+                if (ry < 0) continue;
+                const T wyz = w[1][vy][oy] * wz;
+#pragma unroll
+                for (int ox = 0; ox < 3; ++ox) {
+                    const int rx = rel[0][vx][ox];
+                    if (rx < 0) continue;
+                    const T val = w[0][vx][ox] * wyz;
+                    ACC* dst = &A[(rz * TY + ry) * TX + rx];
+                    if constexpr (std::is_same<ACC, double>::value)
+                        atomicAdd(dst, (double)val);
+                    else
+                        atomicAdd(dst, (unsigned long long)(long long)__float2int_rn((float)val));
+                }
+            }
+        }
+    }
+}
+
 // Spreading: one block per tile; every record whose 3x3x3 support may reach
 // the tile (cells [lo-2, hi+1]) is expanded and its in-tile nodes are added
-// to an LDS copy of the tile (LDS atomics), which is then written out once.
-template <typename T, int TX, int TY, int TZ>
+// to an LDS copy of the tile, which is then written out once.
+//
+// Accumulation: float64 LDS atomics on the float64 path.  On the mixed path
+// the float LDS atomic add of gfx950 is an order of magnitude slower than
+// the integer one, so the float32 contributions are accumulated as fixed
+// point: with fmax the largest |F h^-3| of the step and 2^e the power of two
+// with fmax 2^e < 2^30, each contribution w F 2^e is rounded to int32 (a
+// quantum of at most 2^-29 fmax) and summed in 64-bit integers, which can
+// not overflow and do not depend on the order of the additions.
+template <typename T, typename ACC, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
 k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
-         Tiles tl, T* __restrict__ f) {
+         Tiles tl, const float* __restrict__ fmax, T* __restrict__ f) {
     constexpr int TV = TX * TY * TZ;
-    __shared__ T acc[3 * TV];
+    constexpr bool FIXED = !std::is_same<ACC, double>::value;
+    __shared__ ACC acc[3 * TV];
     __shared__ int seg_start[2 * (TY + 3) * (TZ + 3)];
     __shared__ int seg_pre[2 * (TY + 3) * (TZ + 3) + 1];
     __shared__ int scratch[16];
     const TileBox tb = tile_box(tl, L);
     const int tdim[3] = {tl.tx, tl.ty, tl.tz};
-    for (int i = threadIdx.x; i < 3 * TV; i += BLK) acc[i] = T(0);
+    for (int i = threadIdx.x; i < 3 * TV; i += BLK) acc[i] = ACC(0);
+    int e = 0;
+    if (FIXED) {
+        const float fm = *fmax;
+        if (fm > 0.f) {
+            int ex;
+            (void)frexpf(fm, &ex);  // fm < 2^ex
+            e = 30 - ex;
+        }
+    }
     int nseg;
     const int ext[3] = {tb.full[0] ? L : tl.tx + 3, tb.full[1] ? L : tl.ty + 3,
                         tb.full[2] ? L : tl.tz + 3};
@@ -386,54 +491,7 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
     for (int k = threadIdx.x; k < total; k += BLK) {
         const int s = find_segment(seg_pre, nseg, k);
         const Rec<T> r = rec[seg_start[s] + (k - seg_pre[s])];
-        const int c[3] = {(int)(r.cell & 511u), (int)((r.cell >> 9) & 511u),
-                          (int)((r.cell >> 18) & 511u)};
-        // per axis, per node set (0: cell-centred, 1: shifted): weights and
-        // tile-relative node indices (-1 when outside the tile)
-        T w[3][2][3];
-        int rel[3][2][3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            kernel_weights<T>(r.tu[b], w[b][0]);
-            kernel_weights<T>(r.ts[b], w[b][1]);
-            const int up = (r.cell >> (27 + b)) & 1u;
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                int r0 = c[b] + (v == 0 ? up : 0) - 1 - tb.lo[b];
-                if (r0 < 0) r0 += L;
-                if (r0 >= L) r0 -= L;
-#pragma unroll
-                for (int o = 0; o < 3; ++o) {
-                    int rr = r0 + o;
-                    if (rr >= L) rr -= L;
-                    rel[b][v][o] = rr < tdim[b] ? rr : -1;
-                }
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int vx = a == 0, vy = a == 1, vz = a == 2;
-            T* A = acc + a * TV;
-            const T Fa = r.F[a];
-#pragma unroll
-            for (int oz = 0; oz < 3; ++oz) {
-                const int rz = rel[2][vz][oz];
-                if (rz < 0) continue;
-                const T wz = w[2][vz][oz] * Fa;
-#pragma unroll
-                for (int oy = 0; oy < 3; ++oy) {
-                    const int ry = rel[1][vy][oy];
-                    if (ry < 0) continue;
-                    const T wyz = w[1][vy][oy] * wz;
-#pragma unroll
-                    for (int ox = 0; ox < 3; ++ox) {
-                        const int rx = rel[0][vx][ox];
-                        if (rx < 0) continue;
-                        atomicAdd(&A[(rz * TY + ry) * TX + rx], w[0][vx][ox] * wyz);
-                    }
-                }
-            }
-        }
+        spread_record<T, ACC, TX, TY, TZ>(r, tb, tdim, L, e, acc);
     }
     __syncthreads();
     const int64_t N = (int64_t)L * L * L;
@@ -443,7 +501,12 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
         const int x = rem % TX;
         const int y = (rem / TX) % TY;
         const int z = rem / (TX * TY);
-        f[a * N + ((int64_t)(tb.lo[2] + z) * L + tb.lo[1] + y) * L + tb.lo[0] + x] = acc[i];
+        T val;
+        if constexpr (FIXED)
+            val = (T)ldexp((double)(long long)acc[i], -e);
+        else
+            val = (T)acc[i];
+        f[a * N + ((int64_t)(tb.lo[2] + z) * L + tb.lo[1] + y) * L + tb.lo[0] + x] = val;
     }
 }
 
@@ -595,256 +658,7 @@ k_diag(const double* __restrict__ tile_part, int ntiles,
 }
 
 // ---------------------------------------------------------------------------
-// FFT passes.  Spectrum layout [3][L(z)][L(y)][NC(kx)], NC = L/2 + 1.
-constexpr int EPT = 8;
-
-// Forward x pass.  Each block takes `rows` consecutive (component, z, y)
-// rows, forms the right-hand side r = a v + b (7-point Laplacian of v) + f
-// (Crank-Nicolson explicit half; r = f in steady mode), packs row pairs as
-// one complex line (z = r_even + i r_odd), transforms along x and unpacks
-// the two half spectra.  Also the block's float64 sums of v and f.
-template <typename T>
-__global__ void __launch_bounds__(1024)
-k_fft_x_fwd(const T* __restrict__ v, const T* __restrict__ f, int L, int NC,
-            FFTPlan pl, const cplx<T>* __restrict__ tw, T a, T b, int steady,
-            int rows, cplx<T>* __restrict__ spec, double* __restrict__ psum) {
-    extern __shared__ unsigned char smem_raw[];
-    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-    __shared__ double red[16];
-    const int nlines = rows / 2;
-    const int nthr = blockDim.x;
-    const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * rows;
-    const int64_t LL = (int64_t)L * L;
-    double sv = 0.0, sf = 0.0;
-    for (int e = tid; e < nlines * L; e += nthr) {
-        const int line = e / L;
-        const int x = e - line * L;
-        T val[2];
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            const int64_t row = r0 + 2 * line + hh;
-            const int y = (int)(row % L);
-            const int64_t zc = row / L;  // c * L + z
-            const int z = (int)(zc % L);
-            const int64_t cbase = (zc - z) * LL;  // component offset
-            const int64_t idx = row * L + x;
-            const T fv = f[idx];
-            sf += (double)fv;
-            if (steady) {
-                val[hh] = fv;
-            } else {
-                const T vc = v[idx];
-                sv += (double)vc;
-                const int xm = x == 0 ? L - 1 : x - 1, xp = x == L - 1 ? 0 : x + 1;
-                const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-                const int zm = z == 0 ? L - 1 : z - 1, zp = z == L - 1 ? 0 : z + 1;
-                const int64_t rb = row * L;
-                const T lap = (v[rb + xm] + v[rb + xp]) +
-                              (v[cbase + ((int64_t)z * L + ym) * L + x] +
-                               v[cbase + ((int64_t)z * L + yp) * L + x]) +
-                              (v[cbase + ((int64_t)zm * L + y) * L + x] +
-                               v[cbase + ((int64_t)zp * L + y) * L + x]) -
-                              T(6) * vc;
-                val[hh] = a * vc + b * lap + fv;
-            }
-        }
-        buf[line * L + x] = cplx<T>{val[0], val[1]};
-    }
-    __syncthreads();
-    lds_fft<T, false, EPT, false>(buf, pl, nlines, 1, L, tw, tid, nthr);
-    for (int e = tid; e < nlines * NC; e += nthr) {
-        const int line = e / NC;
-        const int k = e - line * NC;
-        const cplx<T> Z = buf[line * L + k];
-        const cplx<T> Zc = cconj(buf[line * L + (k == 0 ? 0 : L - k)]);
-        const cplx<T> s = cadd(Z, Zc), d = csub(Z, Zc);
-        const int64_t row = r0 + 2 * line;
-        spec[row * NC + k] = cplx<T>{T(0.5) * s.x, T(0.5) * s.y};
-        spec[(row + 1) * NC + k] = cplx<T>{T(0.5) * d.y, T(-0.5) * d.x};
-    }
-    const double ts = block_reduce<false>(sv, red);
-    const double tf = block_reduce<false>(sf, red);
-    if (tid == 0) {
-        psum[2 * blockIdx.x] = ts;
-        psum[2 * blockIdx.x + 1] = tf;
-    }
-}
-
-// y pass (forward or inverse), in place: block = (component, z plane, chunk
-// of W kx columns); each column is one line of length L.
-template <typename T, bool INV>
-__global__ void __launch_bounds__(1024)
-k_fft_y(cplx<T>* __restrict__ spec, int L, int NC, int W, FFTPlan pl,
-        const cplx<T>* __restrict__ tw) {
-    extern __shared__ unsigned char smem_raw[];
-    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int nch = (NC + W - 1) / W;
-    const int ch = blockIdx.x % nch;
-    const int64_t plane = blockIdx.x / nch;
-    const int kx0 = ch * W;
-    const int wc = min(W, NC - kx0);
-    cplx<T>* base = spec + plane * L * NC + kx0;
-    for (int e = threadIdx.x; e < L * W; e += blockDim.x) {
-        const int y = e / W;
-        const int col = e - y * W;
-        if (col < wc) buf[e] = base[(int64_t)y * NC + col];
-    }
-    __syncthreads();
-    lds_fft<T, INV, EPT, true>(buf, pl, wc, W, 1, tw, threadIdx.x, blockDim.x);
-    for (int e = threadIdx.x; e < L * W; e += blockDim.x) {
-        const int y = e / W;
-        const int col = e - y * W;
-        if (col < wc) base[(int64_t)y * NC + col] = buf[e];
-    }
-}
-
-// z pass fused with the spectral solve: block = (y row, chunk of W kx
-// columns) for all three components; forward transform along z, then per
-// wavevector m != 0
-//   v^ = (r^ - conj(D) (D . r^) / |D|^2) / (den |D|^2-dependent * N)
-// (the solenoidal projection of eq. vf on the MAC grid, D the divergence
-// symbol), the mean mode set from the float64 sums, then the inverse
-// transform along z.
-template <typename T>
-__global__ void __launch_bounds__(1024)
-k_fft_z_spectral(cplx<T>* __restrict__ spec, int L, int NC, int W, FFTPlan pl,
-                 const cplx<T>* __restrict__ tw,
-                 const cplx<T>* __restrict__ dsym, const T* __restrict__ d2,
-                 T c0, T c1, int steady, int zero_mean,
-                 const double* __restrict__ psum, int nblk_x, double mean_v_scale,
-                 double mean_f_scale) {
-    extern __shared__ unsigned char smem_raw[];
-    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-    __shared__ double red[16];
-    __shared__ double mean_new[3];
-    const int nch = (NC + W - 1) / W;
-    const int ch = blockIdx.x % nch;
-    const int y = blockIdx.x / nch;
-    const int kx0 = ch * W;
-    const int wc = min(W, NC - kx0);
-    const int64_t LL = (int64_t)L * L;
-    const int W3 = 3 * W;
-    for (int e = threadIdx.x; e < L * W3; e += blockDim.x) {
-        const int z = e / W3;
-        const int rem = e - z * W3;
-        const int c = rem / W;
-        const int col = rem - c * W;
-        cplx<T> val = {T(0), T(0)};
-        if (col < wc) val = spec[((int64_t)c * L + z) * (int64_t)L * NC + (int64_t)y * NC + kx0 + col];
-        buf[e] = val;
-    }
-    const bool owns_mean = (y == 0 && ch == 0);
-    if (owns_mean) {
-        // float64 mean of the new velocity: mean(v) + (dt/rho) mean(f)
-        const int per_c = nblk_x / 3;
-        for (int c = 0; c < 3; ++c) {
-            double s = 0.0;
-            for (int i = threadIdx.x; i < per_c; i += blockDim.x) {
-                const double* p = psum + 2 * (c * per_c + i);
-                s += mean_v_scale * p[0] + mean_f_scale * p[1];
-            }
-            s = block_reduce<false>(s, red);
-            if (threadIdx.x == 0) mean_new[c] = (steady || zero_mean) ? 0.0 : s;
-        }
-    }
-    __syncthreads();
-    lds_fft<T, false, EPT, true>(buf, pl, W3, W3, 1, tw, threadIdx.x, blockDim.x);
-    for (int e = threadIdx.x; e < L * W; e += blockDim.x) {
-        const int kz = e / W;
-        const int col = e - kz * W;
-        if (col >= wc) continue;
-        const int kx = kx0 + col;
-        cplx<T>* X = buf + kz * W3 + col;
-        if (kx == 0 && y == 0 && kz == 0) {
-            X[0] = cplx<T>{(T)mean_new[0], T(0)};
-            X[W] = cplx<T>{(T)mean_new[1], T(0)};
-            X[2 * W] = cplx<T>{(T)mean_new[2], T(0)};
-            continue;
-        }
-        const cplx<T> Dx = dsym[kx], Dy = dsym[y], Dz = dsym[kz];
-        const T D2 = d2[kx] + d2[y] + d2[kz];
-        const cplx<T> rx = X[0], ry = X[W], rz = X[2 * W];
-        const cplx<T> div = cadd(cadd(cmul(Dx, rx), cmul(Dy, ry)), cmul(Dz, rz));
-        const T inv_d2 = T(1) / D2;
-        // scale = 1 / ((c0 + c1 |D|^2) N); steady: c0 = 0, c1 = eta N
-        const T scale = T(1) / (c0 + c1 * D2);
-        const cplx<T> g = {div.x * inv_d2, div.y * inv_d2};
-        const cplx<T> px = csub(rx, cmul(cconj(Dx), g));
-        const cplx<T> py = csub(ry, cmul(cconj(Dy), g));
-        const cplx<T> pz = csub(rz, cmul(cconj(Dz), g));
-        X[0] = cplx<T>{px.x * scale, px.y * scale};
-        X[W] = cplx<T>{py.x * scale, py.y * scale};
-        X[2 * W] = cplx<T>{pz.x * scale, pz.y * scale};
-    }
-    __syncthreads();
-    lds_fft<T, true, EPT, true>(buf, pl, W3, W3, 1, tw, threadIdx.x, blockDim.x);
-    for (int e = threadIdx.x; e < L * W3; e += blockDim.x) {
-        const int z = e / W3;
-        const int rem = e - z * W3;
-        const int c = rem / W;
-        const int col = rem - c * W;
-        if (col < wc)
-            spec[((int64_t)c * L + z) * (int64_t)L * NC + (int64_t)y * NC + kx0 + col] = buf[e];
-    }
-    (void)LL;
-}
-
-// Inverse x pass: row pairs of half spectra are combined into one complex
-// line Z = X_even + i X_odd (Hermitian extension for kx > L/2, imaginary
-// parts of kx = 0 and L/2 dropped), transformed, and the real and imaginary
-// parts written as the two velocity rows.
-template <typename T>
-__global__ void __launch_bounds__(1024)
-k_fft_x_inv(const cplx<T>* __restrict__ spec, int L, int NC, FFTPlan pl,
-            const cplx<T>* __restrict__ tw, int rows, T* __restrict__ vout) {
-    extern __shared__ unsigned char smem_raw[];
-    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int nlines = rows / 2;
-    const int nthr = blockDim.x;
-    const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * rows;
-    const int half = L / 2;
-    for (int e = tid; e < nlines * L; e += nthr) {
-        const int line = e / L;
-        const int k = e - line * L;
-        const int64_t row = r0 + 2 * line;
-        cplx<T> X1, X2;
-        if (k <= half) {
-            X1 = spec[row * NC + k];
-            X2 = spec[(row + 1) * NC + k];
-            if (k == 0 || k == half) {
-                X1.y = T(0);
-                X2.y = T(0);
-            }
-        } else {
-            X1 = cconj(spec[row * NC + (L - k)]);
-            X2 = cconj(spec[(row + 1) * NC + (L - k)]);
-        }
-        buf[e] = cplx<T>{X1.x - X2.y, X1.y + X2.x};
-    }
-    __syncthreads();
-    lds_fft<T, true, EPT, false>(buf, pl, nlines, 1, L, tw, tid, nthr);
-    for (int e = tid; e < nlines * L; e += nthr) {
-        const int line = e / L;
-        const int x = e - line * L;
-        const int64_t row = r0 + 2 * line;
-        const cplx<T> z = buf[e];
-        vout[row * L + x] = z.x;
-        vout[(row + 1) * L + x] = z.y;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Launchers.
-#define MB_LAUNCH(g, id, s, kern, grid, block, shm, ...)                 \
-    do {                                                                 \
-        hipEvent_t ev_ = nullptr;                                        \
-        timer_begin((g), (id), (s), &ev_);                               \
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), (shm), (s),    \
-                           __VA_ARGS__);                                 \
-        timer_end((g), (id), (s), ev_);                                  \
-    } while (0)
 
 static inline unsigned blocks_for(int64_t n) {
     return (unsigned)((n + BLK - 1) / BLK);
@@ -854,7 +668,7 @@ template <typename T>
 hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
     if (M > 0)
         MB_LAUNCH(g, K_BIN_COUNT, s, k_bin_count, blocks_for(M), BLK, 0, q, M,
-                  g->d.h, g->L, g->d_count, g->d_rank);
+                  g->d.h, g->L, g->d_count, g->d_rank, (unsigned int*)g->d_fmax);
     MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
               g->N, g->d_bsum);
     MB_LAUNCH(g, K_SCAN_BLOCKS, s, k_scan_blocks, 1, BLK, 0, g->d_bsum, g->nscan);
@@ -870,7 +684,7 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
     const double h = g->d.h;
     MB_LAUNCH(g, K_BIN_SCATTER, s, k_bin_scatter<T>, blocks_for(M), BLK, 0, q, F,
               M, h, g->L, 1.0 / (h * h * h), g->d_offs, g->d_rank,
-              (Rec<T>*)g->d_rec, g->d_perm);
+              (Rec<T>*)g->d_rec, g->d_perm, (unsigned int*)g->d_fmax);
     return hipGetLastError();
 }
 
@@ -882,7 +696,8 @@ hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
     const double h = g->d.h;
     MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, blocks_for(M), BLK, 0,
               sp, q, Fext, M, h, g->L, 1.0 / (h * h * h), g->d_offs, g->d_rank,
-              (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part);
+              (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part,
+              (unsigned int*)g->d_fmax);
     return hipGetLastError();
 }
 
@@ -897,8 +712,11 @@ hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
 
 template <typename T, int TX>
 static void launch_spread(mb_grid* g, T* f, hipStream_t s) {
-    MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, TX, 8, 8>), g->tiles.n, BLK, 0,
-              (const Rec<T>*)g->d_rec, g->d_offs, g->L, g->tiles, f);
+    using ACC = typename std::conditional<std::is_same<T, float>::value,
+                                          unsigned long long, double>::type;
+    MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, ACC, TX, 8, 8>), g->tiles.n, BLK, 0,
+              (const Rec<T>*)g->d_rec, g->d_offs, g->L, g->tiles,
+              (const float*)g->d_fmax, f);
 }
 
 template <typename T>
@@ -933,46 +751,6 @@ hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t fluid_solve(mb_grid* g, const T* v_in, const T* f, T* v_out,
-                       hipStream_t s) {
-    const int L = g->L, NC = g->NC;
-    const bool steady = g->d.mode == MB_STEADY_STOKES;
-    const double h = g->d.h;
-    const double N = (double)g->N;
-    cplx<T>* spec = (cplx<T>*)g->d_spec;
-    const cplx<T>* tw = (const cplx<T>*)g->d_tw;
-    // explicit half of Crank-Nicolson: r = (rho/dt) v + (eta/2) L_h v + f
-    const T a = steady ? T(0) : (T)(g->d.rho / g->d.dt);
-    const T b = steady ? T(0) : (T)(0.5 * g->d.eta / (h * h));
-    const int rows = g->rows_x;
-    const int tx = (rows / 2) * L / EPT;
-    const size_t shx = (size_t)(rows / 2) * L * sizeof(cplx<T>);
-    MB_LAUNCH(g, K_FFT_X_FWD, s, k_fft_x_fwd<T>, g->nblk_x, tx, shx, v_in, f, L,
-              NC, g->plan, tw, a, b, (int)steady, rows, spec, g->d_psum);
-    const int nchy = (NC + g->wy - 1) / g->wy;
-    const int ty = L * g->wy / EPT;
-    const size_t shy = (size_t)L * g->wy * sizeof(cplx<T>);
-    MB_LAUNCH(g, K_FFT_Y_FWD, s, (k_fft_y<T, false>), 3 * L * nchy, ty, shy, spec,
-              L, NC, g->wy, g->plan, tw);
-    const int nchz = (NC + g->wz - 1) / g->wz;
-    const int tz = 3 * L * g->wz / EPT;
-    const size_t shz = (size_t)3 * L * g->wz * sizeof(cplx<T>);
-    // implicit half: 1 / ((rho/dt + (eta/2)|D|^2) N); steady: 1 / (eta |D|^2 N)
-    const T c0 = steady ? T(0) : (T)(g->d.rho / g->d.dt * N);
-    const T c1 = steady ? (T)(g->d.eta * N) : (T)(0.5 * g->d.eta * N);
-    const double mv = steady ? 0.0 : 1.0 / N;
-    const double mf = steady ? 0.0 : g->d.dt / g->d.rho / N;
-    MB_LAUNCH(g, K_FFT_Z_SPECTRAL, s, k_fft_z_spectral<T>, L * nchz, tz, shz, spec,
-              L, NC, g->wz, g->plan, tw, (const cplx<T>*)g->d_dsym,
-              (const T*)g->d_d2, c0, c1, (int)steady, g->d.zero_mean, g->d_psum,
-              g->nblk_x, mv, mf);
-    MB_LAUNCH(g, K_FFT_Y_INV, s, (k_fft_y<T, true>), 3 * L * nchy, ty, shy, spec, L,
-              NC, g->wy, g->plan, tw);
-    MB_LAUNCH(g, K_FFT_X_INV, s, k_fft_x_inv<T>, g->nblk_x, tx, shx, spec, L, NC,
-              g->plan, tw, rows, v_out);
-    return hipGetLastError();
-}
 
 hipError_t particle_means(mb_grid* g, int64_t P, int nb, const double* u,
                           double* U0, hipStream_t s) {
@@ -999,8 +777,6 @@ template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t,
 template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t);
 template hipError_t spread<float>(mb_grid*, float*, hipStream_t);
 template hipError_t spread<double>(mb_grid*, double*, hipStream_t);
-template hipError_t fluid_solve<float>(mb_grid*, const float*, const float*, float*, hipStream_t);
-template hipError_t fluid_solve<double>(mb_grid*, const double*, const double*, double*, hipStream_t);
 template hipError_t interpolate<float>(mb_grid*, int64_t, const float*, double*, double*, int, hipStream_t);
 template hipError_t interpolate<double>(mb_grid*, int64_t, const double*, double*, double*, int, hipStream_t);
 
