@@ -43,9 +43,8 @@ def algorithmic_bytes(L, M, P, prec, steady=False):
     spec = 3 * L * L * (L // 2 + 1) * 2 * s
     return {
         "bin_count": 24 * M + 4 * M + 8 * M,
-        "scan_reduce": 4 * N,
-        "scan_blocks": 8 * ((N + 4095) // 4096),
-        "scan_apply": 12 * N,
+        "scan_reduce": 4 * (N // 8),          # one count per 2x2x2 bin
+        "scan_apply": 12 * (N // 8),
         "springs_scatter": 24 * M + 24 * P + 12 * M + rec * M,
         "spread": rec * M + field,
         "fft_x_fwd": (1 if steady else 2) * field + spec,
@@ -124,6 +123,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="run one precision (profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device-to-device copy of 2^28 bytes, the "
+                         "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -133,6 +135,13 @@ def main():
     import torch
     from paper_1407_5600_amd import inputs
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)  # elementwise copy: reads and writes 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.cached(args.workload)
     res = {}
     for prec in (["mixed", "fp64"] if args.only is None else [args.only]):

@@ -23,7 +23,7 @@ using namespace mb;
 namespace {
 
 const char* const kKernelNames[K_NUM] = {
-    "bin_count",   "scan_reduce", "scan_blocks",      "scan_apply",
+    "bin_count",   "scan_reduce", "scan_apply",
     "springs_scatter", "bin_scatter", "springs",      "spread",
     "fft_x_fwd",   "fft_y_fwd",   "fft_z_spectral",   "fft_y_inv",
     "fft_x_inv",   "interp",      "interp_step",      "u0",
@@ -105,11 +105,15 @@ mb_status enter(mb_grid* g) {
 
 SpringsDev springs_dev(const mb_springs* sp) {
     SpringsDev d;
+    d.pa = sp->d_pa;
+    d.pb = sp->d_pb;
+    d.r0 = sp->d_r0;
     d.adj_start = sp->d_adj_start;
-    d.adj_other = sp->d_adj_other;
-    d.adj_r0 = sp->d_adj_r0;
+    d.adj_pair = sp->d_adj_pair;
     d.k = sp->k;
     d.nb = sp->nb;
+    d.npairs = sp->npairs;
+    d.ppb = sp->ppb;
     return d;
 }
 
@@ -211,8 +215,10 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     t.remap = (t.n % 8 == 0 && t.n >= 64) ? 1 : 0;
     g->tiles = t;
     g->rec_size = record_size(d.precision);
-    g->force_blocks_cap = (int)((std::max<int64_t>(d.max_blobs, 1) + 255) / 256);
-    g->nscan = (int)((g->N + 4095) / 4096);
+    // springs blocks hold at least one particle of at least one blob
+    g->force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
+    g->nbins = g->N / 8;
+    g->nscan = (int)((g->nbins + 4095) / 4096);
 
     const size_t cbytes = 2 * g->fsz;
     hipError_t e = hipSuccess;
@@ -224,8 +230,8 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     alloc(&g->d_d2, (size_t)L * g->fsz);
     alloc(&g->d_spec, (size_t)3 * L * L * g->NC * cbytes);
     alloc((void**)&g->d_psum, (size_t)g->nblk_x * 2 * sizeof(double));
-    alloc((void**)&g->d_count, (size_t)g->N * sizeof(int));
-    alloc((void**)&g->d_offs, (size_t)(g->N + 1) * sizeof(int));
+    alloc((void**)&g->d_count, (size_t)g->nbins * sizeof(int));
+    alloc((void**)&g->d_offs, (size_t)(g->nbins + 1) * sizeof(int));
     alloc((void**)&g->d_bsum, (size_t)g->nscan * sizeof(int));
     alloc((void**)&g->d_rank, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc((void**)&g->d_perm, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
@@ -236,7 +242,7 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     alloc((void**)&g->d_force_part, (size_t)g->force_blocks_cap * 3 * sizeof(double));
     alloc(&g->d_fmax, 256);
     if (e == hipSuccess) e = hipMemset(g->d_fmax, 0, 256);
-    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)g->N * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)g->nbins * sizeof(int));
     if (e == hipSuccess) e = hipMemset(g->d_force_part, 0, (size_t)g->force_blocks_cap * 3 * sizeof(double));
     if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)t.n * 4 * sizeof(double));
     if (e == hipSuccess) {
@@ -296,15 +302,21 @@ mb_status mb_springs_create(int32_t nb, int32_t npairs, const int32_t* pa,
         if (deg[b] > 63) return MB_ERR_INVALID;
     int dev = 0;
     if (!device_ok(&dev)) return MB_ERR_DEVICE;
+    // per-blob incident pairs, signed: +(e+1) when the blob is pair_a[e]
+    // (force +s d), -(e+1) when it is pair_b[e] (force -s d)
     std::vector<int> start(nb + 1, 0);
     for (int b = 0; b < nb; ++b) start[b + 1] = start[b] + deg[b];
-    std::vector<int> other(std::max(1, 2 * npairs), 0), fill(start.begin(), start.end() - 1);
-    std::vector<double> rest(std::max(1, 2 * npairs), 0.0);
+    std::vector<int> inc(std::max(1, 2 * npairs), 0), fill(start.begin(), start.end() - 1);
     for (int e = 0; e < npairs; ++e) {
-        other[fill[pa[e]]] = pb[e];
-        rest[fill[pa[e]]++] = r0[e];
-        other[fill[pb[e]]] = pa[e];
-        rest[fill[pb[e]]++] = r0[e];
+        inc[fill[pa[e]]++] = e + 1;
+        inc[fill[pb[e]]++] = -(e + 1);
+    }
+    std::vector<int> hpa(std::max(1, npairs), 0), hpb(std::max(1, npairs), 0);
+    std::vector<double> hr0(std::max(1, npairs), 1.0);
+    for (int e = 0; e < npairs; ++e) {
+        hpa[e] = pa[e];
+        hpb[e] = pb[e];
+        hr0[e] = r0[e];
     }
     mb_springs* sp = new (std::nothrow) mb_springs();
     if (!sp) return MB_ERR_NOMEM;
@@ -312,12 +324,24 @@ mb_status mb_springs_create(int32_t nb, int32_t npairs, const int32_t* pa,
     sp->npairs = npairs;
     sp->k = k;
     sp->device = dev;
-    hipError_t e = hipMalloc(&sp->d_adj_start, start.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&sp->d_adj_other, other.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&sp->d_adj_r0, rest.size() * sizeof(double));
-    if (e == hipSuccess) e = hipMemcpy(sp->d_adj_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(sp->d_adj_other, other.data(), other.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(sp->d_adj_r0, rest.data(), rest.size() * sizeof(double), hipMemcpyHostToDevice);
+    // particles per block: at most 256 blobs, pair forces + positions in
+    // at most 48 KB of LDS
+    {
+        const int by_blobs = std::max(1, 256 / nb);
+        const int per_particle = (npairs + nb) * 3 * (int)sizeof(double);
+        const int by_lds = std::max(1, (48 * 1024) / per_particle);
+        sp->ppb = std::min(by_blobs, by_lds);
+    }
+    hipError_t e = hipSuccess;
+    auto up = [&](void** dst, const void* src, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(dst, bytes);
+        if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    up((void**)&sp->d_pa, hpa.data(), hpa.size() * sizeof(int));
+    up((void**)&sp->d_pb, hpb.data(), hpb.size() * sizeof(int));
+    up((void**)&sp->d_r0, hr0.data(), hr0.size() * sizeof(double));
+    up((void**)&sp->d_adj_start, start.data(), start.size() * sizeof(int));
+    up((void**)&sp->d_adj_pair, inc.data(), inc.size() * sizeof(int));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         mb_springs_destroy(sp);
@@ -330,9 +354,9 @@ mb_status mb_springs_create(int32_t nb, int32_t npairs, const int32_t* pa,
 mb_status mb_springs_destroy(mb_springs* sp) {
     if (!sp) return MB_OK;
     (void)hipDeviceSynchronize();
-    if (sp->d_adj_start) (void)hipFree(sp->d_adj_start);
-    if (sp->d_adj_other) (void)hipFree(sp->d_adj_other);
-    if (sp->d_adj_r0) (void)hipFree(sp->d_adj_r0);
+    void* ptrs[] = {sp->d_pa, sp->d_pb, sp->d_r0, sp->d_adj_start, sp->d_adj_pair};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
     delete sp;
     return MB_OK;
 }
@@ -421,7 +445,7 @@ mb_status mb_step(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
     if (nsteps == 0) return MB_OK;
     hipStream_t s = (hipStream_t)stream;
     const SpringsDev sd = springs_dev(sp);
-    const int fb = (int)((M + 255) / 256);
+    const int fb = springs_blocks(sd, P);
     if (M == 0) {
         // no blobs: the force partials of the diagnostics are zero
         hipError_t e0 = hipMemsetAsync(g->d_force_part, 0, 3 * sizeof(double), s);

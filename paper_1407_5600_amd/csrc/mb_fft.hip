@@ -131,9 +131,12 @@ constexpr int cols_y(int L) {
     return w < nc ? w : nc;
 }
 // ky columns per block of the z pass (a divisor of L; LDS <= 64 KB)
+#ifndef MB_ZCOLS
+#define MB_ZCOLS 16
+#endif
 template <typename T>
 constexpr int cols_z(int L) {
-    int w = 16;
+    int w = MB_ZCOLS;
     while (w > 1 && (L % w != 0 || 3 * L * w * 2 * (int)sizeof(T) > 65536 ||
                      3 * w * L / EPT > 1024))
         w /= 2;

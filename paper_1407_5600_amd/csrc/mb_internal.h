@@ -15,7 +15,6 @@ namespace mb {
 enum KernelId : int {
     K_BIN_COUNT = 0,
     K_SCAN_REDUCE,
-    K_SCAN_BLOCKS,
     K_SCAN_APPLY,
     K_SPRINGS_SCATTER,
     K_BIN_SCATTER,
@@ -33,14 +32,19 @@ enum KernelId : int {
     K_NUM
 };
 
-// Spring table on the device, as per-blob adjacency lists of the particle
-// template (each pair appears in the lists of both of its blobs).
+// Spring table of the particle template on the device: the pair list and,
+// per blob, the incident pairs with the sign of their force on that blob
+// (+1 for the pair's first blob, -1 for its second).
 struct SpringsDev {
+    const int* pa;          // [npairs]
+    const int* pb;          // [npairs]
+    const double* r0;       // [npairs]
     const int* adj_start;   // [nb + 1]
-    const int* adj_other;   // [2 * npairs]
-    const double* adj_r0;   // [2 * npairs]
+    const int* adj_pair;    // [2 * npairs] signed: pair + 1 or -(pair + 1)
     double k;
     int nb;
+    int npairs;
+    int ppb;                // particles per block of the springs kernels
 };
 
 // Tile geometry for spreading and interpolation.
@@ -61,11 +65,14 @@ struct TimerPair {
 struct mb_springs {
     int nb;
     int npairs;
+    int ppb;
     double k;
     int device;
+    int* d_pa;
+    int* d_pb;
+    double* d_r0;
     int* d_adj_start;
-    int* d_adj_other;
-    double* d_adj_r0;
+    int* d_adj_pair;
 };
 
 struct mb_grid {
@@ -82,8 +89,9 @@ struct mb_grid {
     int nblk_x;         // blocks of an x pass
     double* d_psum;     // [nblk_x][2] per-block sums of v and f (float64)
     // binning
-    int* d_count;       // [N] (kept zeroed between uses)
-    int* d_offs;        // [N + 1]
+    int64_t nbins;      // (L/2)^3 bins of 2x2x2 cells
+    int* d_count;       // [nbins] (kept zeroed between uses)
+    int* d_offs;        // [nbins + 1]
     int* d_bsum;        // scan block sums
     int nscan;          // scan blocks
     int* d_rank;        // [max_blobs]
@@ -149,5 +157,8 @@ hipError_t particle_means(mb_grid* g, int64_t P, int nb, const double* u,
 hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,
                        hipStream_t s);
 size_t record_size(int precision);
+// Blocks and dynamic LDS bytes of the springs kernels for P particles.
+int springs_blocks(const SpringsDev& sp, int64_t P);
+size_t springs_lds(const SpringsDev& sp);
 
 }  // namespace mb

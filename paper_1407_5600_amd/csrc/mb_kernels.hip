@@ -45,13 +45,18 @@ struct Geom {
 __device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
                                           int64_t i, double h, int L) {
     Geom g;
+    const double Ld = (double)L;
+    const double invL = 1.0 / Ld;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         const double x = q[3 * i + b] / h;
         const double fl = floor(x);
         const double s = x - fl;  // [0, 1)
-        long long c = (long long)fl % L;
-        if (c < 0) c += L;
+        // fl mod L without integer division: exact for |fl| < 2^53, the
+        // rounded quotient is off by at most one and corrected
+        double c = fl - floor(fl * invL) * Ld;
+        if (c < 0.0) c += Ld;
+        if (c >= Ld) c -= Ld;
         g.c[b] = (int)c;
         g.up[b] = s >= 0.5 ? 1 : 0;
         g.tu[b] = s - (double)g.up[b];
@@ -60,8 +65,11 @@ __device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
     return g;
 }
 
-__device__ __forceinline__ int cell_linear(const Geom& g, int L) {
-    return (g.c[2] * L + g.c[1]) * L + g.c[0];
+// Bin of a blob: blobs are sorted by 2x2x2 groups of cells ("bins"),
+// (L/2)^3 of them, x fastest.
+__device__ __forceinline__ int bin_linear(const Geom& g, int L) {
+    const int Lb = L >> 1;
+    return ((g.c[2] >> 1) * Lb + (g.c[1] >> 1)) * Lb + (g.c[0] >> 1);
 }
 
 __device__ __forceinline__ uint32_t cell_pack(const Geom& g) {
@@ -80,7 +88,7 @@ k_bin_count(const double* __restrict__ q, int64_t M, double h, int L,
     if (i == 0) *fmax = 0u;  // max |F h^-3| of this step, set by the scatter
     if (i >= M) return;
     const Geom g = blob_geom(q, i, h, L);
-    rank[i] = atomicAdd(&count[cell_linear(g, L)], 1);
+    rank[i] = atomicAdd(&count[bin_linear(g, L)], 1);
 }
 
 constexpr int SCAN_ITEMS = 16;
@@ -121,42 +129,24 @@ __device__ int scan_tile_lds(int* s, int* scratch) {
     return total;
 }
 
-// Exclusive scan of the block sums, in place (one block).
-__global__ void __launch_bounds__(BLK)
-k_scan_blocks(int* __restrict__ bsum, int nb) {
-    __shared__ int s[SCAN_TILE + SCAN_TILE / 32];
-    __shared__ int scratch[16];
-    int carry = 0;
-    for (int base = 0; base < nb; base += SCAN_TILE) {
-        for (int k = 0; k < SCAN_ITEMS; ++k) {
-            const int i = k * BLK + threadIdx.x;
-            s[scan_pad(i)] = (base + i < nb) ? bsum[base + i] : 0;
-        }
-        __syncthreads();
-        const int total = scan_tile_lds(s, scratch);
-        for (int k = 0; k < SCAN_ITEMS; ++k) {
-            const int i = k * BLK + threadIdx.x;
-            if (base + i < nb) bsum[base + i] = s[scan_pad(i)] + carry;
-        }
-        carry += total;
-        __syncthreads();
-    }
-}
-
 // offs[i] = exclusive prefix of count; offs[n] = total; count reset to 0.
+// Each block adds the sums of the blocks before it (a few hundred at most).
 __global__ void __launch_bounds__(BLK)
 k_scan_apply(int* __restrict__ count, int64_t n, const int* __restrict__ bsum,
              int* __restrict__ offs) {
     __shared__ int s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ int scratch[16];
+    __shared__ double red[16];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int before = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += BLK) before += bsum[b];
+    const int off = (int)block_reduce<false>((double)before, red);
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         const int i = k * BLK + threadIdx.x;
         s[scan_pad(i)] = (base + i < n) ? count[base + i] : 0;
     }
     __syncthreads();
     const int total = scan_tile_lds(s, scratch);
-    const int off = bsum[blockIdx.x];
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         const int i = k * BLK + threadIdx.x;
         if (base + i < n) {
@@ -217,62 +207,108 @@ k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
             f[1] = F[3 * i + 1];
             f[2] = F[3 * i + 2];
         }
-        const int64_t pos = (int64_t)offs[cell_linear(g, L)] + rank[i];
+        const int64_t pos = (int64_t)offs[bin_linear(g, L)] + rank[i];
         m = write_record<T>(rec, perm, pos, i, g, f, inv_vol);
     }
     fold_fmax(m, red, fmax);
 }
 
-// Spring force on blob i (float64): sum over the template pairs of blob b
-// of k (|d| - r0) d / |d| with d = q_other - q_i, plus Fext_p / nb.
-__device__ __forceinline__ void spring_force(const SpringsDev& sp,
+// Spring forces of the sp.ppb particles of this block (float64).  Their
+// blob positions are loaded into LDS once; each pair force of every
+// particle, s d with d = q_b - q_a and s = k (|d| - r0) / |d|, is computed
+// once; then thread j (< nblob) sums the incident pair forces of its blob
+// (+s d on pair_a, -s d on pair_b) plus Fext_p / nb.  Returns the number of
+// blobs of the block; F holds thread j's blob force.
+__device__ __forceinline__ int springs_block(const SpringsDev& sp,
                                              const double* __restrict__ q,
                                              const double* __restrict__ Fext,
-                                             int64_t i, double F[3]) {
-    const int64_t p = i / sp.nb;
-    const int b = (int)(i - p * sp.nb);
-    const double qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (Fext) {
-        const double inv_nb = 1.0 / (double)sp.nb;
-        fx = Fext[3 * p] * inv_nb;
-        fy = Fext[3 * p + 1] * inv_nb;
-        fz = Fext[3 * p + 2] * inv_nb;
+                                             int64_t P, double* smem,
+                                             double F[3], int64_t* blob) {
+    const int nb = sp.nb, np = sp.npairs;
+    const int64_t p0 = (int64_t)blockIdx.x * sp.ppb;
+    const int npart = (int)(P - p0 < sp.ppb ? P - p0 : sp.ppb);
+    const int nblob = npart * nb;
+    double* qs = smem;                     // [ppb * nb][3]
+    double* fp = smem + 3 * sp.ppb * nb;   // [ppb * np][3]
+    double* r0s = fp + 3 * sp.ppb * np;    // [np]
+    int* pab = (int*)(r0s + np);           // [np] packed pair_a | pair_b << 16
+    const double* qg = q + 3 * p0 * nb;    // contiguous blobs of the block
+    for (int i = threadIdx.x; i < 3 * nblob; i += BLK) qs[i] = qg[i];
+    for (int e = threadIdx.x; e < np; e += BLK) {
+        r0s[e] = sp.r0[e];
+        pab[e] = sp.pa[e] | (sp.pb[e] << 16);
     }
-    const int e1 = sp.adj_start[b + 1];
-    for (int e = sp.adj_start[b]; e < e1; ++e) {
-        const int64_t j = p * sp.nb + sp.adj_other[e];
-        const double dx = q[3 * j] - qx, dy = q[3 * j + 1] - qy,
-                     dz = q[3 * j + 2] - qz;
+    __syncthreads();
+    for (int w = threadIdx.x; w < npart * np; w += BLK) {
+        const int pl = w / np;
+        const int e = w - pl * np;
+        const int ab = pab[e];
+        const double* qa = qs + 3 * (pl * nb + (ab & 0xffff));
+        const double* qb = qs + 3 * (pl * nb + (ab >> 16));
+        const double dx = qb[0] - qa[0], dy = qb[1] - qa[1], dz = qb[2] - qa[2];
         const double len = sqrt(dx * dx + dy * dy + dz * dz);
-        const double s = sp.k * (len - sp.adj_r0[e]) / len;
-        fx += s * dx;
-        fy += s * dy;
-        fz += s * dz;
+        const double s = sp.k * (len - r0s[e]) / len;
+        fp[3 * w] = s * dx;
+        fp[3 * w + 1] = s * dy;
+        fp[3 * w + 2] = s * dz;
     }
-    F[0] = fx;
-    F[1] = fy;
-    F[2] = fz;
+    __syncthreads();
+    F[0] = F[1] = F[2] = 0.0;
+    *blob = -1;
+    const int j = threadIdx.x;
+    if (j < nblob) {
+        const int pl = j / nb;
+        const int b = j - pl * nb;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        if (Fext) {
+            const double inv_nb = 1.0 / (double)nb;
+            const double* fe = Fext + 3 * (p0 + pl);
+            fx = fe[0] * inv_nb;
+            fy = fe[1] * inv_nb;
+            fz = fe[2] * inv_nb;
+        }
+        const int e1 = sp.adj_start[b + 1];
+        for (int x = sp.adj_start[b]; x < e1; ++x) {
+            const int code = sp.adj_pair[x];
+            const int e = (code > 0 ? code : -code) - 1;
+            const double* f = fp + 3 * (pl * np + e);
+            if (code > 0) {
+                fx += f[0];
+                fy += f[1];
+                fz += f[2];
+            } else {
+                fx -= f[0];
+                fy -= f[1];
+                fz -= f[2];
+            }
+        }
+        F[0] = fx;
+        F[1] = fy;
+        F[2] = fz;
+        *blob = p0 * nb + j;
+    }
+    return nblob;
 }
 
 // Spring forces fused with the scatter of the records; also the per-block
-// float64 sums of the blob forces (momentum diagnostics).
+// float64 sums of the blob forces (momentum diagnostics) and max |F h^-3|.
 template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
-                  const double* __restrict__ Fext, int64_t M, double h, int L,
+                  const double* __restrict__ Fext, int64_t P, double h, int L,
                   double inv_vol, const int* __restrict__ offs,
                   const int* __restrict__ rank, Rec<T>* __restrict__ rec,
                   int* __restrict__ perm, double* __restrict__ fpart,
                   unsigned int* __restrict__ fmax) {
+    extern __shared__ double smem[];
     __shared__ double red[16];
-    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    double F[3] = {0.0, 0.0, 0.0};
+    double F[3];
+    int64_t i;
+    springs_block(sp, q, Fext, P, smem, F, &i);
     float m = 0.f;
-    if (i < M) {
-        spring_force(sp, q, Fext, i, F);
+    if (i >= 0) {
         const Geom g = blob_geom(q, i, h, L);
-        const int64_t pos = (int64_t)offs[cell_linear(g, L)] + rank[i];
+        const int64_t pos = (int64_t)offs[bin_linear(g, L)] + rank[i];
         m = write_record<T>(rec, perm, pos, i, g, F, inv_vol);
     }
     fold_fmax(m, red, fmax);
@@ -285,11 +321,12 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
 
 __global__ void __launch_bounds__(BLK)
 k_springs(SpringsDev sp, const double* __restrict__ q,
-          const double* __restrict__ Fext, int64_t M, double* __restrict__ Fout) {
-    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    if (i >= M) return;
+          const double* __restrict__ Fext, int64_t P, double* __restrict__ Fout) {
+    extern __shared__ double smem[];
     double F[3];
-    spring_force(sp, q, Fext, i, F);
+    int64_t i;
+    springs_block(sp, q, Fext, P, smem, F, &i);
+    if (i < 0) return;
     Fout[3 * i] = F[0];
     Fout[3 * i + 1] = F[1];
     Fout[3 * i + 2] = F[2];
@@ -465,8 +502,8 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
     constexpr int TV = TX * TY * TZ;
     constexpr bool FIXED = !std::is_same<ACC, double>::value;
     __shared__ ACC acc[3 * TV];
-    __shared__ int seg_start[2 * (TY + 3) * (TZ + 3)];
-    __shared__ int seg_pre[2 * (TY + 3) * (TZ + 3) + 1];
+    __shared__ int seg_start[2 * (TY / 2 + 2) * (TZ / 2 + 2)];
+    __shared__ int seg_pre[2 * (TY / 2 + 2) * (TZ / 2 + 2) + 1];
     __shared__ int scratch[16];
     const TileBox tb = tile_box(tl, L);
     const int tdim[3] = {tl.tx, tl.ty, tl.tz};
@@ -480,15 +517,25 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
             e = 30 - ex;
         }
     }
+    // bins (2x2x2 cells) covering the cells [lo-2, hi+1] that can reach the
+    // tile: bins [lo/2 - 1, (lo+T)/2] per axis (one spare cell layer above)
     int nseg;
-    const int ext[3] = {tb.full[0] ? L : tl.tx + 3, tb.full[1] ? L : tl.ty + 3,
-                        tb.full[2] ? L : tl.tz + 3};
-    const int elo[3] = {tb.full[0] ? 0 : tb.lo[0] - 2, tb.full[1] ? 0 : tb.lo[1] - 2,
-                        tb.full[2] ? 0 : tb.lo[2] - 2};
-    const int total = gather_segments(offs, L, elo[0], ext[0], elo[1], ext[1],
+    const int Lb = L >> 1;
+    const int ext[3] = {tb.full[0] ? Lb : tl.tx / 2 + 2, tb.full[1] ? Lb : tl.ty / 2 + 2,
+                        tb.full[2] ? Lb : tl.tz / 2 + 2};
+    const int elo[3] = {tb.full[0] ? 0 : tb.lo[0] / 2 - 1, tb.full[1] ? 0 : tb.lo[1] / 2 - 1,
+                        tb.full[2] ? 0 : tb.lo[2] / 2 - 1};
+    const int total = gather_segments(offs, Lb, elo[0], ext[0], elo[1], ext[1],
                                       elo[2], ext[2], seg_start, seg_pre,
                                       scratch, &nseg);
-    for (int k = threadIdx.x; k < total; k += BLK) {
+    // Records are bin-sorted, so consecutive records hit the same nodes.
+    // Lane l of a wave takes record l * span + j instead of 64 j + l: a
+    // wave's atomics then land far apart in the tile (fewer same-address and
+    // same-bank collisions).
+    const int span = (total + WAVE - 1) / WAVE;
+    for (int it = threadIdx.x; it < span * WAVE; it += BLK) {
+        const int k = (it % WAVE) * span + it / WAVE;
+        if (k >= total) continue;
         const int s = find_segment(seg_pre, nseg, k);
         const Rec<T> r = rec[seg_start[s] + (k - seg_pre[s])];
         spread_record<T, ACC, TX, TY, TZ>(r, tb, tdim, L, e, acc);
@@ -524,12 +571,17 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
     constexpr int EV = EX * EY * EZ;
     __shared__ T vt[3 * EV];
-    __shared__ int seg_start[TY * TZ];
-    __shared__ int seg_pre[TY * TZ + 1];
+    __shared__ int seg_start[(TY / 2) * (TZ / 2)];
+    __shared__ int seg_pre[(TY / 2) * (TZ / 2) + 1];
     __shared__ int scratch[16];
     __shared__ double red[16];
     const TileBox tb = tile_box(tl, L);
-    const int64_t N = (int64_t)L * L * L;
+    const int N = L * L * L;  // 3 L^3 < 2^31 for L <= 512
+    // the tile's own cells are exactly the bins [lo/2, (lo+T)/2)
+    int nseg;
+    const int total = gather_segments(offs, L >> 1, tb.lo[0] >> 1, tl.tx >> 1,
+                                      tb.lo[1] >> 1, tl.ty >> 1, tb.lo[2] >> 1,
+                                      tl.tz >> 1, seg_start, seg_pre, scratch, &nseg);
     for (int i = threadIdx.x; i < 3 * EV; i += BLK) {
         const int a = i / EV;
         const int rem = i - a * EV;
@@ -539,13 +591,9 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
         const int x = wrapL(tb.lo[0] - 1 + ex, L);
         const int y = wrapL(tb.lo[1] - 1 + ey, L);
         const int z = wrapL(tb.lo[2] - 1 + ez, L);
-        vt[i] = v[a * N + ((int64_t)z * L + y) * L + x];
+        vt[i] = v[a * N + (z * L + y) * L + x];
     }
     __syncthreads();
-    int nseg;
-    const int total = gather_segments(offs, L, tb.lo[0], tl.tx, tb.lo[1], tl.ty,
-                                      tb.lo[2], tl.tz, seg_start, seg_pre,
-                                      scratch, &nseg);
     for (int k = threadIdx.x; k < total; k += BLK) {
         const int s = find_segment(seg_pre, nseg, k);
         const int pos = seg_start[s] + (k - seg_pre[s]);
@@ -670,10 +718,9 @@ hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
         MB_LAUNCH(g, K_BIN_COUNT, s, k_bin_count, blocks_for(M), BLK, 0, q, M,
                   g->d.h, g->L, g->d_count, g->d_rank, (unsigned int*)g->d_fmax);
     MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
-              g->N, g->d_bsum);
-    MB_LAUNCH(g, K_SCAN_BLOCKS, s, k_scan_blocks, 1, BLK, 0, g->d_bsum, g->nscan);
+              g->nbins, g->d_bsum);
     MB_LAUNCH(g, K_SCAN_APPLY, s, k_scan_apply, g->nscan, BLK, 0, g->d_count,
-              g->N, g->d_bsum, g->d_offs);
+              g->nbins, g->d_bsum, g->d_offs);
     return hipGetLastError();
 }
 
@@ -694,9 +741,9 @@ hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
     const int64_t M = P * sp.nb;
     if (M == 0) return hipSuccess;
     const double h = g->d.h;
-    MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, blocks_for(M), BLK, 0,
-              sp, q, Fext, M, h, g->L, 1.0 / (h * h * h), g->d_offs, g->d_rank,
-              (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part,
+    MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, springs_blocks(sp, P), BLK,
+              springs_lds(sp), sp, q, Fext, P, h, g->L, 1.0 / (h * h * h), g->d_offs,
+              g->d_rank, (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part,
               (unsigned int*)g->d_fmax);
     return hipGetLastError();
 }
@@ -706,8 +753,18 @@ hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
                          mb_grid* tg) {
     const int64_t M = P * sp.nb;
     if (M == 0) return hipSuccess;
-    MB_LAUNCH(tg, K_SPRINGS, s, k_springs, blocks_for(M), BLK, 0, sp, q, Fext, M, F);
+    MB_LAUNCH(tg, K_SPRINGS, s, k_springs, springs_blocks(sp, P), BLK, springs_lds(sp),
+              sp, q, Fext, P, F);
     return hipGetLastError();
+}
+
+int springs_blocks(const SpringsDev& sp, int64_t P) {
+    return (int)((P + sp.ppb - 1) / sp.ppb);
+}
+
+size_t springs_lds(const SpringsDev& sp) {
+    return (size_t)sp.ppb * (sp.nb + sp.npairs) * 3 * sizeof(double) +
+           (size_t)sp.npairs * (sizeof(double) + sizeof(int));
 }
 
 template <typename T, int TX>
