@@ -27,7 +27,7 @@ const char* const kKernelNames[K_NUM] = {
     "springs_scatter", "bin_scatter", "springs",      "spread",
     "fft_x_fwd",   "fft_y_fwd",   "fft_z_spectral",   "fft_y_inv",
     "fft_x_inv",   "interp",      "interp_step",      "u0",
-    "diag"};
+    "diag",        "fold"};
 
 bool size_ok(int L) {
     if (L < 8 || L > 512 || L % 8 != 0) return false;
@@ -82,7 +82,7 @@ void free_grid(mb_grid* g) {
     void* ptrs[] = {g->d_tw,    g->d_dsym,  g->d_d2,   g->d_spec,
                     g->d_psum,  g->d_count, g->d_offs, g->d_bsum,
                     g->d_rank,  g->d_perm,  g->d_rec,  g->d_tile_part,
-                    g->d_force_part, g->d_f, g->d_u, g->d_fmax};
+                    g->d_force_part, g->d_box, g->d_u, g->d_fmax};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& tp : g->pending) {
@@ -237,7 +237,7 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     alloc((void**)&g->d_perm, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc(&g->d_rec, (size_t)std::max<int64_t>(d.max_blobs, 1) * g->rec_size);
     alloc((void**)&g->d_tile_part, (size_t)t.n * 4 * sizeof(double));
-    alloc(&g->d_f, (size_t)3 * g->N * g->fsz);
+    alloc(&g->d_box, box_elems(t) * g->fsz);
     alloc((void**)&g->d_u, (size_t)std::max<int64_t>(d.max_blobs, 1) * 3 * sizeof(double));
     alloc((void**)&g->d_force_part, (size_t)g->force_blocks_cap * 3 * sizeof(double));
     alloc(&g->d_fmax, 256);
@@ -373,11 +373,13 @@ mb_status mb_spread(mb_grid* g, int64_t M, const double* q, const double* F,
     if (g->fsz == 4) {
         e = bin_blobs<float>(g, M, q, s);
         if (e == hipSuccess) e = scatter_records<float>(g, M, q, F, s);
-        if (e == hipSuccess) e = spread<float>(g, (float*)f_out, s);
+        if (e == hipSuccess) e = spread_boxes<float>(g, s);
+        if (e == hipSuccess) e = fold_boxes<float>(g, (float*)f_out, s);
     } else {
         e = bin_blobs<double>(g, M, q, s);
         if (e == hipSuccess) e = scatter_records<double>(g, M, q, F, s);
-        if (e == hipSuccess) e = spread<double>(g, (double*)f_out, s);
+        if (e == hipSuccess) e = spread_boxes<double>(g, s);
+        if (e == hipSuccess) e = fold_boxes<double>(g, (double*)f_out, s);
     }
     return from_hip(e);
 }
@@ -457,20 +459,18 @@ mb_status mb_step(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
         double* u_dst = nullptr;
         if (last) u_dst = u_out ? u_out : (U0_out ? g->d_u : nullptr);
         if (g->fsz == 4) {
-            float* f = (float*)g->d_f;
             float* vv = (float*)v;
             e = bin_blobs<float>(g, M, q, s);
             if (e == hipSuccess) e = scatter_springs<float>(g, sd, P, q, Fext, s);
-            if (e == hipSuccess) e = spread<float>(g, f, s);
-            if (e == hipSuccess) e = fluid_solve<float>(g, vv, f, vv, s);
+            if (e == hipSuccess) e = spread_boxes<float>(g, s);
+            if (e == hipSuccess) e = fluid_solve<float>(g, vv, nullptr, vv, s, true);
             if (e == hipSuccess) e = interpolate<float>(g, M, vv, u_dst, q, 1, s);
         } else {
-            double* f = (double*)g->d_f;
             double* vv = (double*)v;
             e = bin_blobs<double>(g, M, q, s);
             if (e == hipSuccess) e = scatter_springs<double>(g, sd, P, q, Fext, s);
-            if (e == hipSuccess) e = spread<double>(g, f, s);
-            if (e == hipSuccess) e = fluid_solve<double>(g, vv, f, vv, s);
+            if (e == hipSuccess) e = spread_boxes<double>(g, s);
+            if (e == hipSuccess) e = fluid_solve<double>(g, vv, nullptr, vv, s, true);
             if (e == hipSuccess) e = interpolate<double>(g, M, vv, u_dst, q, 1, s);
         }
         if (last && e == hipSuccess && U0_out)

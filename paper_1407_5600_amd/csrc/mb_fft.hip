@@ -21,6 +21,7 @@
 
 #include <cstdint>
 
+#include "mb_box.h"
 #include "mb_device.h"
 #include "mb_internal.h"
 
@@ -159,10 +160,10 @@ struct Geo {
 };
 
 // ---------------------------------------------------------------------------
-template <typename T, int L>
+template <typename T, int L, bool BOX, bool STEADY>
 __global__ void __launch_bounds__((Geo<T, L>::TX))
-k_x_fwd(const T* __restrict__ v, const T* __restrict__ f,
-        const cplx<T>* __restrict__ tw, T a, T b, int steady,
+k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
+        const cplx<T>* __restrict__ tw, T a, T b,
         cplx<T>* __restrict__ A, double* __restrict__ psum) {
     using G = Geo<T, L>;
     constexpr int NC = G::NC, R = G::R, NL = G::NL, NTHR = G::TX, LS = G::LS;
@@ -178,19 +179,28 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f,
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
     double sv = 0.0, sf = 0.0;
     const int zm = (z == 0 ? L - 1 : z - 1), zp = (z == L - 1 ? 0 : z + 1);
+    // boxed force: the box entries of this z plane and component
+    const T* Ec = nullptr;
+    AxisSrc bz{};
+    if (BOX) {
+        Ec = f + (size_t)(cz / L) * tl.n * box_volume(tl);
+        bz = box_src_z(tl, z);
+    }
 #pragma unroll
     for (int kk = 0; kk < EPT; ++kk) {
         const int e = tid + kk * NTHR;
         const int line = e / L;
         const int x = e - line * L;
+        AxisSrc bx{};
+        if (BOX) bx = box_src_x(tl, x);
         T val[2];
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             const int y = y0 + 2 * line + hh;
             const int idx = cbase + (z * L + y) * L + x;
-            const T fv = f[idx];
+            const T fv = BOX ? box_sum(Ec, bx, box_src_y(tl, y), bz) : f[idx];
             sf += (double)fv;
-            if (steady) {
+            if (STEADY) {
                 val[hh] = fv;
             } else {
                 const T vc = v[idx];
@@ -205,7 +215,7 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f,
                 val[hh] = a * vc + b * lap + fv;
             }
         }
-        buf[line * LS + x] = cplx<T>{val[0], val[1]};
+    buf[line * LS + x] = cplx<T>{val[0], val[1]};
     }
     __syncthreads();
     line_fft<T, L, false, NL, LS, NTHR>(buf, tws, tid);
@@ -411,7 +421,7 @@ k_x_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
 }
 
 template <typename T, int L>
-hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, T* v_out,
+hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, bool boxed, T* v_out,
                        hipStream_t s) {
     using G = Geo<T, L>;
     const bool steady = g->d.mode == MB_STEADY_STOKES;
@@ -421,8 +431,18 @@ hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, T* v_out,
     const cplx<T>* tw = (const cplx<T>*)g->d_tw;
     const T a = steady ? T(0) : (T)(g->d.rho / g->d.dt);
     const T b = steady ? T(0) : (T)(0.5 * g->d.eta / (h * h));
-    MB_LAUNCH(g, K_FFT_X_FWD, s, (k_x_fwd<T, L>), G::NBX, G::TX, 0, v_in, f, tw, a,
-              b, (int)steady, A, g->d_psum);
+    const T* fin = boxed ? (const T*)g->d_box : f;
+#define MB_XF(BX, ST)                                                              \
+    MB_LAUNCH(g, K_FFT_X_FWD, s, (k_x_fwd<T, L, BX, ST>), G::NBX, G::TX, 0, v_in, fin, \
+              g->tiles, tw, a, b, A, g->d_psum)
+    if (boxed) {
+        if (steady) MB_XF(true, true);
+        else MB_XF(true, false);
+    } else {
+        if (steady) MB_XF(false, true);
+        else MB_XF(false, false);
+    }
+#undef MB_XF
     MB_LAUNCH(g, K_FFT_Y_FWD, s, (k_y<T, L, false>), 3 * L * G::NCHY, G::TY, 0, A, tw);
     const T c0 = steady ? T(0) : (T)(g->d.rho / g->d.dt * N);
     const T c1 = steady ? (T)(g->d.eta * N) : (T)(0.5 * g->d.eta * N);
@@ -445,10 +465,10 @@ hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, T* v_out,
 
 template <typename T>
 hipError_t fluid_solve(mb_grid* g, const T* v_in, const T* f, T* v_out,
-                       hipStream_t s) {
+                       hipStream_t s, bool boxed) {
     switch (g->L) {
 #define MB_CASE(n) \
-    case n: return fft::solve_sized<T, n>(g, v_in, f, v_out, s);
+    case n: return fft::solve_sized<T, n>(g, v_in, f, boxed, v_out, s);
         MB_FFT_SIZES(MB_CASE)
 #undef MB_CASE
     }
@@ -465,7 +485,7 @@ int fft_x_blocks(int L, int precision) {
     return 0;
 }
 
-template hipError_t fluid_solve<float>(mb_grid*, const float*, const float*, float*, hipStream_t);
-template hipError_t fluid_solve<double>(mb_grid*, const double*, const double*, double*, hipStream_t);
+template hipError_t fluid_solve<float>(mb_grid*, const float*, const float*, float*, hipStream_t, bool);
+template hipError_t fluid_solve<double>(mb_grid*, const double*, const double*, double*, hipStream_t, bool);
 
 }  // namespace mb

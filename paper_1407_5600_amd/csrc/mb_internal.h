@@ -29,6 +29,7 @@ enum KernelId : int {
     K_INTERP_STEP,
     K_U0,
     K_DIAG,
+    K_FOLD,
     K_NUM
 };
 
@@ -99,8 +100,9 @@ struct mb_grid {
     void* d_rec;        // [max_blobs] records
     size_t rec_size;
     mb::Tiles tiles;
-    void* d_fmax;          // float bits: max |F h^-3| of the last scatter
-    void* d_f;             // [3][L][L][L] force density of the step
+    void* d_fmax;          // [0] float bits of max |F h^-3| of the last scatter,
+                           // [1] largest bin count of the last binning
+    void* d_box;           // [3][tiles][box nodes] spread boxes of the step
     double* d_u;           // [max_blobs][3] blob velocities of the last step
     double* d_tile_part;   // [tiles][4]  (sum v_a, max |Dv|)
     double* d_force_part;  // [force blocks][3]
@@ -144,11 +146,18 @@ hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
 hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
                          const double* Fext, double* F, hipStream_t s,
                          mb_grid* timing_grid);
+// Spreading into the per-tile boxes (g->d_box), and the field from them.
 template <typename T>
-hipError_t spread(mb_grid* g, T* f, hipStream_t s);
+hipError_t spread_boxes(mb_grid* g, hipStream_t s);
+template <typename T>
+hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s);
+// Fluid solve; the force is f, or the boxes of the last spreading when
+// boxed is set (f unused).
 template <typename T>
 hipError_t fluid_solve(mb_grid* g, const T* v_in, const T* f, T* v_out,
-                       hipStream_t s);
+                       hipStream_t s, bool boxed = false);
+// Elements of the box array: 3 components x tiles x (tx+3)(ty+3)(tz+3).
+size_t box_elems(const Tiles& t);
 template <typename T>
 hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
                        double* q_update, int diag, hipStream_t s);

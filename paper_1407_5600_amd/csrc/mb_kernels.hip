@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "mb_box.h"
 #include "mb_device.h"
 #include "mb_internal.h"
 
@@ -83,9 +84,14 @@ __device__ __forceinline__ uint32_t cell_pack(const Geom& g) {
 __global__ void __launch_bounds__(BLK)
 k_bin_count(const double* __restrict__ q, int64_t M, double h, int L,
             int* __restrict__ count, int* __restrict__ rank,
-            unsigned int* __restrict__ fmax) {
+            unsigned int* __restrict__ stats) {
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    if (i == 0) *fmax = 0u;  // max |F h^-3| of this step, set by the scatter
+    // stats[0]: max |F h^-3| of this step (float bits), set by the scatter;
+    // stats[1]: largest bin count, set by the scan
+    if (i == 0) {
+        stats[0] = 0u;
+        stats[1] = 0u;
+    }
     if (i >= M) return;
     const Geom g = blob_geom(q, i, h, L);
     rank[i] = atomicAdd(&count[bin_linear(g, L)], 1);
@@ -96,18 +102,27 @@ constexpr int SCAN_TILE = BLK * SCAN_ITEMS;  // 4096
 
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
 
-// Per-block sums of the counts.
+// Per-block sums of the counts; the largest count is folded into *cmax.
 __global__ void __launch_bounds__(BLK)
-k_scan_reduce(const int* __restrict__ count, int64_t n, int* __restrict__ bsum) {
+k_scan_reduce(const int* __restrict__ count, int64_t n, int* __restrict__ bsum,
+              unsigned int* __restrict__ cmax) {
     __shared__ double red[16];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    int s = 0;
+    int s = 0, m = 0;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         const int64_t i = base + k * BLK + threadIdx.x;
-        if (i < n) s += count[i];
+        if (i < n) {
+            const int c = count[i];
+            s += c;
+            m = c > m ? c : m;
+        }
     }
     const double tot = block_reduce<false>((double)s, red);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = (int)tot;
+    const double mx = block_reduce<true>((double)m, red);
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = (int)tot;
+        atomicMax(cmax, (unsigned int)mx);
+    }
 }
 
 // Exclusive scan of `vals` (n entries) held in LDS tile `s` of SCAN_TILE
@@ -422,146 +437,184 @@ __device__ __forceinline__ int find_segment(const int* seg_pre, int nseg, int k)
     return lo;
 }
 
-// Adds one record's contributions to the in-tile nodes of all three
-// components.  ACC = double: float64 LDS atomics on the float64 path.
-// ACC = unsigned long long (mixed path): each float32 contribution, already
-// scaled by 2^e, is rounded to int32 and added to a 64-bit integer sum.
-template <typename T, typename ACC, int TX, int TY, int TZ>
-__device__ __forceinline__ void spread_record(const Rec<T>& r, const TileBox& tb,
-                                              const int* tdim, int L, int e,
-                                              ACC* acc) {
-    constexpr int TV = TX * TY * TZ;
-    T w[3][2][3];     // per axis, node set (0 cell-centred, 1 shifted), node
-    int rel[3][2][3]; // tile-relative node index, -1 outside the tile
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        kernel_weights<T>(r.tu[b], w[b][0]);
-        kernel_weights<T>(r.ts[b], w[b][1]);
-        const int cb = (int)((r.cell >> (9 * b)) & 511u);
-        const int up = (int)((r.cell >> (27 + b)) & 1u);
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            int r0 = cb + (v == 0 ? up : 0) - 1 - tb.lo[b];
-            if (r0 < 0) r0 += L;
-            if (r0 >= L) r0 -= L;
-#pragma unroll
-            for (int o = 0; o < 3; ++o) {
-                int rr = r0 + o;
-                if (rr >= L) rr -= L;
-                rel[b][v][o] = rr < tdim[b] ? rr : -1;
-            }
-        }
+// Fixed-point scale of a spreading pass.  A node of component a receives
+// contributions only from blobs whose cells lie within [n-2, n+1] along the
+// two cell-centred axes and [n-1, n+1] along axis a: at most 3 x 3 x 2 bins,
+// so at most 18 cmax contributions (cmax = largest bin count), each at most
+// (2/3)^3 fmax.  Returns the largest e with
+//   (16/3) cmax fmax 2^e + 9 cmax (rounding) <= lim_sum   and
+//   (8/27) fmax 2^e <= lim_one (one contribution),
+// with margins for the rounding of the weights and of fmax.
+__device__ __forceinline__ int fixed_exponent(double fmax, int cmax, double lim_sum,
+                                              double lim_one) {
+    if (!(fmax > 0.0) || cmax <= 0) return 0;
+    const double fm = fmax * (1.0 + 0x1p-20);
+    const double avail = lim_sum * (1.0 - 0x1p-20) - 9.0 * cmax - 1.0;
+    const int e_sum = ilogb(avail / ((16.0 / 3.0) * cmax * fm));
+    const int e_one = ilogb(lim_one / ((8.0 / 27.0) * fm));
+    return e_sum < e_one ? e_sum : e_one;
+}
+
+// Spreading: one block per tile, one velocity component at a time.  The
+// tile's own records (those of its cells, bins [lo/2, (lo+T)/2)) add all 27
+// of their contributions to an LDS box of the nodes they can reach, [lo-1,
+// lo+T+1] per axis: the same box the interpolation stages, so no record is
+// read by more than one block and no contribution is masked.  The box is
+// written to the tile's slot of the box array E[a][tile][box node]; a node
+// of the field is the sum of the entries of the (at most 8) boxes holding it
+// (box_sum), formed by the fold kernel or by the first FFT pass as it reads
+// the force.
+//
+// Accumulation is in fixed point with integer LDS atomics, which are much
+// faster on gfx950 than the floating ones (float32 ones by more than an
+// order of magnitude) and make each box independent of the order of the
+// additions.  The scale 2^e (fixed_exponent) comes from the step's largest
+// |F h^-3| and largest bin count, so that no sum can overflow:
+//  - mixed: 32-bit sums of float32 contributions rounded to int32 when
+//    cmax <= 64 (a quantum of 2^-25 to 2^-24 fmax at cmax = 13, the densest
+//    bin of a phi = 0.3 suspension), else 64-bit sums of int32
+//    contributions;
+//  - float64: 64-bit sums of float64 contributions rounded to int64 (a
+//    quantum of at most 2^-50 fmax for cmax <= 455, coarsening slowly
+//    above) when cmax <= 65536, else float64 LDS atomics.
+template <typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(BLK)
+k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
+         Tiles tl, const unsigned int* __restrict__ stats, T* __restrict__ E) {
+    constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
+    constexpr int EV = EX * EY * EZ;
+    constexpr bool F32 = std::is_same<T, float>::value;
+    __shared__ unsigned long long acc[EV];
+    __shared__ int seg_start[(TY / 2) * (TZ / 2)];
+    __shared__ int seg_pre[(TY / 2) * (TZ / 2) + 1];
+    __shared__ int scratch[16];
+    unsigned int* acc32 = reinterpret_cast<unsigned int*>(acc);
+    double* accd = reinterpret_cast<double*>(acc);
+    const TileBox tb = tile_box(tl, L);
+    const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
+    const double fmax = (double)__uint_as_float(stats[0]);
+    const int cmax = (int)stats[1];
+    // mode 0: the fast fixed-point form (u32 for float, u64 for double)
+    int mode, e;
+    if (F32) {
+        mode = cmax <= 64 ? 0 : 1;
+        e = fixed_exponent(fmax, cmax, mode == 0 ? 0x1p31 : 0x1p63, 0x1p30);
+    } else {
+        mode = cmax <= 65536 ? 0 : 1;
+        e = mode == 0 ? fixed_exponent(fmax, cmax, 0x1p63, 0x1p50) : 0;
+    }
+    for (int i = threadIdx.x; i < EV; i += BLK) acc[i] = 0ull;
+    int nseg;
+    const int total = gather_segments(offs, L >> 1, tb.lo[0] >> 1, tl.tx >> 1,
+                                      tb.lo[1] >> 1, tl.ty >> 1, tb.lo[2] >> 1,
+                                      tl.tz >> 1, seg_start, seg_pre, scratch, &nseg);
+    // this thread's first record is kept in registers for all components
+    Rec<T> r0{};
+    if ((int)threadIdx.x < total) {
+        const int s = find_segment(seg_pre, nseg, threadIdx.x);
+        r0 = rec[seg_start[s] + ((int)threadIdx.x - seg_pre[s])];
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int vx = a == 0, vy = a == 1, vz = a == 2;
-        T Fa = r.F[a];
-        if constexpr (!std::is_same<ACC, double>::value) Fa = ldexp(Fa, e);
-        ACC* A = acc + a * TV;
+        for (int k = threadIdx.x; k < total; k += BLK) {
+            Rec<T> r = r0;
+            if (k >= BLK) {
+                const int s = find_segment(seg_pre, nseg, k);
+                r = rec[seg_start[s] + (k - seg_pre[s])];
+            }
+            T w[3][3];
+            int e0[3];  // box index of node i0 - 1
 #pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-            const int rz = rel[2][vz][oz];
-            if (rz < 0) continue;
-            const T wz = w[2][vz][oz] * Fa;
-#pragma unroll
-            for (int oy = 0; oy < 3; ++oy) {
-                const int ry = rel[1][vy][oy];
-                if (ry < 0) continue;
-                const T wyz = w[1][vy][oy] * wz;
-#pragma unroll
-                for (int ox = 0; ox < 3; ++ox) {
-                    const int rx = rel[0][vx][ox];
-                    if (rx < 0) continue;
-                    const T val = w[0][vx][ox] * wyz;
-                    ACC* dst = &A[(rz * TY + ry) * TX + rx];
-                    if constexpr (std::is_same<ACC, double>::value)
-                        atomicAdd(dst, (double)val);
-                    else
-                        atomicAdd(dst, (unsigned long long)(long long)__float2int_rn((float)val));
+            for (int b = 0; b < 3; ++b) {
+                kernel_weights<T>(a == b ? r.ts[b] : r.tu[b], w[b]);
+                const int c = (int)((r.cell >> (9 * b)) & 511u) - tb.lo[b];  // [0, T)
+                const int up = (int)((r.cell >> (27 + b)) & 1u);
+                e0[b] = a == b ? c : c + up;
+            }
+            const int base = (e0[2] * EY + e0[1]) * EX + e0[0];
+            const T Fa = ldexp(r.F[a], e);
+            // the 27 node offsets from base are compile-time constants
+#define MB_SPREAD_27(ADD)                                                    \
+    _Pragma("unroll") for (int oz = 0; oz < 3; ++oz) {                       \
+        const T wz = w[2][oz] * Fa;                                          \
+        _Pragma("unroll") for (int oy = 0; oy < 3; ++oy) {                   \
+            const T wyz = w[1][oy] * wz;                                     \
+            _Pragma("unroll") for (int ox = 0; ox < 3; ++ox)                 \
+                ADD(base + (oz * EY + oy) * EX + ox, w[0][ox] * wyz);        \
+        }                                                                    \
+    }
+            if (F32) {
+                if (mode == 0) {
+#define MB_ADD(i, v) atomicAdd(&acc32[i], (unsigned int)__float2int_rn((float)(v)))
+                    MB_SPREAD_27(MB_ADD)
+#undef MB_ADD
+                } else {
+#define MB_ADD(i, v) \
+    atomicAdd(&acc[i], (unsigned long long)(long long)__float2int_rn((float)(v)))
+                    MB_SPREAD_27(MB_ADD)
+#undef MB_ADD
+                }
+            } else {
+                if (mode == 0) {
+                    // round to the nearest integer (|v| <= 2^50): adding
+                    // 1.5 * 2^52 leaves it in the low bits of the sum
+#define MB_ADD(i, v)                                                               \
+    atomicAdd(&acc[i], (unsigned long long)(__double_as_longlong((double)(v) + 0x1.8p52) - \
+                                            __double_as_longlong(0x1.8p52)))
+                    MB_SPREAD_27(MB_ADD)
+#undef MB_ADD
+                } else {
+#define MB_ADD(i, v) atomicAdd(&accd[i], (double)(v))
+                    MB_SPREAD_27(MB_ADD)
+#undef MB_ADD
                 }
             }
+#undef MB_SPREAD_27
         }
+        __syncthreads();
+        // write the box and clear it for the next component
+        T* Ea = E + ((size_t)a * tl.n + tile) * EV;
+        for (int i = threadIdx.x; i < EV; i += BLK) {
+            T val;
+            if (F32 && mode == 0) {
+                val = ldexpf((float)(int)acc32[i], -e);
+                acc32[i] = 0u;
+            } else if (F32 || mode == 0) {
+                val = (T)ldexp((double)(long long)acc[i], -e);
+                acc[i] = 0ull;
+            } else {
+                val = (T)accd[i];
+                acc[i] = 0ull;
+            }
+            Ea[i] = val;
+        }
+        __syncthreads();
     }
 }
 
-// Spreading: one block per tile; every record whose 3x3x3 support may reach
-// the tile (cells [lo-2, hi+1]) is expanded and its in-tile nodes are added
-// to an LDS copy of the tile, which is then written out once.
-//
-// Accumulation: float64 LDS atomics on the float64 path.  On the mixed path
-// the float LDS atomic add of gfx950 is an order of magnitude slower than
-// the integer one, so the float32 contributions are accumulated as fixed
-// point: with fmax the largest |F h^-3| of the step and 2^e the power of two
-// with fmax 2^e < 2^30, each contribution w F 2^e is rounded to int32 (a
-// quantum of at most 2^-29 fmax) and summed in 64-bit integers, which can
-// not overflow and do not depend on the order of the additions.
-template <typename T, typename ACC, int TX, int TY, int TZ>
+// The field from the boxes (the spreading call of the library).
+template <typename T>
 __global__ void __launch_bounds__(BLK)
-k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
-         Tiles tl, const float* __restrict__ fmax, T* __restrict__ f) {
-    constexpr int TV = TX * TY * TZ;
-    constexpr bool FIXED = !std::is_same<ACC, double>::value;
-    __shared__ ACC acc[3 * TV];
-    __shared__ int seg_start[2 * (TY / 2 + 2) * (TZ / 2 + 2)];
-    __shared__ int seg_pre[2 * (TY / 2 + 2) * (TZ / 2 + 2) + 1];
-    __shared__ int scratch[16];
-    const TileBox tb = tile_box(tl, L);
-    const int tdim[3] = {tl.tx, tl.ty, tl.tz};
-    for (int i = threadIdx.x; i < 3 * TV; i += BLK) acc[i] = ACC(0);
-    int e = 0;
-    if (FIXED) {
-        const float fm = *fmax;
-        if (fm > 0.f) {
-            int ex;
-            (void)frexpf(fm, &ex);  // fm < 2^ex
-            e = 30 - ex;
-        }
-    }
-    // bins (2x2x2 cells) covering the cells [lo-2, hi+1] that can reach the
-    // tile: bins [lo/2 - 1, (lo+T)/2] per axis (one spare cell layer above)
-    int nseg;
-    const int Lb = L >> 1;
-    const int ext[3] = {tb.full[0] ? Lb : tl.tx / 2 + 2, tb.full[1] ? Lb : tl.ty / 2 + 2,
-                        tb.full[2] ? Lb : tl.tz / 2 + 2};
-    const int elo[3] = {tb.full[0] ? 0 : tb.lo[0] / 2 - 1, tb.full[1] ? 0 : tb.lo[1] / 2 - 1,
-                        tb.full[2] ? 0 : tb.lo[2] / 2 - 1};
-    const int total = gather_segments(offs, Lb, elo[0], ext[0], elo[1], ext[1],
-                                      elo[2], ext[2], seg_start, seg_pre,
-                                      scratch, &nseg);
-    // Records are bin-sorted, so consecutive records hit the same nodes.
-    // Lane l of a wave takes record l * span + j instead of 64 j + l: a
-    // wave's atomics then land far apart in the tile (fewer same-address and
-    // same-bank collisions).
-    const int span = (total + WAVE - 1) / WAVE;
-    for (int it = threadIdx.x; it < span * WAVE; it += BLK) {
-        const int k = (it % WAVE) * span + it / WAVE;
-        if (k >= total) continue;
-        const int s = find_segment(seg_pre, nseg, k);
-        const Rec<T> r = rec[seg_start[s] + (k - seg_pre[s])];
-        spread_record<T, ACC, TX, TY, TZ>(r, tb, tdim, L, e, acc);
-    }
-    __syncthreads();
+k_fold(const T* __restrict__ E, int L, Tiles tl, T* __restrict__ f) {
     const int64_t N = (int64_t)L * L * L;
-    for (int i = threadIdx.x; i < 3 * TV; i += BLK) {
-        const int a = i / TV;
-        const int rem = i - a * TV;
-        const int x = rem % TX;
-        const int y = (rem / TX) % TY;
-        const int z = rem / (TX * TY);
-        T val;
-        if constexpr (FIXED)
-            val = (T)ldexp((double)(long long)acc[i], -e);
-        else
-            val = (T)acc[i];
-        f[a * N + ((int64_t)(tb.lo[2] + z) * L + tb.lo[1] + y) * L + tb.lo[0] + x] = val;
-    }
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i >= 3 * N) return;
+    const int a = (int)(i / N);
+    const int64_t rem = i - a * N;
+    const int x = (int)(rem % L);
+    const int y = (int)((rem / L) % L);
+    const int z = (int)(rem / ((int64_t)L * L));
+    f[i] = box_sum(E, tl, a, x, y, z);
 }
 
-// Interpolation: one block per tile; the field on nodes [lo-1, hi+2] of all
-// three components is staged in LDS, then every record of the tile's cells
-// gathers its 27 nodes per component.  With q_update the blob is moved by
-// dt*u; with diag the block also writes its float64 sum of each component
-// and the max |Dv| over its cells.
+// Interpolation: one block per tile, one velocity component at a time.  The
+// component on nodes [lo-1, hi+2] is staged in LDS (rows located through a
+// table of wrapped row offsets), then every record of the tile's cells
+// gathers its 27 nodes; u (and the move of the blob by dt u) is written
+// once per blob for each thread's first record, per component for the rest
+// (tiles with more records than threads).  With
+// part the block also writes its float64 sum of each component and the max
+// |Dv| over its cells.
 template <typename T, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
 k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
@@ -570,97 +623,118 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
          double inv_h, double* __restrict__ part) {
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
     constexpr int EV = EX * EY * EZ;
-    __shared__ T vt[3 * EV];
+    constexpr int TV = TX * TY * TZ;
+    constexpr int RP = BLK / EX;             // rows staged per pass
+    constexpr int CPT = (TV + BLK - 1) / BLK; // own cells per thread
+    __shared__ T vt[EV];
+    __shared__ int rowoff[EY * EZ];
     __shared__ int seg_start[(TY / 2) * (TZ / 2)];
     __shared__ int seg_pre[(TY / 2) * (TZ / 2) + 1];
     __shared__ int scratch[16];
     __shared__ double red[16];
     const TileBox tb = tile_box(tl, L);
     const int N = L * L * L;  // 3 L^3 < 2^31 for L <= 512
+    for (int r = threadIdx.x; r < EY * EZ; r += BLK) {
+        const int ey = r % EY, ez = r / EY;
+        rowoff[r] = (wrapL(tb.lo[2] - 1 + ez, L) * L + wrapL(tb.lo[1] - 1 + ey, L)) * L;
+    }
     // the tile's own cells are exactly the bins [lo/2, (lo+T)/2)
     int nseg;
     const int total = gather_segments(offs, L >> 1, tb.lo[0] >> 1, tl.tx >> 1,
                                       tb.lo[1] >> 1, tl.ty >> 1, tb.lo[2] >> 1,
                                       tl.tz >> 1, seg_start, seg_pre, scratch, &nseg);
-    for (int i = threadIdx.x; i < 3 * EV; i += BLK) {
-        const int a = i / EV;
-        const int rem = i - a * EV;
-        const int ex = rem % EX;
-        const int ey = (rem / EX) % EY;
-        const int ez = rem / (EX * EY);
-        const int x = wrapL(tb.lo[0] - 1 + ex, L);
-        const int y = wrapL(tb.lo[1] - 1 + ey, L);
-        const int z = wrapL(tb.lo[2] - 1 + ez, L);
-        vt[i] = v[a * N + (z * L + y) * L + x];
+    const int sx = threadIdx.x % EX;  // staging: x slot and first row
+    const int sr = threadIdx.x / EX;
+    const int gx = wrapL(tb.lo[0] - 1 + sx, L);
+    // sorted position of this thread's first record
+    int pos0 = -1;
+    if ((int)threadIdx.x < total) {
+        const int s = find_segment(seg_pre, nseg, threadIdx.x);
+        pos0 = seg_start[s] + ((int)threadIdx.x - seg_pre[s]);
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < total; k += BLK) {
-        const int s = find_segment(seg_pre, nseg, k);
-        const int pos = seg_start[s] + (k - seg_pre[s]);
-        const Rec<T> r = rec[pos];
-        const int c[3] = {(int)(r.cell & 511u), (int)((r.cell >> 9) & 511u),
-                          (int)((r.cell >> 18) & 511u)};
-        T w[3][2][3];
-        int e0[3][2];  // extended-tile index of node i0 - 1
+    double u0[3] = {0.0, 0.0, 0.0};  // velocity of the first record
+    double sv[3] = {0.0, 0.0, 0.0};
+    double dv[CPT];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            kernel_weights<T>(r.tu[b], w[b][0]);
-            kernel_weights<T>(r.ts[b], w[b][1]);
-            const int up = (r.cell >> (27 + b)) & 1u;
-            const int rc = c[b] - tb.lo[b];  // in [0, T)
-            e0[b][0] = rc + up;              // (i0 - 1) - (lo - 1)
-            e0[b][1] = rc;
+    for (int j = 0; j < CPT; ++j) dv[j] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a > 0) __syncthreads();  // the previous component's gathers are done
+        if (sr < RP) {
+            const T* va = v + (int64_t)a * N + gx;
+            for (int r = sr; r < EY * EZ; r += RP) vt[r * EX + sx] = va[rowoff[r]];
         }
-        double u[3];
+        __syncthreads();
+        for (int k = threadIdx.x; k < total; k += BLK) {
+            int pos = pos0;
+            if (k >= BLK) {
+                const int s = find_segment(seg_pre, nseg, k);
+                pos = seg_start[s] + (k - seg_pre[s]);
+            }
+            const Rec<T> r = rec[pos];
+            T w[3][3];
+            int e0[3];  // extended-tile index of node i0 - 1
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int vx = a == 0, vy = a == 1, vz = a == 2;
-            const T* V = vt + a * EV;
+            for (int b = 0; b < 3; ++b) {
+                kernel_weights<T>(a == b ? r.ts[b] : r.tu[b], w[b]);
+                const int c = (int)((r.cell >> (9 * b)) & 511u) - tb.lo[b];  // [0, T)
+                const int up = (int)((r.cell >> (27 + b)) & 1u);
+                e0[b] = a == b ? c : c + up;
+            }
+            const T* base = vt + (e0[2] * EY + e0[1]) * EX + e0[0];
             T acc = T(0);
 #pragma unroll
             for (int oz = 0; oz < 3; ++oz) {
-                const int z = e0[2][vz] + oz;
 #pragma unroll
                 for (int oy = 0; oy < 3; ++oy) {
-                    const int y = e0[1][vy] + oy;
-                    const T wyz = w[2][vz][oz] * w[1][vy][oy];
-                    const T* row = V + (z * EY + y) * EX + e0[0][vx];
-                    T sx = w[0][vx][0] * row[0] + w[0][vx][1] * row[1] + w[0][vx][2] * row[2];
-                    acc += wyz * sx;
+                    const T* row = base + (oz * EY + oy) * EX;
+                    const T sxv = w[0][0] * row[0] + w[0][1] * row[1] + w[0][2] * row[2];
+                    acc += (w[2][oz] * w[1][oy]) * sxv;
                 }
             }
-            u[a] = (double)acc;
+            const double ua = (double)acc;
+            if (k < BLK) {
+                u0[a] = ua;  // written with the other components at the end
+            } else {
+                const int64_t i = perm[pos];
+                if (u_out) u_out[3 * i + a] = ua;
+                if (q) q[3 * i + a] += dt * ua;
+            }
         }
-        const int64_t i = perm[pos];
+        if (part) {
+            const int str = a == 0 ? 1 : (a == 1 ? EX : EX * EY);
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int i = threadIdx.x + j * BLK;
+                if (i < TV) {
+                    const int x = i % TX + 1;
+                    const int y = (i / TX) % TY + 1;
+                    const int z = i / (TX * TY) + 1;
+                    const int c0 = (z * EY + y) * EX + x;
+                    const T val = vt[c0];
+                    sv[a] += (double)val;
+                    dv[j] += (double)(val - vt[c0 - str]);
+                }
+            }
+        }
+    }
+    if (pos0 >= 0) {
+        const int64_t i = perm[pos0];
         if (u_out) {
-            u_out[3 * i] = u[0];
-            u_out[3 * i + 1] = u[1];
-            u_out[3 * i + 2] = u[2];
+            u_out[3 * i] = u0[0];
+            u_out[3 * i + 1] = u0[1];
+            u_out[3 * i + 2] = u0[2];
         }
         if (q) {
-            q[3 * i] += dt * u[0];
-            q[3 * i + 1] += dt * u[1];
-            q[3 * i + 2] += dt * u[2];
+            q[3 * i] += dt * u0[0];
+            q[3 * i + 1] += dt * u0[1];
+            q[3 * i + 2] += dt * u0[2];
         }
     }
     if (part) {
-        double sv[3] = {0.0, 0.0, 0.0};
         double dmax = 0.0;
-        const int TV = TX * TY * TZ;
-        for (int i = threadIdx.x; i < TV; i += BLK) {
-            const int x = i % TX + 1;
-            const int y = (i / TX) % TY + 1;
-            const int z = i / (TX * TY) + 1;
-            const int c0 = (z * EY + y) * EX + x;
-            const T vxc = vt[c0], vyc = vt[EV + c0], vzc = vt[2 * EV + c0];
-            sv[0] += (double)vxc;
-            sv[1] += (double)vyc;
-            sv[2] += (double)vzc;
-            const double dv = ((double)(vxc - vt[c0 - 1]) +
-                               (double)(vyc - vt[EV + c0 - EX]) +
-                               (double)(vzc - vt[2 * EV + c0 - EX * EY])) * inv_h;
-            dmax = fmax(dmax, fabs(dv));
-        }
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) dmax = fmax(dmax, fabs(dv[j]) * inv_h);
         const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
         for (int a = 0; a < 3; ++a) {
             const double s = block_reduce<false>(sv[a], red);
@@ -718,7 +792,7 @@ hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
         MB_LAUNCH(g, K_BIN_COUNT, s, k_bin_count, blocks_for(M), BLK, 0, q, M,
                   g->d.h, g->L, g->d_count, g->d_rank, (unsigned int*)g->d_fmax);
     MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
-              g->nbins, g->d_bsum);
+              g->nbins, g->d_bsum, (unsigned int*)g->d_fmax + 1);
     MB_LAUNCH(g, K_SCAN_APPLY, s, k_scan_apply, g->nscan, BLK, 0, g->d_count,
               g->nbins, g->d_bsum, g->d_offs);
     return hipGetLastError();
@@ -768,21 +842,26 @@ size_t springs_lds(const SpringsDev& sp) {
 }
 
 template <typename T, int TX>
-static void launch_spread(mb_grid* g, T* f, hipStream_t s) {
-    using ACC = typename std::conditional<std::is_same<T, float>::value,
-                                          unsigned long long, double>::type;
-    MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, ACC, TX, 8, 8>), g->tiles.n, BLK, 0,
+static void launch_spread(mb_grid* g, hipStream_t s) {
+    MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, TX, 8, 8>), g->tiles.n, BLK, 0,
               (const Rec<T>*)g->d_rec, g->d_offs, g->L, g->tiles,
-              (const float*)g->d_fmax, f);
+              (const unsigned int*)g->d_fmax, (T*)g->d_box);
 }
 
 template <typename T>
-hipError_t spread(mb_grid* g, T* f, hipStream_t s) {
+hipError_t spread_boxes(mb_grid* g, hipStream_t s) {
     switch (g->tiles.tx) {
-        case 32: launch_spread<T, 32>(g, f, s); break;
-        case 16: launch_spread<T, 16>(g, f, s); break;
-        default: launch_spread<T, 8>(g, f, s); break;
+        case 32: launch_spread<T, 32>(g, s); break;
+        case 16: launch_spread<T, 16>(g, s); break;
+        default: launch_spread<T, 8>(g, s); break;
     }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s) {
+    MB_LAUNCH(g, K_FOLD, s, k_fold<T>, blocks_for(3 * g->N), BLK, 0,
+              (const T*)g->d_box, g->L, g->tiles, f);
     return hipGetLastError();
 }
 
@@ -832,10 +911,16 @@ template hipError_t scatter_records<float>(mb_grid*, int64_t, const double*, con
 template hipError_t scatter_records<double>(mb_grid*, int64_t, const double*, const double*, hipStream_t);
 template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t);
 template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t);
-template hipError_t spread<float>(mb_grid*, float*, hipStream_t);
-template hipError_t spread<double>(mb_grid*, double*, hipStream_t);
+template hipError_t spread_boxes<float>(mb_grid*, hipStream_t);
+template hipError_t spread_boxes<double>(mb_grid*, hipStream_t);
+template hipError_t fold_boxes<float>(mb_grid*, float*, hipStream_t);
+template hipError_t fold_boxes<double>(mb_grid*, double*, hipStream_t);
 template hipError_t interpolate<float>(mb_grid*, int64_t, const float*, double*, double*, int, hipStream_t);
 template hipError_t interpolate<double>(mb_grid*, int64_t, const double*, double*, double*, int, hipStream_t);
+
+size_t box_elems(const Tiles& t) {
+    return (size_t)3 * t.n * (t.tx + 3) * (t.ty + 3) * (t.tz + 3);
+}
 
 size_t record_size(int precision) {
     return precision == MB_MIXED ? sizeof(Rec<float>) : sizeof(Rec<double>);

@@ -302,15 +302,39 @@ def test_step_dense_full_size(torch_cuda, prec):
     _step_case(torch, w, prec, 1)
 
 
-def test_repeat_runs_agree(torch_cuda):
-    """LDS float atomics may add in a different order on each run; two runs
-    agree to rounding."""
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_spread_independent_of_blob_order(torch_cuda, prec):
+    """Spreading sums in fixed point, so the field does not depend on the
+    order of the blobs (nor of the atomic additions): a permuted input gives
+    the same bits, and so does a repeated call."""
     torch = torch_cuda
-    say("repeat")
+    say("spread order", prec)
     L, M = 32, 3000
     q = blobs(1, M, L, "uniform")
     F = np.random.default_rng(2).standard_normal((M, 3))
-    g = grid(L, "fp64", M)
+    perm = np.random.default_rng(3).permutation(M)
+    g = grid(L, prec, M)
     a = g.spread(dev(torch, q), dev(torch, F)).cpu().numpy()
-    b = g.spread(dev(torch, q), dev(torch, F)).cpu().numpy()
-    assert rel(a, b) < 1e-14
+    b = g.spread(dev(torch, q[perm]), dev(torch, F[perm])).cpu().numpy()
+    c = g.spread(dev(torch, q), dev(torch, F)).cpu().numpy()
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+    check(f"spread order {prec}", a, oracle.spread(oracle.params(L), q, F), prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_spread_crowded_bin(torch_cuda, prec):
+    """More blobs in one 2x2x2 bin than the fast fixed-point forms are sized
+    for (70,000: float64 falls back to float64 LDS atomics, mixed to 64-bit
+    integer sums), next to a bin of ordinary density."""
+    torch = torch_cuda
+    say("spread crowded bin", prec)
+    L, M = 16, 70000
+    rng = np.random.default_rng(9)
+    q = 4.0 + rng.uniform(0.0, 2.0, size=(M, 3))
+    q[:10] = rng.uniform(0, L, size=(10, 3))
+    F = rng.standard_normal((M, 3))
+    g = grid(L, prec, M)
+    f = g.spread(dev(torch, q), dev(torch, F))
+    torch.cuda.synchronize()
+    ref = oracle.spread(oracle.params(L), q, F)
+    check(f"spread crowded {prec}", f.double().cpu().numpy(), ref, prec)
