@@ -41,10 +41,11 @@ def algorithmic_bytes(L, M, P, prec, steady=False):
     N = L ** 3
     field = 3 * N * s
     spec = 3 * L * L * (L // 2 + 1) * 2 * s
+    ntiles = (L // 16 if L % 16 == 0 else L // 8) * (L // 8) ** 2  # 16x8x8 tiles
     return {
-        "bin_count": 24 * M + 4 * M + 8 * M,
-        "scan_reduce": 4 * (N // 8),          # one count per 2x2x2 bin
-        "scan_apply": 12 * (N // 8),
+        "bin_count": 24 * M + 4 * M + 4 * M + 4 * M,  # q, previous order, tile, rank
+        "scan_reduce": 4 * ntiles,
+        "scan_apply": 12 * ntiles,
         "springs_scatter": 24 * M + 24 * P + 12 * M + rec * M,
         "spread": rec * M + field,
         "fft_x_fwd": (1 if steady else 2) * field + spec,

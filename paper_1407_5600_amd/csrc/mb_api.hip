@@ -82,7 +82,7 @@ void free_grid(mb_grid* g) {
     void* ptrs[] = {g->d_tw,    g->d_dsym,  g->d_d2,   g->d_spec,
                     g->d_psum,  g->d_count, g->d_offs, g->d_bsum,
                     g->d_rank,  g->d_perm,  g->d_rec,  g->d_tile_part,
-                    g->d_force_part, g->d_box, g->d_u, g->d_fmax};
+                    g->d_force_part, g->d_box, g->d_u, g->d_tile};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& tp : g->pending) {
@@ -217,8 +217,8 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     g->rec_size = record_size(d.precision);
     // springs blocks hold at least one particle of at least one blob
     g->force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
-    g->nbins = g->N / 8;
-    g->nscan = (int)((g->nbins + 4095) / 4096);
+    g->nscan = (t.n + 4095) / 4096;
+    g->perm_m = -1;
 
     const size_t cbytes = 2 * g->fsz;
     hipError_t e = hipSuccess;
@@ -230,9 +230,10 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     alloc(&g->d_d2, (size_t)L * g->fsz);
     alloc(&g->d_spec, (size_t)3 * L * L * g->NC * cbytes);
     alloc((void**)&g->d_psum, (size_t)g->nblk_x * 2 * sizeof(double));
-    alloc((void**)&g->d_count, (size_t)g->nbins * sizeof(int));
-    alloc((void**)&g->d_offs, (size_t)(g->nbins + 1) * sizeof(int));
+    alloc((void**)&g->d_count, (size_t)t.n * sizeof(int));
+    alloc((void**)&g->d_offs, (size_t)(t.n + 1) * sizeof(int));
     alloc((void**)&g->d_bsum, (size_t)g->nscan * sizeof(int));
+    alloc((void**)&g->d_tile, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc((void**)&g->d_rank, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc((void**)&g->d_perm, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc(&g->d_rec, (size_t)std::max<int64_t>(d.max_blobs, 1) * g->rec_size);
@@ -240,9 +241,7 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     alloc(&g->d_box, box_elems(t) * g->fsz);
     alloc((void**)&g->d_u, (size_t)std::max<int64_t>(d.max_blobs, 1) * 3 * sizeof(double));
     alloc((void**)&g->d_force_part, (size_t)g->force_blocks_cap * 3 * sizeof(double));
-    alloc(&g->d_fmax, 256);
-    if (e == hipSuccess) e = hipMemset(g->d_fmax, 0, 256);
-    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)g->nbins * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)t.n * sizeof(int));
     if (e == hipSuccess) e = hipMemset(g->d_force_part, 0, (size_t)g->force_blocks_cap * 3 * sizeof(double));
     if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)t.n * 4 * sizeof(double));
     if (e == hipSuccess) {

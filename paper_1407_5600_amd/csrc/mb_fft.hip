@@ -198,7 +198,15 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
         for (int hh = 0; hh < 2; ++hh) {
             const int y = y0 + 2 * line + hh;
             const int idx = cbase + (z * L + y) * L + x;
-            const T fv = BOX ? box_sum(Ec, bx, box_src_y(tl, y), bz) : f[idx];
+            T fv;
+            if constexpr (BOX) {
+                // a wave's lanes share y when L is a multiple of the wave
+                constexpr bool UNI = L % WAVE == 0 && NTHR % L == 0;
+                const int yu = UNI ? __builtin_amdgcn_readfirstlane(y) : y;
+                fv = box_sum<UNI>(Ec, bx, box_src_y(tl, yu), bz);
+            } else {
+                fv = f[idx];
+            }
             sf += (double)fv;
             if (STEADY) {
                 val[hh] = fv;

@@ -89,19 +89,18 @@ struct mb_grid {
     void* d_spec;       // [3][L(z)][NC(kx)][L(ky)] cplx<T>
     int nblk_x;         // blocks of an x pass
     double* d_psum;     // [nblk_x][2] per-block sums of v and f (float64)
-    // binning
-    int64_t nbins;      // (L/2)^3 bins of 2x2x2 cells
-    int* d_count;       // [nbins] (kept zeroed between uses)
-    int* d_offs;        // [nbins + 1]
+    // binning (by tile)
+    int* d_count;       // [tiles] (kept zeroed between uses)
+    int* d_offs;        // [tiles + 1]
     int* d_bsum;        // scan block sums
     int nscan;          // scan blocks
-    int* d_rank;        // [max_blobs]
-    int* d_perm;        // [max_blobs]
+    int* d_tile;        // [max_blobs] tile of each blob
+    int* d_rank;        // [max_blobs] place among its tile's blobs
+    int* d_perm;        // [max_blobs] blob of each sorted record
+    int64_t perm_m;     // d_perm is a permutation of [0, perm_m) (-1: none)
     void* d_rec;        // [max_blobs] records
     size_t rec_size;
     mb::Tiles tiles;
-    void* d_fmax;          // [0] float bits of max |F h^-3| of the last scatter,
-                           // [1] largest bin count of the last binning
     void* d_box;           // [3][tiles][box nodes] spread boxes of the step
     double* d_u;           // [max_blobs][3] blob velocities of the last step
     double* d_tile_part;   // [tiles][4]  (sum v_a, max |Dv|)

@@ -66,11 +66,11 @@ __device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
     return g;
 }
 
-// Bin of a blob: blobs are sorted by 2x2x2 groups of cells ("bins"),
-// (L/2)^3 of them, x fastest.
-__device__ __forceinline__ int bin_linear(const Geom& g, int L) {
-    const int Lb = L >> 1;
-    return ((g.c[2] >> 1) * Lb + (g.c[1] >> 1)) * Lb + (g.c[0] >> 1);
+// Tile of a cell: blobs are sorted by the tiles of spreading and
+// interpolation (extents powers of two), tile index x fastest.
+__device__ __forceinline__ int tile_linear(const int c[3], const Tiles& tl) {
+    return ((c[2] >> (__ffs(tl.tz) - 1)) * tl.nty + (c[1] >> (__ffs(tl.ty) - 1))) * tl.ntx +
+           (c[0] >> (__ffs(tl.tx) - 1));
 }
 
 __device__ __forceinline__ uint32_t cell_pack(const Geom& g) {
@@ -80,21 +80,47 @@ __device__ __forceinline__ uint32_t cell_pack(const Geom& g) {
 }
 
 // ---------------------------------------------------------------------------
-// Binning: counting sort of blobs by cell.
+// Binning: counting sort of blobs by tile.  Blobs are taken in `order` (the
+// sorted order of the previous binning when it covered the same blobs, so
+// that a block's blobs fall in a few consecutive tiles; the identity
+// otherwise): a block counts its blobs of tiles [t0, t0 + 64) in LDS (t0 the
+// tile of its first blob) and adds each such count to the global count with
+// one atomic; other blobs take a global atomic each.  rank is the blob's
+// place among its tile's blobs, in no particular order.
+constexpr int TILE_WIN = 64;
+
 __global__ void __launch_bounds__(BLK)
-k_bin_count(const double* __restrict__ q, int64_t M, double h, int L,
-            int* __restrict__ count, int* __restrict__ rank,
-            unsigned int* __restrict__ stats) {
-    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    // stats[0]: max |F h^-3| of this step (float bits), set by the scatter;
-    // stats[1]: largest bin count, set by the scan
-    if (i == 0) {
-        stats[0] = 0u;
-        stats[1] = 0u;
+k_tile_count(const double* __restrict__ q, const int* __restrict__ order,
+             int64_t M, double h, int L, Tiles tl, int* __restrict__ count,
+             int* __restrict__ tile_of, int* __restrict__ rank) {
+    __shared__ int lcount[TILE_WIN];
+    __shared__ int lbase[TILE_WIN];
+    __shared__ int t0s;
+    const int64_t j = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (threadIdx.x < TILE_WIN) lcount[threadIdx.x] = 0;
+    int64_t i = -1;
+    int t = 0;
+    if (j < M) {
+        i = order ? order[j] : j;
+        const Geom g = blob_geom(q, i, h, L);
+        t = tile_linear(g.c, tl);
     }
-    if (i >= M) return;
-    const Geom g = blob_geom(q, i, h, L);
-    rank[i] = atomicAdd(&count[bin_linear(g, L)], 1);
+    if (threadIdx.x == 0) t0s = t;  // block 0's first blob exists (M > 0)
+    __syncthreads();
+    const int k = t - t0s;
+    const bool local = i >= 0 && k >= 0 && k < TILE_WIN;
+    int r = 0;
+    if (local) r = atomicAdd(&lcount[k], 1);
+    else if (i >= 0) r = atomicAdd(&count[t], 1);
+    __syncthreads();
+    if (threadIdx.x < TILE_WIN) {
+        const int c = lcount[threadIdx.x];
+        lbase[threadIdx.x] = c > 0 ? atomicAdd(&count[t0s + threadIdx.x], c) : 0;
+    }
+    __syncthreads();
+    if (i < 0) return;
+    tile_of[i] = t;
+    rank[i] = local ? lbase[k] + r : r;
 }
 
 constexpr int SCAN_ITEMS = 16;
@@ -102,27 +128,18 @@ constexpr int SCAN_TILE = BLK * SCAN_ITEMS;  // 4096
 
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
 
-// Per-block sums of the counts; the largest count is folded into *cmax.
+// Per-block sums of the counts.
 __global__ void __launch_bounds__(BLK)
-k_scan_reduce(const int* __restrict__ count, int64_t n, int* __restrict__ bsum,
-              unsigned int* __restrict__ cmax) {
+k_scan_reduce(const int* __restrict__ count, int64_t n, int* __restrict__ bsum) {
     __shared__ double red[16];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    int s = 0, m = 0;
+    int s = 0;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         const int64_t i = base + k * BLK + threadIdx.x;
-        if (i < n) {
-            const int c = count[i];
-            s += c;
-            m = c > m ? c : m;
-        }
+        if (i < n) s += count[i];
     }
     const double tot = block_reduce<false>((double)s, red);
-    const double mx = block_reduce<true>((double)m, red);
-    if (threadIdx.x == 0) {
-        bsum[blockIdx.x] = (int)tot;
-        atomicMax(cmax, (unsigned int)mx);
-    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (int)tot;
 }
 
 // Exclusive scan of `vals` (n entries) held in LDS tile `s` of SCAN_TILE
@@ -172,60 +189,44 @@ k_scan_apply(int* __restrict__ count, int64_t n, const int* __restrict__ bsum,
     if (base + SCAN_TILE >= n && threadIdx.x == 0) offs[n] = off + total;
 }
 
-// Writes the record and returns the largest |F h^-3| it stores (as float).
+// Writes the record of blob i at sorted position pos.
 template <typename T>
-__device__ __forceinline__ float write_record(Rec<T>* __restrict__ rec,
-                                              int* __restrict__ perm,
-                                              int64_t pos, int64_t i,
-                                              const Geom& g, const double F[3],
-                                              double inv_vol) {
+__device__ __forceinline__ void write_record(Rec<T>* __restrict__ rec,
+                                             int* __restrict__ perm, int64_t pos,
+                                             int64_t i, const Geom& g,
+                                             const double F[3], double inv_vol) {
     Rec<T> r;
-    float m = 0.f;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         r.tu[b] = (T)g.tu[b];
         r.ts[b] = (T)g.ts[b];
         r.F[b] = (T)(F[b] * inv_vol);
-        m = fmaxf(m, fabsf((float)r.F[b]));
     }
     r.cell = cell_pack(g);
     r.pad = 0;
     rec[pos] = r;
     perm[pos] = (int)i;
-    return m;
 }
 
-// Block maximum of non-negative floats folded into *fmax (bit patterns of
-// non-negative floats order like the values).
-__device__ __forceinline__ void fold_fmax(float m, double* red,
-                                          unsigned int* __restrict__ fmax) {
-    const double bm = block_reduce<true>((double)m, red);
-    if (threadIdx.x == 0) atomicMax(fmax, __float_as_uint((float)bm));
-}
-
-// Records in cell order for given forces (F may be null: interpolation).
+// Records in tile order for given forces (F may be null: interpolation).
 template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
               int64_t M, double h, int L, double inv_vol,
-              const int* __restrict__ offs, const int* __restrict__ rank,
-              Rec<T>* __restrict__ rec, int* __restrict__ perm,
-              unsigned int* __restrict__ fmax) {
-    __shared__ double red[16];
+              const int* __restrict__ offs, const int* __restrict__ tile_of,
+              const int* __restrict__ rank, Rec<T>* __restrict__ rec,
+              int* __restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    float m = 0.f;
-    if (i < M) {
-        const Geom g = blob_geom(q, i, h, L);
-        double f[3] = {0.0, 0.0, 0.0};
-        if (F) {
-            f[0] = F[3 * i];
-            f[1] = F[3 * i + 1];
-            f[2] = F[3 * i + 2];
-        }
-        const int64_t pos = (int64_t)offs[bin_linear(g, L)] + rank[i];
-        m = write_record<T>(rec, perm, pos, i, g, f, inv_vol);
+    if (i >= M) return;
+    const Geom g = blob_geom(q, i, h, L);
+    double f[3] = {0.0, 0.0, 0.0};
+    if (F) {
+        f[0] = F[3 * i];
+        f[1] = F[3 * i + 1];
+        f[2] = F[3 * i + 2];
     }
-    fold_fmax(m, red, fmax);
+    const int64_t pos = (int64_t)offs[tile_of[i]] + rank[i];
+    write_record<T>(rec, perm, pos, i, g, f, inv_vol);
 }
 
 // Spring forces of the sp.ppb particles of this block (float64).  Their
@@ -306,27 +307,25 @@ __device__ __forceinline__ int springs_block(const SpringsDev& sp,
 }
 
 // Spring forces fused with the scatter of the records; also the per-block
-// float64 sums of the blob forces (momentum diagnostics) and max |F h^-3|.
+// float64 sums of the blob forces (momentum diagnostics).
 template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
                   const double* __restrict__ Fext, int64_t P, double h, int L,
                   double inv_vol, const int* __restrict__ offs,
-                  const int* __restrict__ rank, Rec<T>* __restrict__ rec,
-                  int* __restrict__ perm, double* __restrict__ fpart,
-                  unsigned int* __restrict__ fmax) {
+                  const int* __restrict__ tile_of, const int* __restrict__ rank,
+                  Rec<T>* __restrict__ rec, int* __restrict__ perm,
+                  double* __restrict__ fpart) {
     extern __shared__ double smem[];
     __shared__ double red[16];
     double F[3];
     int64_t i;
     springs_block(sp, q, Fext, P, smem, F, &i);
-    float m = 0.f;
     if (i >= 0) {
         const Geom g = blob_geom(q, i, h, L);
-        const int64_t pos = (int64_t)offs[bin_linear(g, L)] + rank[i];
-        m = write_record<T>(rec, perm, pos, i, g, F, inv_vol);
+        const int64_t pos = (int64_t)offs[tile_of[i]] + rank[i];
+        write_record<T>(rec, perm, pos, i, g, F, inv_vol);
     }
-    fold_fmax(m, red, fmax);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double s = block_reduce<false>(F[c], red);
@@ -377,151 +376,86 @@ __device__ __forceinline__ int wrapL(int v, int L) {
     return v;
 }
 
-// Contiguous ranges of sorted records for the cells of a box of rows.
-// Rows y in [ylo, ylo + ny), z in [zlo, zlo + nz) (wrapped), x cells
-// [xlo, xlo + nx) (wrapped, split in at most two runs).  Fills seg_start /
-// seg_pre (exclusive prefix of lengths) and returns the record count.
-__device__ int gather_segments(const int* __restrict__ offs, int L, int xlo,
-                               int nx, int ylo, int ny, int zlo, int nz,
-                               int* seg_start, int* seg_pre, int* scratch,
-                               int* nseg_out) {
-    // x runs
-    int xs0 = wrapL(xlo, L), xe0, xs1 = 0, xe1 = -1, nxs = 1;
-    if (nx >= L) {
-        xs0 = 0;
-        xe0 = L - 1;
-    } else if (xs0 + nx - 1 < L) {
-        xe0 = xs0 + nx - 1;
-    } else {
-        xe0 = L - 1;
-        xs1 = 0;
-        xe1 = xs0 + nx - 1 - L;
-        nxs = 2;
-    }
-    const int nseg = ny * nz * nxs;
-    // one segment per thread per pass; nseg <= blockDim.x * passes
-    int carry = 0;
-    for (int base = 0; base < nseg; base += blockDim.x) {
-        const int s = base + threadIdx.x;
-        int len = 0;
-        if (s < nseg) {
-            const int xi = s % nxs;
-            const int r = s / nxs;
-            const int y = wrapL(ylo + r % ny, L);
-            const int z = wrapL(zlo + r / ny, L);
-            const int row = (z * L + y) * L;
-            const int a = row + (xi ? xs1 : xs0);
-            const int e = row + (xi ? xe1 : xe0);
-            const int st = offs[a];
-            len = offs[e + 1] - st;
-            seg_start[s] = st;
-        }
-        int total;
-        const int ex = block_exclusive_scan(len, scratch, &total);
-        if (s < nseg) seg_pre[s] = carry + ex;
-        carry += total;
-    }
-    if (threadIdx.x == 0) seg_pre[nseg] = carry;
-    __syncthreads();
-    *nseg_out = nseg;
-    return carry;
-}
-
-__device__ __forceinline__ int find_segment(const int* seg_pre, int nseg, int k) {
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (seg_pre[mid] <= k) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Fixed-point scale of a spreading pass.  A node of component a receives
-// contributions only from blobs whose cells lie within [n-2, n+1] along the
-// two cell-centred axes and [n-1, n+1] along axis a: at most 3 x 3 x 2 bins,
-// so at most 18 cmax contributions (cmax = largest bin count), each at most
-// (2/3)^3 fmax.  Returns the largest e with
-//   (16/3) cmax fmax 2^e + 9 cmax (rounding) <= lim_sum   and
+// Fixed-point scale of one tile's box.  A box node receives at most one
+// contribution per component from each of the tile's n records, each at
+// most (2/3)^3 fmax (fmax = the tile's largest |F h^-3|).  Returns the
+// largest e with
+//   n (8/27) fmax 2^e + n (rounding) <= lim_sum   and
 //   (8/27) fmax 2^e <= lim_one (one contribution),
 // with margins for the rounding of the weights and of fmax.
-__device__ __forceinline__ int fixed_exponent(double fmax, int cmax, double lim_sum,
+__device__ __forceinline__ int fixed_exponent(double fmax, int n, double lim_sum,
                                               double lim_one) {
-    if (!(fmax > 0.0) || cmax <= 0) return 0;
-    const double fm = fmax * (1.0 + 0x1p-20);
-    const double avail = lim_sum * (1.0 - 0x1p-20) - 9.0 * cmax - 1.0;
-    const int e_sum = ilogb(avail / ((16.0 / 3.0) * cmax * fm));
-    const int e_one = ilogb(lim_one / ((8.0 / 27.0) * fm));
+    if (!(fmax > 0.0) || n <= 0) return 0;
+    const double fm = fmax * (1.0 + 0x1p-20) * (8.0 / 27.0);
+    const double avail = lim_sum * (1.0 - 0x1p-20) - n - 1.0;
+    const int e_sum = ilogb(avail / (n * fm));
+    const int e_one = ilogb(lim_one / fm);
     return e_sum < e_one ? e_sum : e_one;
 }
 
 // Spreading: one block per tile, one velocity component at a time.  The
-// tile's own records (those of its cells, bins [lo/2, (lo+T)/2)) add all 27
-// of their contributions to an LDS box of the nodes they can reach, [lo-1,
-// lo+T+1] per axis: the same box the interpolation stages, so no record is
-// read by more than one block and no contribution is masked.  The box is
-// written to the tile's slot of the box array E[a][tile][box node]; a node
-// of the field is the sum of the entries of the (at most 8) boxes holding it
-// (box_sum), formed by the fold kernel or by the first FFT pass as it reads
-// the force.
+// tile's own records (those of its cells) add all 27 of their contributions
+// to an LDS box of the nodes they can reach, [lo-1, lo+T+1] per axis: the
+// same box the interpolation stages, so no record is read by more than one
+// block and no contribution is masked.  The box is written to the tile's
+// slot of the box array E[a][tile][box node]; a node of the field is the sum
+// of the entries of the (at most 8) boxes holding it (box_sum), formed by
+// the fold kernel or by the first FFT pass as it reads the force.
 //
 // Accumulation is in fixed point with integer LDS atomics, which are much
 // faster on gfx950 than the floating ones (float32 ones by more than an
 // order of magnitude) and make each box independent of the order of the
-// additions.  The scale 2^e (fixed_exponent) comes from the step's largest
-// |F h^-3| and largest bin count, so that no sum can overflow:
+// additions.  The scale 2^e (fixed_exponent) comes from the tile's record
+// count n and largest |F h^-3|, so that no sum can overflow:
 //  - mixed: 32-bit sums of float32 contributions rounded to int32 when
-//    cmax <= 64 (a quantum of 2^-25 to 2^-24 fmax at cmax = 13, the densest
-//    bin of a phi = 0.3 suspension), else 64-bit sums of int32
+//    n <= 2048 (a quantum of about 2^-23 fmax at the ~230 records of a
+//    16x8x8 tile of a phi = 0.3 suspension), else 64-bit sums of int32
 //    contributions;
 //  - float64: 64-bit sums of float64 contributions rounded to int64 (a
-//    quantum of at most 2^-50 fmax for cmax <= 455, coarsening slowly
-//    above) when cmax <= 65536, else float64 LDS atomics.
+//    quantum of at most 2^-50 fmax for n < 27000, coarsening slowly above)
+//    when n <= 2^20, else float64 LDS atomics.
 template <typename T, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
 k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
-         Tiles tl, const unsigned int* __restrict__ stats, T* __restrict__ E) {
+         Tiles tl, T* __restrict__ E) {
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
     constexpr int EV = EX * EY * EZ;
     constexpr bool F32 = std::is_same<T, float>::value;
     __shared__ unsigned long long acc[EV];
-    __shared__ int seg_start[(TY / 2) * (TZ / 2)];
-    __shared__ int seg_pre[(TY / 2) * (TZ / 2) + 1];
-    __shared__ int scratch[16];
+    __shared__ double red[16];
     unsigned int* acc32 = reinterpret_cast<unsigned int*>(acc);
     double* accd = reinterpret_cast<double*>(acc);
     const TileBox tb = tile_box(tl, L);
     const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
-    const double fmax = (double)__uint_as_float(stats[0]);
-    const int cmax = (int)stats[1];
+    for (int i = threadIdx.x; i < EV; i += BLK) acc[i] = 0ull;
+    const int first = offs[tile];
+    const int total = offs[tile + 1] - first;
+    const Rec<T>* trec = rec + first;
+    // this thread's first record is kept in registers for all components
+    Rec<T> r0{};
+    if ((int)threadIdx.x < total) r0 = trec[threadIdx.x];
+    double fm = 0.0;
+    for (int k = threadIdx.x; k < total; k += BLK) {
+        Rec<T> r = r0;
+        if (k >= BLK) r = trec[k];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) fm = fmax(fm, fabs((double)r.F[b]));
+    }
+    const double fmx = block_reduce<true>(fm, red);
     // mode 0: the fast fixed-point form (u32 for float, u64 for double)
     int mode, e;
     if (F32) {
-        mode = cmax <= 64 ? 0 : 1;
-        e = fixed_exponent(fmax, cmax, mode == 0 ? 0x1p31 : 0x1p63, 0x1p30);
+        mode = total <= 2048 ? 0 : 1;
+        e = fixed_exponent(fmx, total, mode == 0 ? 0x1p31 : 0x1p63, 0x1p30);
     } else {
-        mode = cmax <= 65536 ? 0 : 1;
-        e = mode == 0 ? fixed_exponent(fmax, cmax, 0x1p63, 0x1p50) : 0;
-    }
-    for (int i = threadIdx.x; i < EV; i += BLK) acc[i] = 0ull;
-    int nseg;
-    const int total = gather_segments(offs, L >> 1, tb.lo[0] >> 1, tl.tx >> 1,
-                                      tb.lo[1] >> 1, tl.ty >> 1, tb.lo[2] >> 1,
-                                      tl.tz >> 1, seg_start, seg_pre, scratch, &nseg);
-    // this thread's first record is kept in registers for all components
-    Rec<T> r0{};
-    if ((int)threadIdx.x < total) {
-        const int s = find_segment(seg_pre, nseg, threadIdx.x);
-        r0 = rec[seg_start[s] + ((int)threadIdx.x - seg_pre[s])];
+        mode = total <= (1 << 20) ? 0 : 1;
+        e = mode == 0 ? fixed_exponent(fmx, total, 0x1p63, 0x1p50) : 0;
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         for (int k = threadIdx.x; k < total; k += BLK) {
             Rec<T> r = r0;
-            if (k >= BLK) {
-                const int s = find_segment(seg_pre, nseg, k);
-                r = rec[seg_start[s] + (k - seg_pre[s])];
-            }
+            if (k >= BLK) r = trec[k];
             T w[3][3];
             int e0[3];  // box index of node i0 - 1
 #pragma unroll
@@ -628,30 +562,22 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     constexpr int CPT = (TV + BLK - 1) / BLK; // own cells per thread
     __shared__ T vt[EV];
     __shared__ int rowoff[EY * EZ];
-    __shared__ int seg_start[(TY / 2) * (TZ / 2)];
-    __shared__ int seg_pre[(TY / 2) * (TZ / 2) + 1];
-    __shared__ int scratch[16];
     __shared__ double red[16];
     const TileBox tb = tile_box(tl, L);
+    const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
     const int N = L * L * L;  // 3 L^3 < 2^31 for L <= 512
     for (int r = threadIdx.x; r < EY * EZ; r += BLK) {
         const int ey = r % EY, ez = r / EY;
         rowoff[r] = (wrapL(tb.lo[2] - 1 + ez, L) * L + wrapL(tb.lo[1] - 1 + ey, L)) * L;
     }
-    // the tile's own cells are exactly the bins [lo/2, (lo+T)/2)
-    int nseg;
-    const int total = gather_segments(offs, L >> 1, tb.lo[0] >> 1, tl.tx >> 1,
-                                      tb.lo[1] >> 1, tl.ty >> 1, tb.lo[2] >> 1,
-                                      tl.tz >> 1, seg_start, seg_pre, scratch, &nseg);
+    // the tile's own records
+    const int first = offs[tile];
+    const int total = offs[tile + 1] - first;
     const int sx = threadIdx.x % EX;  // staging: x slot and first row
     const int sr = threadIdx.x / EX;
     const int gx = wrapL(tb.lo[0] - 1 + sx, L);
-    // sorted position of this thread's first record
-    int pos0 = -1;
-    if ((int)threadIdx.x < total) {
-        const int s = find_segment(seg_pre, nseg, threadIdx.x);
-        pos0 = seg_start[s] + ((int)threadIdx.x - seg_pre[s]);
-    }
+    const int pos0 = (int)threadIdx.x < total ? first + (int)threadIdx.x : -1;
+    __syncthreads();  // rowoff
     double u0[3] = {0.0, 0.0, 0.0};  // velocity of the first record
     double sv[3] = {0.0, 0.0, 0.0};
     double dv[CPT];
@@ -666,11 +592,7 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
         }
         __syncthreads();
         for (int k = threadIdx.x; k < total; k += BLK) {
-            int pos = pos0;
-            if (k >= BLK) {
-                const int s = find_segment(seg_pre, nseg, k);
-                pos = seg_start[s] + (k - seg_pre[s]);
-            }
+            const int pos = first + k;
             const Rec<T> r = rec[pos];
             T w[3][3];
             int e0[3];  // extended-tile index of node i0 - 1
@@ -735,7 +657,6 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
         double dmax = 0.0;
 #pragma unroll
         for (int j = 0; j < CPT; ++j) dmax = fmax(dmax, fabs(dv[j]) * inv_h);
-        const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
         for (int a = 0; a < 3; ++a) {
             const double s = block_reduce<false>(sv[a], red);
             if (threadIdx.x == 0) part[4 * tile + a] = s;
@@ -788,13 +709,18 @@ static inline unsigned blocks_for(int64_t n) {
 
 template <typename T>
 hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
-    if (M > 0)
-        MB_LAUNCH(g, K_BIN_COUNT, s, k_bin_count, blocks_for(M), BLK, 0, q, M,
-                  g->d.h, g->L, g->d_count, g->d_rank, (unsigned int*)g->d_fmax);
-    MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
-              g->nbins, g->d_bsum, (unsigned int*)g->d_fmax + 1);
+    const int nt = g->tiles.n;
+    if (M > 0) {
+        // the previous sorted order, when it is a permutation of these blobs
+        const int* order = g->perm_m == M ? g->d_perm : nullptr;
+        MB_LAUNCH(g, K_BIN_COUNT, s, k_tile_count, blocks_for(M), BLK, 0, q, order, M,
+                  g->d.h, g->L, g->tiles, g->d_count, g->d_tile, g->d_rank);
+    }
+    if (g->nscan > 1)
+        MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
+                  (int64_t)nt, g->d_bsum);
     MB_LAUNCH(g, K_SCAN_APPLY, s, k_scan_apply, g->nscan, BLK, 0, g->d_count,
-              g->nbins, g->d_bsum, g->d_offs);
+              (int64_t)nt, g->d_bsum, g->d_offs);
     return hipGetLastError();
 }
 
@@ -804,8 +730,9 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
     if (M == 0) return hipSuccess;
     const double h = g->d.h;
     MB_LAUNCH(g, K_BIN_SCATTER, s, k_bin_scatter<T>, blocks_for(M), BLK, 0, q, F,
-              M, h, g->L, 1.0 / (h * h * h), g->d_offs, g->d_rank,
-              (Rec<T>*)g->d_rec, g->d_perm, (unsigned int*)g->d_fmax);
+              M, h, g->L, 1.0 / (h * h * h), g->d_offs, g->d_tile, g->d_rank,
+              (Rec<T>*)g->d_rec, g->d_perm);
+    g->perm_m = M;
     return hipGetLastError();
 }
 
@@ -817,8 +744,8 @@ hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
     const double h = g->d.h;
     MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, springs_blocks(sp, P), BLK,
               springs_lds(sp), sp, q, Fext, P, h, g->L, 1.0 / (h * h * h), g->d_offs,
-              g->d_rank, (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part,
-              (unsigned int*)g->d_fmax);
+              g->d_tile, g->d_rank, (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part);
+    g->perm_m = M;
     return hipGetLastError();
 }
 
@@ -844,8 +771,7 @@ size_t springs_lds(const SpringsDev& sp) {
 template <typename T, int TX>
 static void launch_spread(mb_grid* g, hipStream_t s) {
     MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, TX, 8, 8>), g->tiles.n, BLK, 0,
-              (const Rec<T>*)g->d_rec, g->d_offs, g->L, g->tiles,
-              (const unsigned int*)g->d_fmax, (T*)g->d_box);
+              (const Rec<T>*)g->d_rec, g->d_offs, g->L, g->tiles, (T*)g->d_box);
 }
 
 template <typename T>

@@ -321,14 +321,15 @@ def test_spread_independent_of_blob_order(torch_cuda, prec):
     check(f"spread order {prec}", a, oracle.spread(oracle.params(L), q, F), prec)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_spread_crowded_bin(torch_cuda, prec):
-    """More blobs in one 2x2x2 bin than the fast fixed-point forms are sized
-    for (70,000: float64 falls back to float64 LDS atomics, mixed to 64-bit
-    integer sums), next to a bin of ordinary density."""
+@pytest.mark.parametrize("prec,M", [("mixed", 70000), ("fp64", 70000), ("fp64", 1100000)])
+def test_spread_crowded_tile(torch_cuda, prec, M):
+    """More records in one tile than the fast fixed-point forms are sized
+    for: mixed falls back to 64-bit integer sums above 2048 records, float64
+    coarsens its quantum above ~27,000 and falls back to float64 LDS atomics
+    above 2^20; next to tiles of ordinary density."""
     torch = torch_cuda
-    say("spread crowded bin", prec)
-    L, M = 16, 70000
+    say("spread crowded tile", prec, M)
+    L = 8 if M > 100000 else 16
     rng = np.random.default_rng(9)
     q = 4.0 + rng.uniform(0.0, 2.0, size=(M, 3))
     q[:10] = rng.uniform(0, L, size=(10, 3))
@@ -337,4 +338,4 @@ def test_spread_crowded_bin(torch_cuda, prec):
     f = g.spread(dev(torch, q), dev(torch, F))
     torch.cuda.synchronize()
     ref = oracle.spread(oracle.params(L), q, F)
-    check(f"spread crowded {prec}", f.double().cpu().numpy(), ref, prec)
+    check(f"spread crowded {prec} M={M}", f.double().cpu().numpy(), ref, prec)
