@@ -191,39 +191,50 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
         const int e = tid + kk * NTHR;
         const int line = e / L;
         const int x = e - line * L;
-        AxisSrc bx{};
-        if (BOX) bx = box_src_x(tl, x);
-        T val[2];
+        const int xm = x == 0 ? L - 1 : x - 1, xp = x == L - 1 ? 0 : x + 1;
+        // the loads of both rows are issued before any arithmetic
+        T vc[2], vn[2][6], fv[2];
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             const int y = y0 + 2 * line + hh;
-            const int idx = cbase + (z * L + y) * L + x;
-            T fv;
-            if constexpr (BOX) {
-                // a wave's lanes share y when L is a multiple of the wave
-                constexpr bool UNI = L % WAVE == 0 && NTHR % L == 0;
-                const int yu = UNI ? __builtin_amdgcn_readfirstlane(y) : y;
-                fv = box_sum<UNI>(Ec, bx, box_src_y(tl, yu), bz);
-            } else {
-                fv = f[idx];
-            }
-            sf += (double)fv;
-            if (STEADY) {
-                val[hh] = fv;
-            } else {
-                const T vc = v[idx];
-                sv += (double)vc;
-                const int xm = x == 0 ? L - 1 : x - 1, xp = x == L - 1 ? 0 : x + 1;
+            const int row = cbase + (z * L + y) * L;
+            if (!BOX) fv[hh] = f[row + x];
+            if (!STEADY) {
                 const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-                const int row = cbase + (z * L + y) * L;
-                const T lap = (v[row + xm] + v[row + xp]) +
-                              (v[cbase + (z * L + ym) * L + x] + v[cbase + (z * L + yp) * L + x]) +
-                              (v[cbase + (zm * L + y) * L + x] + v[cbase + (zp * L + y) * L + x]) -
-                              T(6) * vc;
-                val[hh] = a * vc + b * lap + fv;
+                vc[hh] = v[row + x];
+                vn[hh][0] = v[row + xm];
+                vn[hh][1] = v[row + xp];
+                vn[hh][2] = v[cbase + (z * L + ym) * L + x];
+                vn[hh][3] = v[cbase + (z * L + yp) * L + x];
+                vn[hh][4] = v[cbase + (zm * L + y) * L + x];
+                vn[hh][5] = v[cbase + (zp * L + y) * L + x];
             }
         }
-    buf[line * LS + x] = cplx<T>{val[0], val[1]};
+        if constexpr (BOX) {
+            // a wave's lanes share y when L is a multiple of the wave
+            constexpr bool UNI = L % WAVE == 0 && NTHR % L == 0;
+            const AxisSrc bx = box_src_x(tl, x);
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int y = y0 + 2 * line + hh;
+                const int yu = UNI ? __builtin_amdgcn_readfirstlane(y) : y;
+                fv[hh] = box_sum<UNI>(Ec, bx, box_src_y(tl, yu), bz);
+            }
+        }
+        T val[2];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            sf += (double)fv[hh];
+            if (STEADY) {
+                val[hh] = fv[hh];
+            } else {
+                sv += (double)vc[hh];
+                const T lap = (vn[hh][0] + vn[hh][1]) + (vn[hh][2] + vn[hh][3]) +
+                              (vn[hh][4] + vn[hh][5]) - T(6) * vc[hh];
+                val[hh] = a * vc[hh] + b * lap + fv[hh];
+            }
+        }
+        buf[line * LS + x] = cplx<T>{val[0], val[1]};
     }
     __syncthreads();
     line_fft<T, L, false, NL, LS, NTHR>(buf, tws, tid);
@@ -267,12 +278,21 @@ k_y(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw) {
     const int wc = NC - kx0 < W ? NC - kx0 : W;
     cplx<T>* base = A + ((size_t)cz * NC + kx0) * L;
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
+    // all loads first (a short last chunk re-reads its first row), then the
+    // LDS stores, so that the loads overlap
+    cplx<T> ld[EPT];
+#pragma unroll
+    for (int kk = 0; kk < EPT; ++kk) {
+        const int e = tid + kk * NTHR;
+        const int w = e / L;
+        ld[kk] = base[w < wc ? e : e - w * L];
+    }
 #pragma unroll
     for (int kk = 0; kk < EPT; ++kk) {
         const int e = tid + kk * NTHR;
         const int w = e / L;
         const int y = e - w * L;
-        if (w < wc) buf[w * LS + y] = base[e];
+        if (w < wc) buf[w * LS + y] = ld[kk];
     }
     __syncthreads();
     line_fft<T, L, INV, W, LS, NTHR>(buf, tws, tid);
@@ -311,13 +331,27 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     const int kx = blockIdx.x / (L / W);
     const int ky0 = ch * W;
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
-    // load: e -> (c, z, w), w fastest (contiguous ky segments)
-    for (int e = tid; e < 3 * L * W; e += NTHR) {
-        const int w = e % W;
-        const int cz = e / W;
-        const int c = cz / L;
-        const int z = cz - c * L;
-        buf[(c * W + w) * LS + z] = A[((size_t)cz * NC + kx) * L + ky0 + w];
+    // load: e -> (c, z, w), w fastest (contiguous ky segments); 3 L W =
+    // EPT NTHR elements, all loads issued before the LDS stores
+    static_assert(3 * L * W == EPT * NTHR, "z pass geometry");
+    {
+        cplx<T> ld[EPT];
+#pragma unroll
+        for (int kk = 0; kk < EPT; ++kk) {
+            const int e = tid + kk * NTHR;
+            const int w = e % W;
+            const int cz = e / W;
+            ld[kk] = A[((size_t)cz * NC + kx) * L + ky0 + w];
+        }
+#pragma unroll
+        for (int kk = 0; kk < EPT; ++kk) {
+            const int e = tid + kk * NTHR;
+            const int w = e % W;
+            const int cz = e / W;
+            const int c = cz / L;
+            const int z = cz - c * L;
+            buf[(c * W + w) * LS + z] = ld[kk];
+        }
     }
     if (kx == 0 && ch == 0) {
         constexpr int per_c = G::NBX / 3;
@@ -362,7 +396,9 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     }
     __syncthreads();
     line_fft<T, L, true, NLN, LS, NTHR>(buf, tws, tid);
-    for (int e = tid; e < 3 * L * W; e += NTHR) {
+#pragma unroll
+    for (int kk = 0; kk < EPT; ++kk) {
+        const int e = tid + kk * NTHR;
         const int w = e % W;
         const int cz = e / W;
         const int c = cz / L;
@@ -391,12 +427,28 @@ k_x_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     const int y0 = yb * R;
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
     const cplx<T>* in = A + (size_t)cz * NC * L + y0;
-    for (int e = tid; e < NC * R; e += NTHR) {
-        const int kx = e / R;
-        const int rl = e - kx * R;
-        cplx<T> X = in[kx * L + rl];
-        if (kx == 0 || kx == L / 2) X.y = T(0);
-        stg[rl * SS + kx] = X;
+    {
+        // all loads first (out-of-range slots re-read the first element)
+        constexpr int K = (NC * R + NTHR - 1) / NTHR;
+        cplx<T> ld[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = tid + k * NTHR;
+            const int kx = e / R;
+            const int rl = e - kx * R;
+            ld[k] = in[e < NC * R ? kx * L + rl : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = tid + k * NTHR;
+            if (e < NC * R) {
+                const int kx = e / R;
+                const int rl = e - kx * R;
+                cplx<T> X = ld[k];
+                if (kx == 0 || kx == L / 2) X.y = T(0);
+                stg[rl * SS + kx] = X;
+            }
+        }
     }
     __syncthreads();
 #pragma unroll

@@ -249,10 +249,24 @@ __device__ __forceinline__ int springs_block(const SpringsDev& sp,
     double* r0s = fp + 3 * sp.ppb * np;    // [np]
     int* pab = (int*)(r0s + np);           // [np] packed pair_a | pair_b << 16
     const double* qg = q + 3 * p0 * nb;    // contiguous blobs of the block
-    for (int i = threadIdx.x; i < 3 * nblob; i += BLK) qs[i] = qg[i];
-    for (int e = threadIdx.x; e < np; e += BLK) {
-        r0s[e] = sp.r0[e];
-        pab[e] = sp.pa[e] | (sp.pb[e] << 16);
+    {
+        // the position loads are issued first (a block holds at most BLK
+        // blobs: springs_blocks), then the pair table, then the LDS stores
+        double ld[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int i = threadIdx.x + k * BLK;
+            ld[k] = qg[i < 3 * nblob ? i : 0];
+        }
+        for (int e = threadIdx.x; e < np; e += BLK) {
+            r0s[e] = sp.r0[e];
+            pab[e] = sp.pa[e] | (sp.pb[e] << 16);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int i = threadIdx.x + k * BLK;
+            if (i < 3 * nblob) qs[i] = ld[k];
+        }
     }
     __syncthreads();
     for (int w = threadIdx.x; w < npart * np; w += BLK) {
@@ -577,6 +591,13 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     const int sr = threadIdx.x / EX;
     const int gx = wrapL(tb.lo[0] - 1 + sx, L);
     const int pos0 = (int)threadIdx.x < total ? first + (int)threadIdx.x : -1;
+    // the thread's first record and its blob, loaded once
+    Rec<T> r0{};
+    int64_t i0 = -1;
+    if (pos0 >= 0) {
+        r0 = rec[pos0];
+        i0 = perm[pos0];
+    }
     __syncthreads();  // rowoff
     double u0[3] = {0.0, 0.0, 0.0};  // velocity of the first record
     double sv[3] = {0.0, 0.0, 0.0};
@@ -587,13 +608,26 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     for (int a = 0; a < 3; ++a) {
         if (a > 0) __syncthreads();  // the previous component's gathers are done
         if (sr < RP) {
+            // all loads of the thread first, then the LDS stores
+            constexpr int NR = (EY * EZ + RP - 1) / RP;
             const T* va = v + (int64_t)a * N + gx;
-            for (int r = sr; r < EY * EZ; r += RP) vt[r * EX + sx] = va[rowoff[r]];
+            T ld[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const int r = sr + k * RP;
+                ld[k] = va[rowoff[r < EY * EZ ? r : sr]];
+            }
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const int r = sr + k * RP;
+                if (r < EY * EZ) vt[r * EX + sx] = ld[k];
+            }
         }
         __syncthreads();
         for (int k = threadIdx.x; k < total; k += BLK) {
             const int pos = first + k;
-            const Rec<T> r = rec[pos];
+            Rec<T> r = r0;
+            if (k >= BLK) r = rec[pos];
             T w[3][3];
             int e0[3];  // extended-tile index of node i0 - 1
 #pragma unroll
@@ -641,7 +675,7 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
         }
     }
     if (pos0 >= 0) {
-        const int64_t i = perm[pos0];
+        const int64_t i = i0;
         if (u_out) {
             u_out[3 * i] = u0[0];
             u_out[3 * i + 1] = u0[1];
