@@ -120,12 +120,60 @@ __device__ __forceinline__ void dft3(cplx<T>* v) {
     }
 }
 
+// W_16^m (m = 1, 2, 3, 6, 9) applied to a: forward W = cos(pi m/8) -
+// i sin(pi m/8), inverse its conjugate.
+template <typename T, bool INV, int M>
+__device__ __forceinline__ cplx<T> w16(cplx<T> a) {
+    constexpr double C[10] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                              0.38268343236508977173, 0.0, -0.38268343236508977173,
+                              -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                              -0.92387953251128675613};
+    constexpr double S[10] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                              0.92387953251128675613, 1.0, 0.92387953251128675613,
+                              0.70710678118654752440, 0.38268343236508977173, 0.0,
+                              -0.38268343236508977173};
+    const T c = (T)C[M];
+    const T s = INV ? (T)S[M] : -(T)S[M];  // W = c + i s
+    return cplx<T>{a.x * c - a.y * s, a.x * s + a.y * c};
+}
+
+// 16-point DFT as 4 x 4: DFTs of the four decimated sequences v[4 n1 + n2]
+// (over n1), twiddles W_16^{n2 k1}, then DFTs over n2; output k1 + 4 k2.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cplx<T>* v) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<T, INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // v[4 k1 + n2] now holds Y[n2][k1]
+    v[4 + 1] = w16<T, INV, 1>(v[4 + 1]);
+    v[4 + 2] = w16<T, INV, 2>(v[4 + 2]);
+    v[4 + 3] = w16<T, INV, 3>(v[4 + 3]);
+    v[8 + 1] = w16<T, INV, 2>(v[8 + 1]);
+    v[8 + 2] = mul_mi<T, INV>(v[8 + 2]);  // W_16^4 = -i (forward)
+    v[8 + 3] = w16<T, INV, 6>(v[8 + 3]);
+    v[12 + 1] = w16<T, INV, 3>(v[12 + 1]);
+    v[12 + 2] = w16<T, INV, 6>(v[12 + 2]);
+    v[12 + 3] = w16<T, INV, 9>(v[12 + 3]);
+    cplx<T> o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cplx<T> a0 = v[4 * k1], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+        dft4<T, INV>(a0, a1, a2, a3);
+        o[k1] = a0;
+        o[k1 + 4] = a1;
+        o[k1 + 8] = a2;
+        o[k1 + 12] = a3;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = o[k];
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dftR(cplx<T>* v) {
     if constexpr (R == 2) dft2<T, INV>(v);
     else if constexpr (R == 3) dft3<T, INV>(v);
     else if constexpr (R == 4) dft4v<T, INV>(v);
-    else dft8<T, INV>(v);
+    else if constexpr (R == 8) dft8<T, INV>(v);
+    else dft16<T, INV>(v);
 }
 
 // ---------------------------------------------------------------------------

@@ -30,9 +30,10 @@ namespace fft {
 
 constexpr int EPT = 8;  // elements per thread in a line transform
 
-// Radix plan: 8s, then 4, then 2, then 3s.
+// Radix plan: 16s, then 8, 4, 2, then 3s.
 constexpr int nstages(int n) {
     int s = 0;
+    while (n % 16 == 0) { n /= 16; ++s; }
     while (n % 8 == 0) { n /= 8; ++s; }
     while (n % 4 == 0) { n /= 4; ++s; }
     while (n % 2 == 0) { n /= 2; ++s; }
@@ -41,6 +42,7 @@ constexpr int nstages(int n) {
 }
 constexpr int radix_at(int n, int k) {
     int s = 0;
+    while (n % 16 == 0) { if (s == k) return 16; n /= 16; ++s; }
     while (n % 8 == 0) { if (s == k) return 8; n /= 8; ++s; }
     while (n % 4 == 0) { if (s == k) return 4; n /= 4; ++s; }
     while (n % 2 == 0) { if (s == k) return 2; n /= 2; ++s; }
@@ -53,15 +55,19 @@ constexpr int ns_at(int n, int k) {
     return p;
 }
 
-// One Stockham stage of radix R on NLINES lines of length N held in LDS
-// (element e of line l at buf[l * LS + e]).  Butterfly j of a line reads
-// elements j + r N/R, multiplies input r by W_N^{r (j mod NS) N/(NS R)},
-// applies the R-point DFT and writes output r to (j - j mod NS) R +
-// (j mod NS) + r NS.  All loads of a stage precede a barrier and all stores,
-// so the stage runs in place.  Consecutive threads take consecutive
-// butterflies of a line.
-template <typename T, int N, int R, int NS, bool INV, int NLINES, int LS, int NTHR>
-__device__ __forceinline__ void stage(cplx<T>* buf, const cplx<T>* tw, int tid) {
+// One Stockham stage of radix R on NLINES lines of length N.  Butterfly j
+// of a line reads elements j + r N/R through load(line, element),
+// multiplies input r by W_N^{r (j mod NS) N/(NS R)}, applies the R-point
+// DFT and writes output r to element (j - j mod NS) R + (j mod NS) + r NS
+// through store(line, element, value).  With MIDSYNC (loads and stores on
+// the same LDS lines) a barrier separates all loads from all stores, so the
+// stage runs in place.  Butterflies are spread over the threads with the
+// butterfly index fastest, or the line index fastest with LFAST (lanes then
+// walk across lines: contiguous when lines are adjacent in memory).
+template <typename T, int N, int R, int NS, bool INV, int NLINES, int NTHR, bool LFAST,
+          bool MIDSYNC, typename LD, typename ST>
+__device__ __forceinline__ void stage_io(const cplx<T>* tw, int tid, const LD& load,
+                                         const ST& store) {
     constexpr int NB = N / R;
     constexpr int TOTAL = NB * NLINES;
     constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
@@ -71,13 +77,12 @@ __device__ __forceinline__ void stage(cplx<T>* buf, const cplx<T>* tw, int tid) 
     for (int it = 0; it < MAXB; ++it) {
         const int w = tid + it * NTHR;
         if (TOTAL % NTHR == 0 || w < TOTAL) {
-            const int line = w / NB;
-            const int j = w - line * NB;
-            const cplx<T>* base = buf + line * LS;
+            const int line = LFAST ? w % NLINES : w / NB;
+            const int j = LFAST ? w / NLINES : w - line * NB;
             const int k = j % NS;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                cplx<T> a = base[j + r * NB];
+                cplx<T> a = load(line, j + r * NB);
                 if (NS > 1 && r > 0) {
                     cplx<T> t = tw[r * k * TSTEP];
                     if (INV) t.y = -t.y;
@@ -87,30 +92,67 @@ __device__ __forceinline__ void stage(cplx<T>* buf, const cplx<T>* tw, int tid) 
             }
         }
     }
-    __syncthreads();
+    if (MIDSYNC) __syncthreads();
 #pragma unroll
     for (int it = 0; it < MAXB; ++it) {
         const int w = tid + it * NTHR;
         if (TOTAL % NTHR == 0 || w < TOTAL) {
-            const int line = w / NB;
-            const int j = w - line * NB;
-            cplx<T>* base = buf + line * LS;
+            const int line = LFAST ? w % NLINES : w / NB;
+            const int j = LFAST ? w / NLINES : w - line * NB;
             const int k = j % NS;
             dftR<T, R, INV>(v[it]);
             const int dst = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) base[dst + r * NS] = v[it][r];
+            for (int r = 0; r < R; ++r) store(line, dst + r * NS, v[it][r]);
         }
     }
-    __syncthreads();
 }
 
-template <typename T, int N, bool INV, int NLINES, int LS, int NTHR, int S = 0>
-__device__ __forceinline__ void line_fft(cplx<T>* buf, const cplx<T>* tw, int tid) {
-    if constexpr (S < nstages(N)) {
-        stage<T, N, radix_at(N, S), ns_at(N, S), INV, NLINES, LS, NTHR>(buf, tw, tid);
-        line_fft<T, N, INV, NLINES, LS, NTHR, S + 1>(buf, tw, tid);
+template <typename T, int N, bool INV, int NLINES, int LS, int NTHR, bool LFAST, int S>
+__device__ __forceinline__ void middle_stages(cplx<T>* buf, const cplx<T>* tw, int tid) {
+    if constexpr (S < nstages(N) - 1) {
+        auto ld = [buf](int line, int e) { return buf[line * LS + e]; };
+        auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + e] = x; };
+        stage_io<T, N, radix_at(N, S), ns_at(N, S), INV, NLINES, NTHR, LFAST, true>(tw, tid, ld,
+                                                                                     st);
+        __syncthreads();
+        middle_stages<T, N, INV, NLINES, LS, NTHR, LFAST, S + 1>(buf, tw, tid);
     }
+}
+
+// Transform of NLINES lines of length N: the first stage reads through
+// `load`, the last writes through `store`, the stages in between work in
+// place on the LDS lines buf (element e of line l at buf[l * LS + e]).
+// FIRST_LDS / LAST_LDS: load / store use buf itself (the stage then needs
+// its internal barrier).  A barrier follows every stage but the last; the
+// caller orders what comes before the first and after the last.
+template <typename T, int N, bool INV, int NLINES, int LS, int NTHR, bool LFAST,
+          bool FIRST_LDS, bool LAST_LDS, typename LD, typename ST>
+__device__ __forceinline__ void line_fft_io(cplx<T>* buf, const cplx<T>* tw, int tid,
+                                            const LD& load, const ST& store) {
+    constexpr int S = nstages(N);
+    if constexpr (S == 1) {
+        stage_io<T, N, N, 1, INV, NLINES, NTHR, LFAST, FIRST_LDS && LAST_LDS>(tw, tid, load,
+                                                                           store);
+    } else {
+        auto ld = [buf](int line, int e) { return buf[line * LS + e]; };
+        auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + e] = x; };
+        stage_io<T, N, radix_at(N, 0), 1, INV, NLINES, NTHR, LFAST, FIRST_LDS>(tw, tid, load,
+                                                                            st);
+        __syncthreads();
+        middle_stages<T, N, INV, NLINES, LS, NTHR, LFAST, 1>(buf, tw, tid);
+        stage_io<T, N, radix_at(N, S - 1), ns_at(N, S - 1), INV, NLINES, NTHR, LFAST,
+                 LAST_LDS>(tw, tid, ld, store);
+    }
+}
+
+// In-place transform of LDS lines, ending with a barrier.
+template <typename T, int N, bool INV, int NLINES, int LS, int NTHR>
+__device__ __forceinline__ void line_fft(cplx<T>* buf, const cplx<T>* tw, int tid) {
+    auto ld = [buf](int line, int e) { return buf[line * LS + e]; };
+    auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + e] = x; };
+    line_fft_io<T, N, INV, NLINES, LS, NTHR, false, true, true>(buf, tw, tid, ld, st);
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -278,31 +320,14 @@ k_y(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw) {
     const int wc = NC - kx0 < W ? NC - kx0 : W;
     cplx<T>* base = A + ((size_t)cz * NC + kx0) * L;
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
-    // all loads first (a short last chunk re-reads its first row), then the
-    // LDS stores, so that the loads overlap
-    cplx<T> ld[EPT];
-#pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        const int e = tid + kk * NTHR;
-        const int w = e / L;
-        ld[kk] = base[w < wc ? e : e - w * L];
-    }
-#pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        const int e = tid + kk * NTHR;
-        const int w = e / L;
-        const int y = e - w * L;
-        if (w < wc) buf[w * LS + y] = ld[kk];
-    }
-    __syncthreads();
-    line_fft<T, L, INV, W, LS, NTHR>(buf, tws, tid);
-#pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        const int e = tid + kk * NTHR;
-        const int w = e / L;
-        const int y = e - w * L;
-        if (w < wc) base[e] = buf[w * LS + y];
-    }
+    // first stage straight from A, last stage straight back (a short last
+    // chunk re-reads its first row and stores only its own rows)
+    auto gload = [base, wc](int line, int e) { return base[(line < wc ? line : 0) * L + e]; };
+    auto gstore = [base, wc](int line, int e, cplx<T> x) {
+        if (line < wc) base[line * L + e] = x;
+    };
+    __syncthreads();  // twiddles
+    line_fft_io<T, L, INV, W, LS, NTHR, false, false, false>(buf, tws, tid, gload, gstore);
 }
 
 // z pass fused with the solve: block = (kx, WZ consecutive ky), all three
@@ -331,28 +356,6 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     const int kx = blockIdx.x / (L / W);
     const int ky0 = ch * W;
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
-    // load: e -> (c, z, w), w fastest (contiguous ky segments); 3 L W =
-    // EPT NTHR elements, all loads issued before the LDS stores
-    static_assert(3 * L * W == EPT * NTHR, "z pass geometry");
-    {
-        cplx<T> ld[EPT];
-#pragma unroll
-        for (int kk = 0; kk < EPT; ++kk) {
-            const int e = tid + kk * NTHR;
-            const int w = e % W;
-            const int cz = e / W;
-            ld[kk] = A[((size_t)cz * NC + kx) * L + ky0 + w];
-        }
-#pragma unroll
-        for (int kk = 0; kk < EPT; ++kk) {
-            const int e = tid + kk * NTHR;
-            const int w = e % W;
-            const int cz = e / W;
-            const int c = cz / L;
-            const int z = cz - c * L;
-            buf[(c * W + w) * LS + z] = ld[kk];
-        }
-    }
     if (kx == 0 && ch == 0) {
         constexpr int per_c = G::NBX / 3;
         for (int c = 0; c < 3; ++c) {
@@ -365,8 +368,23 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
             if (tid == 0) mean_new[c] = zero_mean_mode ? 0.0 : s;
         }
     }
+    __syncthreads();  // twiddles, mean mode
+    // line (c, w), w fastest: lanes read contiguous ky segments of A; the
+    // forward transform reads A and leaves the spectrum in LDS, the inverse
+    // reads LDS and writes A
+    auto gload = [A, kx, ky0](int line, int z) {
+        const int c = line / W, w = line - (line / W) * W;
+        return A[((size_t)(c * L + z) * NC + kx) * L + ky0 + w];
+    };
+    auto gstore = [A, kx, ky0](int line, int z, cplx<T> x) {
+        const int c = line / W, w = line - (line / W) * W;
+        A[((size_t)(c * L + z) * NC + kx) * L + ky0 + w] = x;
+    };
+    cplx<T>* lb = buf;
+    auto lload = [lb](int line, int e) { return lb[line * LS + e]; };
+    auto lstore = [lb](int line, int e, cplx<T> x) { lb[line * LS + e] = x; };
+    line_fft_io<T, L, false, NLN, LS, NTHR, true, false, true>(buf, tws, tid, gload, lstore);
     __syncthreads();
-    line_fft<T, L, false, NLN, LS, NTHR>(buf, tws, tid);
     const cplx<T> Dx = dsym[kx];
     const T d2x = d2[kx];
     for (int e = tid; e < L * W; e += NTHR) {
@@ -395,16 +413,7 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
         X[2 * W * LS] = cplx<T>{pz.x * scale, pz.y * scale};
     }
     __syncthreads();
-    line_fft<T, L, true, NLN, LS, NTHR>(buf, tws, tid);
-#pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        const int e = tid + kk * NTHR;
-        const int w = e % W;
-        const int cz = e / W;
-        const int c = cz / L;
-        const int z = cz - c * L;
-        A[((size_t)cz * NC + kx) * L + ky0 + w] = buf[(c * W + w) * LS + z];
-    }
+    line_fft_io<T, L, true, NLN, LS, NTHR, true, true, false>(buf, tws, tid, lload, gstore);
 }
 
 // Inverse x pass: the half spectra of a row pair are staged, combined into
@@ -451,33 +460,27 @@ k_x_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        const int e = tid + kk * NTHR;
-        const int line = e / L;
-        const int k = e - line * L;
+    // first stage: the combined line Z = X_even + i X_odd read from the
+    // staged half spectra; last stage: real and imaginary parts stored as
+    // the two velocity rows
+    const cplx<T>* sg = stg;
+    auto ld = [sg](int line, int k) {
         cplx<T> X1, X2;
         if (k <= L / 2) {
-            X1 = stg[(2 * line) * SS + k];
-            X2 = stg[(2 * line + 1) * SS + k];
+            X1 = sg[(2 * line) * SS + k];
+            X2 = sg[(2 * line + 1) * SS + k];
         } else {
-            X1 = cconj(stg[(2 * line) * SS + (L - k)]);
-            X2 = cconj(stg[(2 * line + 1) * SS + (L - k)]);
+            X1 = cconj(sg[(2 * line) * SS + (L - k)]);
+            X2 = cconj(sg[(2 * line + 1) * SS + (L - k)]);
         }
-        buf[line * LS + k] = cplx<T>{X1.x - X2.y, X1.y + X2.x};
-    }
-    __syncthreads();
-    line_fft<T, L, true, NL, LS, NTHR>(buf, tws, tid);
+        return cplx<T>{X1.x - X2.y, X1.y + X2.x};
+    };
     T* out = vout + ((size_t)cz * L + y0) * L;
-#pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        const int e = tid + kk * NTHR;
-        const int line = e / L;
-        const int x = e - line * L;
-        const cplx<T> zz = buf[line * LS + x];
+    auto st = [out](int line, int x, cplx<T> zz) {
         out[(2 * line) * L + x] = zz.x;
         out[(2 * line + 1) * L + x] = zz.y;
-    }
+    };
+    line_fft_io<T, L, true, NL, LS, NTHR, false, false, false>(buf, tws, tid, ld, st);
 }
 
 template <typename T, int L>
