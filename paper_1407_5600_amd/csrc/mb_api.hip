@@ -317,18 +317,22 @@ mb_status mb_springs_create(int32_t nb, int32_t npairs, const int32_t* pa,
         hpb[e] = pb[e];
         hr0[e] = r0[e];
     }
+    // particles per block: at most 256 blobs; their positions and pair
+    // forces plus the pair and incidence tables in at most 48 KB of LDS
+    // (64 KB for a single particle)
+    const int per_particle = (npairs + nb) * 3 * (int)sizeof(double);
+    const int tables = npairs * (int)(sizeof(double) + sizeof(int)) +
+                       (nb + 1 + 2 * npairs) * (int)sizeof(int);
+    if (tables + per_particle > 64 * 1024) return MB_ERR_UNSUPPORTED;
     mb_springs* sp = new (std::nothrow) mb_springs();
     if (!sp) return MB_ERR_NOMEM;
     sp->nb = nb;
     sp->npairs = npairs;
     sp->k = k;
     sp->device = dev;
-    // particles per block: at most 256 blobs, pair forces + positions in
-    // at most 48 KB of LDS
     {
         const int by_blobs = std::max(1, 256 / nb);
-        const int per_particle = (npairs + nb) * 3 * (int)sizeof(double);
-        const int by_lds = std::max(1, (48 * 1024) / per_particle);
+        const int by_lds = std::max(1, (48 * 1024 - tables) / per_particle);
         sp->ppb = std::min(by_blobs, by_lds);
     }
     hipError_t e = hipSuccess;

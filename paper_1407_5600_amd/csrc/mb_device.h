@@ -209,6 +209,29 @@ __device__ double block_reduce(double v, double* scratch) {
     return r;
 }
 
+// Sums of three doubles over the block, returned to every thread (scratch:
+// 3 * 16 doubles).
+__device__ __forceinline__ void block_reduce3(double v[3], double* scratch) {
+    const int lane = threadIdx.x % WAVE;
+    const int wid = threadIdx.x / WAVE;
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = wave_sum(v[c]);
+    if (lane == 0) {
+        scratch[3 * wid] = v[0];
+        scratch[3 * wid + 1] = v[1];
+        scratch[3 * wid + 2] = v[2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double r = 0.0;
+        for (int i = 0; i < nw; ++i) r += scratch[3 * i + c];
+        v[c] = r;
+    }
+    __syncthreads();
+}
+
 // Exclusive prefix sum of one int per thread over the block; returns the
 // thread's exclusive prefix and writes the block total to *total.
 __device__ __forceinline__ int block_exclusive_scan(int v, int* scratch,

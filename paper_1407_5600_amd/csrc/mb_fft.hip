@@ -30,6 +30,13 @@ namespace fft {
 
 constexpr int EPT = 8;  // elements per thread in a line transform
 
+// LDS position of element e within a line: one spare slot after every 16
+// elements, so that the radix-16 stage's stores (stride 16) and the
+// following stage's loads spread over the banks.
+__device__ __forceinline__ constexpr int lpad(int e) { return e + (e >> 4); }
+// line stride: room for the padded line, odd
+constexpr int line_stride(int L) { return (L + (L - 1) / 16 + 1) | 1; }
+
 // Radix plan: 16s, then 8, 4, 2, then 3s.
 constexpr int nstages(int n) {
     int s = 0;
@@ -111,8 +118,8 @@ __device__ __forceinline__ void stage_io(const cplx<T>* tw, int tid, const LD& l
 template <typename T, int N, bool INV, int NLINES, int LS, int NTHR, bool LFAST, int S>
 __device__ __forceinline__ void middle_stages(cplx<T>* buf, const cplx<T>* tw, int tid) {
     if constexpr (S < nstages(N) - 1) {
-        auto ld = [buf](int line, int e) { return buf[line * LS + e]; };
-        auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + e] = x; };
+        auto ld = [buf](int line, int e) { return buf[line * LS + lpad(e)]; };
+        auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + lpad(e)] = x; };
         stage_io<T, N, radix_at(N, S), ns_at(N, S), INV, NLINES, NTHR, LFAST, true>(tw, tid, ld,
                                                                                      st);
         __syncthreads();
@@ -122,7 +129,7 @@ __device__ __forceinline__ void middle_stages(cplx<T>* buf, const cplx<T>* tw, i
 
 // Transform of NLINES lines of length N: the first stage reads through
 // `load`, the last writes through `store`, the stages in between work in
-// place on the LDS lines buf (element e of line l at buf[l * LS + e]).
+// place on the LDS lines buf (element e of line l at buf[l * LS + lpad(e)]).
 // FIRST_LDS / LAST_LDS: load / store use buf itself (the stage then needs
 // its internal barrier).  A barrier follows every stage but the last; the
 // caller orders what comes before the first and after the last.
@@ -135,8 +142,8 @@ __device__ __forceinline__ void line_fft_io(cplx<T>* buf, const cplx<T>* tw, int
         stage_io<T, N, N, 1, INV, NLINES, NTHR, LFAST, FIRST_LDS && LAST_LDS>(tw, tid, load,
                                                                            store);
     } else {
-        auto ld = [buf](int line, int e) { return buf[line * LS + e]; };
-        auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + e] = x; };
+        auto ld = [buf](int line, int e) { return buf[line * LS + lpad(e)]; };
+        auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + lpad(e)] = x; };
         stage_io<T, N, radix_at(N, 0), 1, INV, NLINES, NTHR, LFAST, FIRST_LDS>(tw, tid, load,
                                                                             st);
         __syncthreads();
@@ -149,8 +156,8 @@ __device__ __forceinline__ void line_fft_io(cplx<T>* buf, const cplx<T>* tw, int
 // In-place transform of LDS lines, ending with a barrier.
 template <typename T, int N, bool INV, int NLINES, int LS, int NTHR>
 __device__ __forceinline__ void line_fft(cplx<T>* buf, const cplx<T>* tw, int tid) {
-    auto ld = [buf](int line, int e) { return buf[line * LS + e]; };
-    auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + e] = x; };
+    auto ld = [buf](int line, int e) { return buf[line * LS + lpad(e)]; };
+    auto st = [buf](int line, int e, cplx<T> x) { buf[line * LS + lpad(e)] = x; };
     line_fft_io<T, N, INV, NLINES, LS, NTHR, false, true, true>(buf, tw, tid, ld, st);
     __syncthreads();
 }
@@ -192,7 +199,7 @@ struct Geo {
     static constexpr int R = rows_x(L);
     static constexpr int NL = R / 2;
     static constexpr int TX = NL * L / EPT;  // threads of an x pass
-    static constexpr int LS = L + 1;         // LDS line stride (complex)
+    static constexpr int LS = line_stride(L); // LDS line stride (complex)
     static constexpr int WY = cols_y<T>(L);
     static constexpr int NCHY = (NC + WY - 1) / WY;
     static constexpr int TY = WY * L / EPT;
@@ -276,7 +283,7 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
                 val[hh] = a * vc[hh] + b * lap + fv[hh];
             }
         }
-        buf[line * LS + x] = cplx<T>{val[0], val[1]};
+        buf[line * LS + lpad(x)] = cplx<T>{val[0], val[1]};
     }
     __syncthreads();
     line_fft<T, L, false, NL, LS, NTHR>(buf, tws, tid);
@@ -286,8 +293,8 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
         const int kx = e / R;
         const int rl = e - kx * R;
         const int line = rl >> 1;
-        const cplx<T> Z = buf[line * LS + kx];
-        const cplx<T> Zc = cconj(buf[line * LS + (kx == 0 ? 0 : L - kx)]);
+        const cplx<T> Z = buf[line * LS + lpad(kx)];
+        const cplx<T> Zc = cconj(buf[line * LS + lpad(kx == 0 ? 0 : L - kx)]);
         cplx<T> o;
         if (rl & 1) {  // (Z - Zc) / 2i
             o = cplx<T>{T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
@@ -381,8 +388,8 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
         A[((size_t)(c * L + z) * NC + kx) * L + ky0 + w] = x;
     };
     cplx<T>* lb = buf;
-    auto lload = [lb](int line, int e) { return lb[line * LS + e]; };
-    auto lstore = [lb](int line, int e, cplx<T> x) { lb[line * LS + e] = x; };
+    auto lload = [lb](int line, int e) { return lb[line * LS + lpad(e)]; };
+    auto lstore = [lb](int line, int e, cplx<T> x) { lb[line * LS + lpad(e)] = x; };
     line_fft_io<T, L, false, NLN, LS, NTHR, true, false, true>(buf, tws, tid, gload, lstore);
     __syncthreads();
     const cplx<T> Dx = dsym[kx];
@@ -391,7 +398,7 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
         const int w = e % W;
         const int kz = e / W;
         const int ky = ky0 + w;
-        cplx<T>* X = buf + w * LS + kz;
+        cplx<T>* X = buf + w * LS + lpad(kz);
         if (kx == 0 && ky == 0 && kz == 0) {
             X[0] = cplx<T>{(T)mean_new[0], T(0)};
             X[W * LS] = cplx<T>{(T)mean_new[1], T(0)};

@@ -229,99 +229,119 @@ k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
     write_record<T>(rec, perm, pos, i, g, f, inv_vol);
 }
 
-// Spring forces of the sp.ppb particles of this block (float64).  Their
-// blob positions are loaded into LDS once; each pair force of every
-// particle, s d with d = q_b - q_a and s = k (|d| - r0) / |d|, is computed
-// once; then thread j (< nblob) sums the incident pair forces of its blob
-// (+s d on pair_a, -s d on pair_b) plus Fext_p / nb.  Returns the number of
-// blobs of the block; F holds thread j's blob force.
-__device__ __forceinline__ int springs_block(const SpringsDev& sp,
-                                             const double* __restrict__ q,
-                                             const double* __restrict__ Fext,
-                                             int64_t P, double* smem,
-                                             double F[3], int64_t* blob) {
+// Spring forces of the sp.ppb particles of a block (float64), in two
+// parts.  springs_stage loads the blob positions, the pair table and the
+// incidence lists into LDS (and each blob's share Fext_p / nb of its
+// particle's force into registers); springs_forces computes each pair force
+// of every particle once, s d with d = q_b - q_a and s = k (|d| - r0) / |d|,
+// then thread j (< nblob) sums the incident pair forces of its blob (+s d on
+// pair_a, -s d on pair_b) plus Fext_p / nb.
+struct SpringsBlk {
+    int64_t p0;    // first particle
+    int npart;     // particles of the block
+    int nblob;     // blobs of the block (thread j < nblob owns blob p0 nb + j)
+    double* qs;    // [ppb * nb][3] positions
+    double* fp;    // [ppb * np][3] pair forces
+    double* r0s;   // [np] rest lengths
+    int* pab;      // [np] pair_a | pair_b << 16
+    int* adj;      // [nb + 1] incidence starts, then [2 np] signed pairs
+};
+
+__device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
+                                                    const double* __restrict__ q,
+                                                    const double* __restrict__ Fext,
+                                                    int64_t P, double* smem,
+                                                    double fe[3]) {
+    SpringsBlk B;
     const int nb = sp.nb, np = sp.npairs;
-    const int64_t p0 = (int64_t)blockIdx.x * sp.ppb;
-    const int npart = (int)(P - p0 < sp.ppb ? P - p0 : sp.ppb);
-    const int nblob = npart * nb;
-    double* qs = smem;                     // [ppb * nb][3]
-    double* fp = smem + 3 * sp.ppb * nb;   // [ppb * np][3]
-    double* r0s = fp + 3 * sp.ppb * np;    // [np]
-    int* pab = (int*)(r0s + np);           // [np] packed pair_a | pair_b << 16
-    const double* qg = q + 3 * p0 * nb;    // contiguous blobs of the block
-    {
-        // the position loads are issued first (a block holds at most BLK
-        // blobs: springs_blocks), then the pair table, then the LDS stores
-        double ld[3];
+    B.p0 = (int64_t)blockIdx.x * sp.ppb;
+    B.npart = (int)(P - B.p0 < sp.ppb ? P - B.p0 : sp.ppb);
+    B.nblob = B.npart * nb;
+    B.qs = smem;
+    B.fp = smem + 3 * sp.ppb * nb;
+    B.r0s = B.fp + 3 * sp.ppb * np;
+    B.pab = (int*)(B.r0s + np);
+    B.adj = B.pab + np;
+    const double* qg = q + 3 * B.p0 * nb;  // contiguous blobs of the block
+    // the position loads are issued first (a block holds at most BLK blobs:
+    // springs_blocks), then the external force and the tables, then the
+    // LDS stores
+    double ld[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int i = threadIdx.x + k * BLK;
-            ld[k] = qg[i < 3 * nblob ? i : 0];
-        }
-        for (int e = threadIdx.x; e < np; e += BLK) {
-            r0s[e] = sp.r0[e];
-            pab[e] = sp.pa[e] | (sp.pb[e] << 16);
-        }
+    for (int k = 0; k < 3; ++k) {
+        const int i = threadIdx.x + k * BLK;
+        ld[k] = qg[i < 3 * B.nblob ? i : 0];
+    }
+    fe[0] = fe[1] = fe[2] = 0.0;
+    if (Fext && (int)threadIdx.x < B.nblob) {
+        const double inv_nb = 1.0 / (double)nb;
+        const double* f = Fext + 3 * (B.p0 + threadIdx.x / nb);
+        fe[0] = f[0] * inv_nb;
+        fe[1] = f[1] * inv_nb;
+        fe[2] = f[2] * inv_nb;
+    }
+    for (int e = threadIdx.x; e < np; e += BLK) {
+        B.r0s[e] = sp.r0[e];
+        B.pab[e] = sp.pa[e] | (sp.pb[e] << 16);
+    }
+    for (int e = threadIdx.x; e <= nb; e += BLK) B.adj[e] = sp.adj_start[e];
+    for (int e = threadIdx.x; e < 2 * np; e += BLK) B.adj[nb + 1 + e] = sp.adj_pair[e];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int i = threadIdx.x + k * BLK;
-            if (i < 3 * nblob) qs[i] = ld[k];
-        }
+    for (int k = 0; k < 3; ++k) {
+        const int i = threadIdx.x + k * BLK;
+        if (i < 3 * B.nblob) B.qs[i] = ld[k];
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < npart * np; w += BLK) {
+    return B;
+}
+
+__device__ __forceinline__ void springs_forces(const SpringsDev& sp, const SpringsBlk& B,
+                                               const double fe[3], double F[3],
+                                               int64_t* blob) {
+    const int nb = sp.nb, np = sp.npairs;
+    for (int w = threadIdx.x; w < B.npart * np; w += BLK) {
         const int pl = w / np;
         const int e = w - pl * np;
-        const int ab = pab[e];
-        const double* qa = qs + 3 * (pl * nb + (ab & 0xffff));
-        const double* qb = qs + 3 * (pl * nb + (ab >> 16));
+        const int ab = B.pab[e];
+        const double* qa = B.qs + 3 * (pl * nb + (ab & 0xffff));
+        const double* qb = B.qs + 3 * (pl * nb + (ab >> 16));
         const double dx = qb[0] - qa[0], dy = qb[1] - qa[1], dz = qb[2] - qa[2];
         const double len = sqrt(dx * dx + dy * dy + dz * dz);
-        const double s = sp.k * (len - r0s[e]) / len;
-        fp[3 * w] = s * dx;
-        fp[3 * w + 1] = s * dy;
-        fp[3 * w + 2] = s * dz;
+        const double s = sp.k * (len - B.r0s[e]) / len;
+        B.fp[3 * w] = s * dx;
+        B.fp[3 * w + 1] = s * dy;
+        B.fp[3 * w + 2] = s * dz;
     }
     __syncthreads();
     F[0] = F[1] = F[2] = 0.0;
     *blob = -1;
     const int j = threadIdx.x;
-    if (j < nblob) {
+    if (j < B.nblob) {
         const int pl = j / nb;
         const int b = j - pl * nb;
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        if (Fext) {
-            const double inv_nb = 1.0 / (double)nb;
-            const double* fe = Fext + 3 * (p0 + pl);
-            fx = fe[0] * inv_nb;
-            fy = fe[1] * inv_nb;
-            fz = fe[2] * inv_nb;
-        }
-        const int e1 = sp.adj_start[b + 1];
-        for (int x = sp.adj_start[b]; x < e1; ++x) {
-            const int code = sp.adj_pair[x];
+        double fx = fe[0], fy = fe[1], fz = fe[2];
+        const int* adj_pair = B.adj + nb + 1;
+        const int e1 = B.adj[b + 1];
+        for (int x = B.adj[b]; x < e1; ++x) {
+            const int code = adj_pair[x];
             const int e = (code > 0 ? code : -code) - 1;
-            const double* f = fp + 3 * (pl * np + e);
-            if (code > 0) {
-                fx += f[0];
-                fy += f[1];
-                fz += f[2];
-            } else {
-                fx -= f[0];
-                fy -= f[1];
-                fz -= f[2];
-            }
+            const double* f = B.fp + 3 * (pl * np + e);
+            const double sg = code > 0 ? 1.0 : -1.0;
+            fx += sg * f[0];
+            fy += sg * f[1];
+            fz += sg * f[2];
         }
         F[0] = fx;
         F[1] = fy;
         F[2] = fz;
-        *blob = p0 * nb + j;
+        *blob = B.p0 * nb + j;
     }
-    return nblob;
 }
 
 // Spring forces fused with the scatter of the records; also the per-block
-// float64 sums of the blob forces (momentum diagnostics).
+// float64 sums of the blob forces (momentum diagnostics).  The blob's tile,
+// rank and the tile's offset are fetched while the forces are computed, and
+// its record geometry comes from the LDS copy of the positions.
 template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
@@ -331,19 +351,32 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
                   Rec<T>* __restrict__ rec, int* __restrict__ perm,
                   double* __restrict__ fpart) {
     extern __shared__ double smem[];
-    __shared__ double red[16];
+    __shared__ double red[16 * 3];
+    const int64_t p0 = (int64_t)blockIdx.x * sp.ppb;
+    const int nblob = (int)((P - p0 < sp.ppb ? P - p0 : sp.ppb) * sp.nb);
+    const bool own = (int)threadIdx.x < nblob;
+    const int64_t ib = p0 * sp.nb + threadIdx.x;
+    int tl = 0, rk = 0;
+    if (own) {
+        tl = tile_of[ib];
+        rk = rank[ib];
+    }
+    double fe[3];
+    const SpringsBlk B = springs_stage(sp, q, Fext, P, smem, fe);
+    const int off = own ? offs[tl] : 0;
     double F[3];
     int64_t i;
-    springs_block(sp, q, Fext, P, smem, F, &i);
+    springs_forces(sp, B, fe, F, &i);
     if (i >= 0) {
-        const Geom g = blob_geom(q, i, h, L);
-        const int64_t pos = (int64_t)offs[tile_of[i]] + rank[i];
-        write_record<T>(rec, perm, pos, i, g, F, inv_vol);
+        const Geom g = blob_geom(B.qs, threadIdx.x, h, L);
+        write_record<T>(rec, perm, (int64_t)off + rk, i, g, F, inv_vol);
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double s = block_reduce<false>(F[c], red);
-        if (threadIdx.x == 0) fpart[3 * blockIdx.x + c] = s;
+    double tot[3] = {F[0], F[1], F[2]};
+    block_reduce3(tot, red);
+    if (threadIdx.x == 0) {
+        fpart[3 * blockIdx.x] = tot[0];
+        fpart[3 * blockIdx.x + 1] = tot[1];
+        fpart[3 * blockIdx.x + 2] = tot[2];
     }
 }
 
@@ -351,9 +384,11 @@ __global__ void __launch_bounds__(BLK)
 k_springs(SpringsDev sp, const double* __restrict__ q,
           const double* __restrict__ Fext, int64_t P, double* __restrict__ Fout) {
     extern __shared__ double smem[];
+    double fe[3];
+    const SpringsBlk B = springs_stage(sp, q, Fext, P, smem, fe);
     double F[3];
     int64_t i;
-    springs_block(sp, q, Fext, P, smem, F, &i);
+    springs_forces(sp, B, fe, F, &i);
     if (i < 0) return;
     Fout[3 * i] = F[0];
     Fout[3 * i + 1] = F[1];
@@ -799,7 +834,8 @@ int springs_blocks(const SpringsDev& sp, int64_t P) {
 
 size_t springs_lds(const SpringsDev& sp) {
     return (size_t)sp.ppb * (sp.nb + sp.npairs) * 3 * sizeof(double) +
-           (size_t)sp.npairs * (sizeof(double) + sizeof(int));
+           (size_t)sp.npairs * (sizeof(double) + sizeof(int)) +
+           (size_t)(sp.nb + 1 + 2 * sp.npairs) * sizeof(int);
 }
 
 template <typename T, int TX>
