@@ -109,9 +109,7 @@ mb_status mb_grid_destroy(mb_grid* grid);
  * [0, blobs_per_particle) with rest lengths rest_len[e] > 0 and stiffness
  * k >= 0; energy sum_e (k/2)(|q_b - q_a| - rest_len[e])^2 per particle.
  * All three arrays are HOST arrays, copied.  blobs_per_particle <= 64, each
- * blob in at most 63 pairs.  MB_ERR_UNSUPPORTED when one particle's
- * positions and pair forces with the tables exceed 64 KB of LDS (more than
- * about 1,300 pairs at 64 blobs). */
+ * blob in at most 63 pairs. */
 mb_status mb_springs_create(int32_t blobs_per_particle, int32_t npairs,
                             const int32_t* pair_a, const int32_t* pair_b,
                             const double* rest_len, double k,

@@ -301,14 +301,13 @@ mb_status mb_springs_create(int32_t nb, int32_t npairs, const int32_t* pa,
         if (deg[b] > 63) return MB_ERR_INVALID;
     int dev = 0;
     if (!device_ok(&dev)) return MB_ERR_DEVICE;
-    // per-blob incident pairs, signed: +(e+1) when the blob is pair_a[e]
-    // (force +s d), -(e+1) when it is pair_b[e] (force -s d)
+    // per-blob incident pairs: e << 8 | (the pair's other blob)
     std::vector<int> start(nb + 1, 0);
     for (int b = 0; b < nb; ++b) start[b + 1] = start[b] + deg[b];
     std::vector<int> inc(std::max(1, 2 * npairs), 0), fill(start.begin(), start.end() - 1);
     for (int e = 0; e < npairs; ++e) {
-        inc[fill[pa[e]]++] = e + 1;
-        inc[fill[pb[e]]++] = -(e + 1);
+        inc[fill[pa[e]]++] = (e << 8) | pb[e];
+        inc[fill[pb[e]]++] = (e << 8) | pa[e];
     }
     std::vector<int> hpa(std::max(1, npairs), 0), hpb(std::max(1, npairs), 0);
     std::vector<double> hr0(std::max(1, npairs), 1.0);
@@ -317,13 +316,11 @@ mb_status mb_springs_create(int32_t nb, int32_t npairs, const int32_t* pa,
         hpb[e] = pb[e];
         hr0[e] = r0[e];
     }
-    // particles per block: at most 256 blobs; their positions and pair
-    // forces plus the pair and incidence tables in at most 48 KB of LDS
-    // (64 KB for a single particle)
-    const int per_particle = (npairs + nb) * 3 * (int)sizeof(double);
-    const int tables = npairs * (int)(sizeof(double) + sizeof(int)) +
-                       (nb + 1 + 2 * npairs) * (int)sizeof(int);
-    if (tables + per_particle > 64 * 1024) return MB_ERR_UNSUPPORTED;
+    // particles per block: at most 256 blobs; their positions plus the rest
+    // lengths and incidence lists in at most 48 KB of LDS (at most 34 KB
+    // for a single particle of 64 blobs and all 2016 pairs)
+    const int per_particle = nb * 3 * (int)sizeof(double);
+    const int tables = npairs * (int)sizeof(double) + (nb + 1 + 2 * npairs) * (int)sizeof(int);
     mb_springs* sp = new (std::nothrow) mb_springs();
     if (!sp) return MB_ERR_NOMEM;
     sp->nb = nb;

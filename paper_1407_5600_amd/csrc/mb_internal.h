@@ -34,14 +34,13 @@ enum KernelId : int {
 };
 
 // Spring table of the particle template on the device: the pair list and,
-// per blob, the incident pairs with the sign of their force on that blob
-// (+1 for the pair's first blob, -1 for its second).
+// per blob, its incident pairs with the pair's other blob.
 struct SpringsDev {
     const int* pa;          // [npairs]
     const int* pb;          // [npairs]
     const double* r0;       // [npairs]
     const int* adj_start;   // [nb + 1]
-    const int* adj_pair;    // [2 * npairs] signed: pair + 1 or -(pair + 1)
+    const int* adj_pair;    // [2 * npairs] pair << 8 | other blob of the pair
     double k;
     int nb;
     int npairs;

@@ -80,6 +80,32 @@ __device__ __forceinline__ uint32_t cell_pack(const Geom& g) {
 }
 
 // ---------------------------------------------------------------------------
+// Block scan helpers.
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = BLK * SCAN_ITEMS;  // 4096
+
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
+
+// Exclusive scan of `vals` (n entries) held in LDS tile `s` of SCAN_TILE
+// entries (padded indexing); returns the tile total.
+__device__ int scan_tile_lds(int* s, int* scratch) {
+    int local[SCAN_ITEMS];
+    int sum = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        local[k] = s[scan_pad(threadIdx.x * SCAN_ITEMS + k)];
+        sum += local[k];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, scratch, &total);
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        s[scan_pad(threadIdx.x * SCAN_ITEMS + k)] = run;
+        run += local[k];
+    }
+    __syncthreads();
+    return total;
+}
+
+// ---------------------------------------------------------------------------
 // Binning: counting sort of blobs by tile.  Blobs are taken in `order` (the
 // sorted order of the previous binning when it covered the same blobs, so
 // that a block's blobs fall in a few consecutive tiles; the identity
@@ -118,15 +144,11 @@ k_tile_count(const double* __restrict__ q, const int* __restrict__ order,
         lbase[threadIdx.x] = c > 0 ? atomicAdd(&count[t0s + threadIdx.x], c) : 0;
     }
     __syncthreads();
-    if (i < 0) return;
-    tile_of[i] = t;
-    rank[i] = local ? lbase[k] + r : r;
+    if (i >= 0) {
+        tile_of[i] = t;
+        rank[i] = local ? lbase[k] + r : r;
+    }
 }
-
-constexpr int SCAN_ITEMS = 16;
-constexpr int SCAN_TILE = BLK * SCAN_ITEMS;  // 4096
-
-__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
 
 // Per-block sums of the counts.
 __global__ void __launch_bounds__(BLK)
@@ -142,25 +164,6 @@ k_scan_reduce(const int* __restrict__ count, int64_t n, int* __restrict__ bsum) 
     if (threadIdx.x == 0) bsum[blockIdx.x] = (int)tot;
 }
 
-// Exclusive scan of `vals` (n entries) held in LDS tile `s` of SCAN_TILE
-// entries (padded indexing); returns the tile total.
-__device__ int scan_tile_lds(int* s, int* scratch) {
-    int local[SCAN_ITEMS];
-    int sum = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        local[k] = s[scan_pad(threadIdx.x * SCAN_ITEMS + k)];
-        sum += local[k];
-    }
-    int total;
-    int run = block_exclusive_scan(sum, scratch, &total);
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        s[scan_pad(threadIdx.x * SCAN_ITEMS + k)] = run;
-        run += local[k];
-    }
-    __syncthreads();
-    return total;
-}
-
 // offs[i] = exclusive prefix of count; offs[n] = total; count reset to 0.
 // Each block adds the sums of the blocks before it (a few hundred at most).
 __global__ void __launch_bounds__(BLK)
@@ -173,9 +176,18 @@ k_scan_apply(int* __restrict__ count, int64_t n, const int* __restrict__ bsum,
     int before = 0;
     for (int b = threadIdx.x; b < (int)blockIdx.x; b += BLK) before += bsum[b];
     const int off = (int)block_reduce<false>((double)before, red);
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int i = k * BLK + threadIdx.x;
-        s[scan_pad(i)] = (base + i < n) ? count[base + i] : 0;
+    {
+        int c[SCAN_ITEMS];  // all loads before the LDS stores
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            const int i = k * BLK + threadIdx.x;
+            c[k] = count[base + i < n ? base + i : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            const int i = k * BLK + threadIdx.x;
+            s[scan_pad(i)] = (base + i < n) ? c[k] : 0;
+        }
     }
     __syncthreads();
     const int total = scan_tile_lds(s, scratch);
@@ -230,21 +242,19 @@ k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
 }
 
 // Spring forces of the sp.ppb particles of a block (float64), in two
-// parts.  springs_stage loads the blob positions, the pair table and the
-// incidence lists into LDS (and each blob's share Fext_p / nb of its
-// particle's force into registers); springs_forces computes each pair force
-// of every particle once, s d with d = q_b - q_a and s = k (|d| - r0) / |d|,
-// then thread j (< nblob) sums the incident pair forces of its blob (+s d on
-// pair_a, -s d on pair_b) plus Fext_p / nb.
+// parts.  springs_stage loads the blob positions and the incidence lists
+// into LDS (and each blob's share Fext_p / nb of its particle's force into
+// registers); springs_forces then has thread j (< nblob) sum over the pairs
+// incident to its blob the pair force on it, k (|d| - r0) d / |d| with
+// d = q_other - q_self (the two blobs of a pair get exactly opposite
+// forces), plus Fext_p / nb.
 struct SpringsBlk {
     int64_t p0;    // first particle
     int npart;     // particles of the block
     int nblob;     // blobs of the block (thread j < nblob owns blob p0 nb + j)
     double* qs;    // [ppb * nb][3] positions
-    double* fp;    // [ppb * np][3] pair forces
     double* r0s;   // [np] rest lengths
-    int* pab;      // [np] pair_a | pair_b << 16
-    int* adj;      // [nb + 1] incidence starts, then [2 np] signed pairs
+    int* adj;      // [nb + 1] incidence starts, then [2 np] (pair << 8 | other)
 };
 
 __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
@@ -258,10 +268,8 @@ __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
     B.npart = (int)(P - B.p0 < sp.ppb ? P - B.p0 : sp.ppb);
     B.nblob = B.npart * nb;
     B.qs = smem;
-    B.fp = smem + 3 * sp.ppb * nb;
-    B.r0s = B.fp + 3 * sp.ppb * np;
-    B.pab = (int*)(B.r0s + np);
-    B.adj = B.pab + np;
+    B.r0s = smem + 3 * sp.ppb * nb;
+    B.adj = (int*)(B.r0s + np);
     const double* qg = q + 3 * B.p0 * nb;  // contiguous blobs of the block
     // the position loads are issued first (a block holds at most BLK blobs:
     // springs_blocks), then the external force and the tables, then the
@@ -280,10 +288,7 @@ __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
         fe[1] = f[1] * inv_nb;
         fe[2] = f[2] * inv_nb;
     }
-    for (int e = threadIdx.x; e < np; e += BLK) {
-        B.r0s[e] = sp.r0[e];
-        B.pab[e] = sp.pa[e] | (sp.pb[e] << 16);
-    }
+    for (int e = threadIdx.x; e < np; e += BLK) B.r0s[e] = sp.r0[e];
     for (int e = threadIdx.x; e <= nb; e += BLK) B.adj[e] = sp.adj_start[e];
     for (int e = threadIdx.x; e < 2 * np; e += BLK) B.adj[nb + 1 + e] = sp.adj_pair[e];
 #pragma unroll
@@ -298,44 +303,33 @@ __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
 __device__ __forceinline__ void springs_forces(const SpringsDev& sp, const SpringsBlk& B,
                                                const double fe[3], double F[3],
                                                int64_t* blob) {
-    const int nb = sp.nb, np = sp.npairs;
-    for (int w = threadIdx.x; w < B.npart * np; w += BLK) {
-        const int pl = w / np;
-        const int e = w - pl * np;
-        const int ab = B.pab[e];
-        const double* qa = B.qs + 3 * (pl * nb + (ab & 0xffff));
-        const double* qb = B.qs + 3 * (pl * nb + (ab >> 16));
-        const double dx = qb[0] - qa[0], dy = qb[1] - qa[1], dz = qb[2] - qa[2];
-        const double len = sqrt(dx * dx + dy * dy + dz * dz);
-        const double s = sp.k * (len - B.r0s[e]) / len;
-        B.fp[3 * w] = s * dx;
-        B.fp[3 * w + 1] = s * dy;
-        B.fp[3 * w + 2] = s * dz;
-    }
-    __syncthreads();
+    const int nb = sp.nb;
     F[0] = F[1] = F[2] = 0.0;
     *blob = -1;
     const int j = threadIdx.x;
-    if (j < B.nblob) {
-        const int pl = j / nb;
-        const int b = j - pl * nb;
-        double fx = fe[0], fy = fe[1], fz = fe[2];
-        const int* adj_pair = B.adj + nb + 1;
-        const int e1 = B.adj[b + 1];
-        for (int x = B.adj[b]; x < e1; ++x) {
-            const int code = adj_pair[x];
-            const int e = (code > 0 ? code : -code) - 1;
-            const double* f = B.fp + 3 * (pl * np + e);
-            const double sg = code > 0 ? 1.0 : -1.0;
-            fx += sg * f[0];
-            fy += sg * f[1];
-            fz += sg * f[2];
-        }
-        F[0] = fx;
-        F[1] = fy;
-        F[2] = fz;
-        *blob = B.p0 * nb + j;
+    if (j >= B.nblob) return;
+    const int pl = j / nb;
+    const int b = j - pl * nb;
+    const double* qp = B.qs + 3 * pl * nb;  // the particle's blobs
+    const double qx = qp[3 * b], qy = qp[3 * b + 1], qz = qp[3 * b + 2];
+    double fx = fe[0], fy = fe[1], fz = fe[2];
+    const int* inc = B.adj + nb + 1;
+    const int e1 = B.adj[b + 1];
+    for (int x = B.adj[b]; x < e1; ++x) {
+        const int code = inc[x];
+        const int o = code & 0xff;
+        const double* qo = qp + 3 * o;
+        const double dx = qo[0] - qx, dy = qo[1] - qy, dz = qo[2] - qz;
+        const double len = sqrt(dx * dx + dy * dy + dz * dz);
+        const double s = sp.k * (len - B.r0s[code >> 8]) / len;
+        fx += s * dx;
+        fy += s * dy;
+        fz += s * dz;
     }
+    F[0] = fx;
+    F[1] = fy;
+    F[2] = fz;
+    *blob = B.p0 * nb + j;
 }
 
 // Spring forces fused with the scatter of the records; also the per-block
@@ -833,8 +827,7 @@ int springs_blocks(const SpringsDev& sp, int64_t P) {
 }
 
 size_t springs_lds(const SpringsDev& sp) {
-    return (size_t)sp.ppb * (sp.nb + sp.npairs) * 3 * sizeof(double) +
-           (size_t)sp.npairs * (sizeof(double) + sizeof(int)) +
+    return (size_t)sp.ppb * sp.nb * 3 * sizeof(double) + (size_t)sp.npairs * sizeof(double) +
            (size_t)(sp.nb + 1 + 2 * sp.npairs) * sizeof(int);
 }
 
