@@ -584,14 +584,14 @@ k_fold(const T* __restrict__ E, int L, Tiles tl, T* __restrict__ f) {
     f[i] = box_sum(E, tl, a, x, y, z);
 }
 
-// Interpolation: one block per tile, one velocity component at a time.  The
-// component on nodes [lo-1, hi+2] is staged in LDS (rows located through a
-// table of wrapped row offsets), then every record of the tile's cells
-// gathers its 27 nodes; u (and the move of the blob by dt u) is written
+// Interpolation: one block per tile.  The velocity on nodes [lo-1, hi+2]
+// is staged in LDS (rows located through a table of wrapped row offsets),
+// all three components at once for float32 fields and one at a time for
+// float64 ones (LDS size); then every record of the tile's cells gathers its
+// 27 nodes per component.  u (and the move of the blob by dt u) is written
 // once per blob for each thread's first record, per component for the rest
-// (tiles with more records than threads).  With
-// part the block also writes its float64 sum of each component and the max
-// |Dv| over its cells.
+// (tiles with more records than threads).  With part the block also writes
+// its float64 sum of each component and the max |Dv| over its cells.
 template <typename T, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
 k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
@@ -602,8 +602,10 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     constexpr int EV = EX * EY * EZ;
     constexpr int TV = TX * TY * TZ;
     constexpr int RP = BLK / EX;             // rows staged per pass
+    constexpr int NR = (EY * EZ + RP - 1) / RP;
     constexpr int CPT = (TV + BLK - 1) / BLK; // own cells per thread
-    __shared__ T vt[EV];
+    constexpr int NCS = sizeof(T) == 4 ? 3 : 1;  // components staged together
+    __shared__ T vt[NCS * EV];
     __shared__ int rowoff[EY * EZ];
     __shared__ double red[16];
     const TileBox tb = tile_box(tl, L);
@@ -634,71 +636,88 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
 #pragma unroll
     for (int j = 0; j < CPT; ++j) dv[j] = 0.0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (a > 0) __syncthreads();  // the previous component's gathers are done
+    for (int a0 = 0; a0 < 3; a0 += NCS) {
+        if (a0 > 0) __syncthreads();  // the previous component's gathers are done
         if (sr < RP) {
             // all loads of the thread first, then the LDS stores
-            constexpr int NR = (EY * EZ + RP - 1) / RP;
-            const T* va = v + (int64_t)a * N + gx;
-            T ld[NR];
+            T ld[NCS][NR];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const int r = sr + k * RP;
-                ld[k] = va[rowoff[r < EY * EZ ? r : sr]];
+            for (int c = 0; c < NCS; ++c) {
+                const T* va = v + (int64_t)(a0 + c) * N + gx;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const int r = sr + k * RP;
+                    ld[c][k] = va[rowoff[r < EY * EZ ? r : sr]];
+                }
             }
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const int r = sr + k * RP;
-                if (r < EY * EZ) vt[r * EX + sx] = ld[k];
-            }
+            for (int c = 0; c < NCS; ++c)
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const int r = sr + k * RP;
+                    if (r < EY * EZ) vt[c * EV + r * EX + sx] = ld[c][k];
+                }
         }
         __syncthreads();
         for (int k = threadIdx.x; k < total; k += BLK) {
             const int pos = first + k;
             Rec<T> r = r0;
             if (k >= BLK) r = rec[pos];
-            T w[3][3];
-            int e0[3];  // extended-tile index of node i0 - 1
+            double ua[NCS];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                kernel_weights<T>(a == b ? r.ts[b] : r.tu[b], w[b]);
-                const int c = (int)((r.cell >> (9 * b)) & 511u) - tb.lo[b];  // [0, T)
-                const int up = (int)((r.cell >> (27 + b)) & 1u);
-                e0[b] = a == b ? c : c + up;
-            }
-            const T* base = vt + (e0[2] * EY + e0[1]) * EX + e0[0];
-            T acc = T(0);
+            for (int c = 0; c < NCS; ++c) {
+                const int a = a0 + c;
+                T w[3][3];
+                int e0[3];  // extended-tile index of node i0 - 1
 #pragma unroll
-            for (int oz = 0; oz < 3; ++oz) {
-#pragma unroll
-                for (int oy = 0; oy < 3; ++oy) {
-                    const T* row = base + (oz * EY + oy) * EX;
-                    const T sxv = w[0][0] * row[0] + w[0][1] * row[1] + w[0][2] * row[2];
-                    acc += (w[2][oz] * w[1][oy]) * sxv;
+                for (int b = 0; b < 3; ++b) {
+                    kernel_weights<T>(a == b ? r.ts[b] : r.tu[b], w[b]);
+                    const int cc = (int)((r.cell >> (9 * b)) & 511u) - tb.lo[b];  // [0, T)
+                    const int up = (int)((r.cell >> (27 + b)) & 1u);
+                    e0[b] = a == b ? cc : cc + up;
                 }
+                const T* base = vt + c * EV + (e0[2] * EY + e0[1]) * EX + e0[0];
+                T acc = T(0);
+#pragma unroll
+                for (int oz = 0; oz < 3; ++oz) {
+#pragma unroll
+                    for (int oy = 0; oy < 3; ++oy) {
+                        const T* row = base + (oz * EY + oy) * EX;
+                        const T sxv = w[0][0] * row[0] + w[0][1] * row[1] + w[0][2] * row[2];
+                        acc += (w[2][oz] * w[1][oy]) * sxv;
+                    }
+                }
+                ua[c] = (double)acc;
             }
-            const double ua = (double)acc;
             if (k < BLK) {
-                u0[a] = ua;  // written with the other components at the end
+#pragma unroll
+                for (int c = 0; c < NCS; ++c) u0[a0 + c] = ua[c];  // written at the end
             } else {
                 const int64_t i = perm[pos];
-                if (u_out) u_out[3 * i + a] = ua;
-                if (q) q[3 * i + a] += dt * ua;
+#pragma unroll
+                for (int c = 0; c < NCS; ++c) {
+                    if (u_out) u_out[3 * i + a0 + c] = ua[c];
+                    if (q) q[3 * i + a0 + c] += dt * ua[c];
+                }
             }
         }
         if (part) {
-            const int str = a == 0 ? 1 : (a == 1 ? EX : EX * EY);
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const int i = threadIdx.x + j * BLK;
-                if (i < TV) {
-                    const int x = i % TX + 1;
-                    const int y = (i / TX) % TY + 1;
-                    const int z = i / (TX * TY) + 1;
-                    const int c0 = (z * EY + y) * EX + x;
-                    const T val = vt[c0];
-                    sv[a] += (double)val;
-                    dv[j] += (double)(val - vt[c0 - str]);
+            for (int c = 0; c < NCS; ++c) {
+                const int a = a0 + c;
+                const int str = a == 0 ? 1 : (a == 1 ? EX : EX * EY);
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+                    const int i = threadIdx.x + j * BLK;
+                    if (i < TV) {
+                        const int x = i % TX + 1;
+                        const int y = (i / TX) % TY + 1;
+                        const int z = i / (TX * TY) + 1;
+                        const int c0 = c * EV + (z * EY + y) * EX + x;
+                        const T val = vt[c0];
+                        sv[a] += (double)val;
+                        dv[j] += (double)(val - vt[c0 - str]);
+                    }
                 }
             }
         }
