@@ -57,6 +57,38 @@ def algorithmic_bytes(L, M, P, prec, steady=False):
     }
 
 
+def library_sources_sha256():
+    """SHA-256 over the library's kernel and interface sources (the key under
+    which measured HBM traffic is stored)."""
+    import glob
+    import hashlib
+    src = sorted(glob.glob(os.path.join(ROOT, "paper_1407_5600_amd", "csrc", "*.hip")) +
+                 glob.glob(os.path.join(ROOT, "paper_1407_5600_amd", "csrc", "*.h")) +
+                 glob.glob(os.path.join(ROOT, "include", "*.h")))
+    h = hashlib.sha256()
+    for p in src:
+        h.update(os.path.relpath(p, ROOT).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE scaled by the
+    copy calibration) from the stored counter summary of the dense workload,
+    or None when there is none or the library sources changed since."""
+    path = os.path.join(ROOT, "profiles", "dense128_traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != library_sources_sha256():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return round(k["read_bytes"] + k["write_bytes"]) if k else None
+
+
 def run_steps(torch, g, sp, q, v, Fe, n):
     for _ in range(n):
         g.step(sp, q, v, Fe, 1)
@@ -189,7 +221,8 @@ def main():
                      "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": None,
+                     "traffic": (measured_traffic(dom)
+                                 if args.workload == "dense" and head_prec == "mixed" else None),
                      "alg_bytes_per_launch": dom_bytes,
                      "live_avg_launch_ms": round(head["dominant_live_ms"], 5)},
     }

@@ -96,9 +96,10 @@ typedef struct {
 typedef struct mb_grid mb_grid;       /* opaque; owns FFT tables and scratch */
 typedef struct mb_springs mb_springs; /* opaque; owns the pair table */
 
-/* Create a grid on the current HIP device.  Allocates the spectrum, binning
- * and blob scratch (about 3 L^3 complex values plus 2 L^3 int32 plus
- * ~100 B per blob).  *out is set to NULL on error. */
+/* Create a grid on the current HIP device.  Allocates the spectrum (about
+ * 1.5 L^3 complex values), the spread boxes (about 6.75 L^3 values of the
+ * field precision), the per-tile binning arrays and ~100 B per blob of
+ * scratch.  *out is set to NULL on error. */
 mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out);
 
 /* Release a grid (synchronises its device first).  NULL is accepted. */
