@@ -43,6 +43,8 @@ def lib():
         d = ctypes.c_double
         _lib.mbo_phi.restype = d
         _lib.mbo_phi.argtypes = [d]
+        _lib.mbo_phi_deriv.restype = d
+        _lib.mbo_phi_deriv.argtypes = [d]
     return _lib
 
 
@@ -167,3 +169,68 @@ def step(prm, springs, q, v, Fext, nsteps=1):
                    ctypes.c_double(springs["k"]), _p(q), _p(v), _p(Fext),
                    _p(u), _p(U0), ctypes.c_int(nsteps), _p(diag))
     return {"q": q, "v": v, "u": u, "U0": U0, "diag": diag}
+
+
+# ---- derivatives (reverse mode) -------------------------------------------
+
+def phi_deriv(r):
+    """Phi'(r) of the 3-point kernel (eq. delta is C^1)."""
+    return lib().mbo_phi_deriv(float(r))
+
+
+def interpolate_grad(prm, q, v, W):
+    """sum_a W_{i,a} grad_{q_i} (J_i v)_a per blob (M, 3): the derivative of
+    the interpolation of eq. ju with respect to the blob positions."""
+    q = _f64(q)
+    v = _f64(v)
+    W = _f64(W)
+    g = np.zeros_like(q)
+    lib().mbo_interpolate_grad(ctypes.byref(prm), ctypes.c_long(q.shape[0]), _p(q),
+                               _p(v), _p(W), _p(g))
+    return g
+
+
+def spring_adjoint(P, nb, pa, pb, r0, k, q, Fbar):
+    """(dF/dq)^T Fbar, Fbar . dF/dk and Fbar . dF/dr0 of the spring forces
+    (Fig. 1 springs, Fext excluded).  Returns (qbar (M, 3), kbar, r0bar)."""
+    pa = np.ascontiguousarray(pa, dtype=np.int32)
+    pb = np.ascontiguousarray(pb, dtype=np.int32)
+    r0 = _f64(r0)
+    q = _f64(q)
+    Fbar = _f64(Fbar)
+    qbar = np.zeros_like(q)
+    kbar = ctypes.c_double(0.0)
+    r0bar = np.zeros(len(pa))
+    lib().mbo_spring_adjoint(ctypes.c_long(P), ctypes.c_int(nb), ctypes.c_int(len(pa)),
+                             _p(pa), _p(pb), _p(r0), ctypes.c_double(k), _p(q),
+                             _p(Fbar), _p(qbar), ctypes.byref(kbar), _p(r0bar))
+    return qbar, kbar.value, r0bar
+
+
+def loss_grad(prm, springs, q0, v0, G, V, nsteps):
+    """Loss sum_p |U_p - V_p|^2 of an nsteps trajectory (per-blob external
+    forces G (M, 3); U_p the mean blob velocity of particle p in the last
+    step) and its gradients by the reverse sweep.  Returns (loss, dict with
+    q0, v0, G, k, r0)."""
+    q0 = _f64(q0)
+    v0 = _f64(v0)
+    G = _f64(G)
+    V = _f64(V)
+    nb = int(springs["nb"])
+    P = q0.shape[0] // nb
+    pa = np.ascontiguousarray(springs["pa"], dtype=np.int32)
+    pb = np.ascontiguousarray(springs["pb"], dtype=np.int32)
+    r0 = _f64(springs["r0"])
+    loss = ctypes.c_double(0.0)
+    kbar = ctypes.c_double(0.0)
+    qbar = np.zeros_like(q0)
+    vbar = np.zeros_like(v0)
+    Gbar = np.zeros_like(G)
+    r0bar = np.zeros(len(pa))
+    lib().mbo_loss_grad(ctypes.byref(prm), ctypes.c_long(P), ctypes.c_int(nb),
+                        ctypes.c_int(len(pa)), _p(pa), _p(pb), _p(r0),
+                        ctypes.c_double(springs["k"]), _p(q0), _p(v0), _p(G), _p(V),
+                        ctypes.c_int(nsteps), ctypes.byref(loss), _p(qbar), _p(vbar),
+                        _p(Gbar), ctypes.byref(kbar), _p(r0bar))
+    return loss.value, {"q0": qbar, "v0": vbar, "G": Gbar, "k": kbar.value, "r0": r0bar}
+

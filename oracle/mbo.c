@@ -413,3 +413,239 @@ void mbo_step(const mbo_params* p, long P, int nb, int npairs, const int* pa,
     free(uu);
     free(f);
 }
+
+/* ------------------------------------------------------------------------
+ * Derivatives (reverse mode) of the step.
+ *
+ * These are the plain transposed chain rule of the functions above, for
+ * the gradient of a trajectory loss.  Each is pinned by central finite
+ * differences of the corresponding forward function.
+ * ---------------------------------------------------------------------- */
+
+/* d Phi / dr of the 3-point kernel (C^1: Phi' is continuous at |r| = 1/2
+ * and vanishes at |r| = 3/2). */
+double mbo_phi_deriv(double r)
+{
+    double a = fabs(r);
+    double sgn = r < 0.0 ? -1.0 : 1.0;
+    if (a <= 0.5)
+        return -r / sqrt(1.0 - 3.0 * r * r);
+    if (a <= 1.5) {
+        double c = 1.0 - a;
+        return sgn * (-0.5 - c / (2.0 * sqrt(1.0 - 3.0 * c * c)));
+    }
+    return 0.0;
+}
+
+/* One-dimensional kernel values and their derivatives with respect to the
+ * blob coordinate qb (d/dqb Phi((x - qb)/h) = -Phi'((x - qb)/h)/h). */
+static void axis_weights_deriv(double qb, double h, double shift, long* first,
+                               double w[5], double dw[5])
+{
+    long base = (long)floor(qb / h - shift);
+    *first = base - 2;
+    for (int o = 0; o < 5; ++o) {
+        double xnode = ((double)(*first + o) + shift) * h;
+        double r = (xnode - qb) / h;
+        w[o] = mbo_phi(r);
+        dw[o] = -mbo_phi_deriv(r) / h;
+    }
+}
+
+void mbo_interpolate_grad(const mbo_params* p, long M, const double* q,
+                          const double* v, const double* W, double* g)
+{
+    const long L = p->L;
+    const long N = L * L * L;
+    const double h = p->h;
+    for (long i = 0; i < M; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            long first[3];
+            double w[3][5], dw[3][5];
+            for (int b = 0; b < 3; ++b)
+                axis_weights_deriv(q[3 * i + b], h, a == b ? 0.5 : 0.0,
+                                   &first[b], w[b], dw[b]);
+            double grad[3] = {0.0, 0.0, 0.0};
+            for (int oz = 0; oz < 5; ++oz)
+                for (int oy = 0; oy < 5; ++oy)
+                    for (int ox = 0; ox < 5; ++ox) {
+                        long node = wrap_index(first[2] + oz, L) * L * L +
+                                    wrap_index(first[1] + oy, L) * L +
+                                    wrap_index(first[0] + ox, L);
+                        double val = v[a * N + node];
+                        grad[0] += dw[0][ox] * w[1][oy] * w[2][oz] * val;
+                        grad[1] += w[0][ox] * dw[1][oy] * w[2][oz] * val;
+                        grad[2] += w[0][ox] * w[1][oy] * dw[2][oz] * val;
+                    }
+            for (int b = 0; b < 3; ++b)
+                g[3 * i + b] += W[3 * i + a] * grad[b];
+        }
+    }
+}
+
+void mbo_spring_adjoint(long P, int nb, int npairs, const int* pa,
+                        const int* pb, const double* r0, double k,
+                        const double* q, const double* Fbar, double* qbar,
+                        double* kbar, double* r0bar)
+{
+    for (long p = 0; p < P; ++p) {
+        for (int e = 0; e < npairs; ++e) {
+            long ia = p * nb + pa[e];
+            long ib = p * nb + pb[e];
+            double d[3], lam[3];
+            double len2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                d[c] = q[3 * ib + c] - q[3 * ia + c];
+                len2 += d[c] * d[c];
+                /* the pair force enters F_a with + and F_b with - */
+                lam[c] = Fbar[3 * ia + c] - Fbar[3 * ib + c];
+            }
+            double len = sqrt(len2);
+            /* force on a: f = k (1 - r0/|d|) d;
+             * df/dd = k [(1 - r0/|d|) I + r0 d d^T / |d|^3] (symmetric) */
+            double s = k * (1.0 - r0[e] / len);
+            double t = k * r0[e] / (len * len * len);
+            double ld = lam[0] * d[0] + lam[1] * d[1] + lam[2] * d[2];
+            for (int c = 0; c < 3; ++c) {
+                double jl = s * lam[c] + t * d[c] * ld; /* (df/dd)^T lam */
+                qbar[3 * ib + c] += jl;                 /* dd/dq_b = +I */
+                qbar[3 * ia + c] -= jl;                 /* dd/dq_a = -I */
+            }
+            if (kbar)
+                *kbar += ld * (1.0 - r0[e] / len);      /* df/dk = f/k */
+            if (r0bar)
+                r0bar[e] += -k * ld / len;              /* df/dr0 = -k d/|d| */
+        }
+    }
+}
+
+/* Apply C = (rho/dt) I + (eta/2) L_h (the explicit half of the
+ * Crank-Nicolson step; the 7-point Laplacian per component) to a field. */
+static void apply_cn_explicit(const mbo_params* p, const double* x, double* y)
+{
+    const long L = p->L;
+    const long N = L * L * L;
+    const double a = p->rho / p->dt;
+    const double b = 0.5 * p->eta / (p->h * p->h);
+    for (int c = 0; c < 3; ++c)
+        for (long z = 0; z < L; ++z)
+            for (long yy = 0; yy < L; ++yy)
+                for (long xx = 0; xx < L; ++xx) {
+                    const double* X = x + c * N;
+                    long idx = (z * L + yy) * L + xx;
+                    double lap = X[(z * L + yy) * L + wrap_index(xx - 1, L)] +
+                                 X[(z * L + yy) * L + wrap_index(xx + 1, L)] +
+                                 X[(z * L + wrap_index(yy - 1, L)) * L + xx] +
+                                 X[(z * L + wrap_index(yy + 1, L)) * L + xx] +
+                                 X[(wrap_index(z - 1, L) * L + yy) * L + xx] +
+                                 X[(wrap_index(z + 1, L) * L + yy) * L + xx] -
+                                 6.0 * X[idx];
+                    y[c * N + idx] = a * X[idx] + b * lap;
+                }
+}
+
+void mbo_loss_grad(const mbo_params* p, long P, int nb, int npairs,
+                   const int* pa, const int* pb, const double* r0, double k,
+                   const double* q0, const double* v0, const double* G,
+                   const double* V, int nsteps, double* loss, double* qbar0,
+                   double* vbar0, double* Gbar, double* kbar, double* r0bar)
+{
+    const long L = p->L;
+    const long N = L * L * L;
+    const long M = P * nb;
+    const double h3 = p->h * p->h * p->h;
+    const long MM = M > 0 ? M : 1;
+    /* forward, keeping q^n and v^{n+1} of every step */
+    double* qs = (double*)malloc(sizeof(double) * 3 * MM * (nsteps + 1));
+    double* vs = (double*)malloc(sizeof(double) * 3 * N * (nsteps + 1));
+    double* F = (double*)malloc(sizeof(double) * 3 * MM);
+    double* f = (double*)malloc(sizeof(double) * 3 * N);
+    double* u = (double*)malloc(sizeof(double) * 3 * MM);
+    memcpy(qs, q0, sizeof(double) * 3 * M);
+    memcpy(vs, v0, sizeof(double) * 3 * N);
+    for (int n = 0; n < nsteps; ++n) {
+        double* q = qs + 3 * M * n;
+        mbo_spring_forces(P, nb, npairs, pa, pb, r0, k, q, NULL, F);
+        for (long i = 0; i < 3 * M; ++i)
+            F[i] += G[i];
+        mbo_spread(p, M, q, F, f);
+        mbo_fluid_solve(p, vs + 3 * N * n, f, vs + 3 * N * (n + 1));
+        mbo_interpolate(p, M, q, vs + 3 * N * (n + 1), u);
+        for (long i = 0; i < 3 * M; ++i)
+            qs[3 * M * (n + 1) + i] = q[i] + p->dt * u[i];
+    }
+    /* loss = sum_p |U_p - V_p|^2 with U_p the mean blob velocity of the last
+     * step; dloss/du_i = 2 (U_p - V_p) / nb */
+    double* ubar = (double*)calloc(3 * MM, sizeof(double));
+    double l = 0.0;
+    if (nsteps > 0) {
+        for (long pp = 0; pp < P; ++pp)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int b = 0; b < nb; ++b)
+                    s += u[3 * (pp * nb + b) + c];
+                double dU = s / nb - V[3 * pp + c];
+                l += dU * dU;
+                for (int b = 0; b < nb; ++b)
+                    ubar[3 * (pp * nb + b) + c] = 2.0 * dU / nb;
+            }
+    }
+    *loss = l;
+    /* reverse sweep */
+    double* qbar = (double*)calloc(3 * MM, sizeof(double));
+    double* vbar = (double*)calloc(3 * N, sizeof(double));
+    double* wbar = (double*)malloc(sizeof(double) * 3 * N);
+    double* fbar = (double*)malloc(sizeof(double) * 3 * N);
+    double* zero = (double*)calloc(3 * N, sizeof(double));
+    double* Fbar = (double*)malloc(sizeof(double) * 3 * MM);
+    double* Wt = (double*)malloc(sizeof(double) * 3 * MM);
+    for (long i = 0; i < 3 * M; ++i)
+        Gbar[i] = 0.0;
+    *kbar = 0.0;
+    for (int e = 0; e < npairs; ++e)
+        r0bar[e] = 0.0;
+    for (int n = nsteps - 1; n >= 0; --n) {
+        const double* q = qs + 3 * M * n;
+        const double* vn1 = vs + 3 * N * (n + 1);
+        /* q^{n+1} = q^n + dt u^n */
+        for (long i = 0; i < 3 * M; ++i)
+            ubar[i] += p->dt * qbar[i];
+        /* u^n = J(q^n) v^{n+1}: position part, and J^T = h^3 S */
+        mbo_interpolate_grad(p, M, q, vn1, ubar, qbar);
+        for (long i = 0; i < 3 * M; ++i)
+            Wt[i] = h3 * ubar[i];
+        mbo_spread(p, M, q, Wt, wbar);
+        for (long j = 0; j < 3 * N; ++j)
+            wbar[j] += vbar[j];
+        /* v^{n+1} = Q (C v^n + f^n) with Q = P K^-1 symmetric and commuting
+         * with C: fbar = Q wbar, vbar = C Q wbar.  Q is the fluid solve with
+         * a zero input velocity (steady: the whole solve). */
+        mbo_fluid_solve(p, zero, wbar, fbar);
+        if (p->steady)
+            memset(vbar, 0, sizeof(double) * 3 * N);
+        else
+            apply_cn_explicit(p, fbar, vbar);
+        /* f^n = S(q^n) F^n: F part (S^T = h^-3 J) and position part */
+        mbo_spring_forces(P, nb, npairs, pa, pb, r0, k, q, NULL, F);
+        for (long i = 0; i < 3 * M; ++i)
+            F[i] += G[i];
+        mbo_interpolate(p, M, q, fbar, Fbar);
+        for (long i = 0; i < 3 * M; ++i) {
+            Fbar[i] /= h3;
+            Wt[i] = F[i] / h3;
+        }
+        mbo_interpolate_grad(p, M, q, fbar, Wt, qbar);
+        /* F^n = springs(q^n; k, r0) + G */
+        mbo_spring_adjoint(P, nb, npairs, pa, pb, r0, k, q, Fbar, qbar, kbar,
+                           r0bar);
+        for (long i = 0; i < 3 * M; ++i) {
+            Gbar[i] += Fbar[i];
+            ubar[i] = 0.0;
+        }
+    }
+    memcpy(qbar0, qbar, sizeof(double) * 3 * M);
+    memcpy(vbar0, vbar, sizeof(double) * 3 * N);
+    free(qs); free(vs); free(F); free(f); free(u); free(ubar); free(qbar);
+    free(vbar); free(wbar); free(fbar); free(zero); free(Fbar); free(Wt);
+}
+

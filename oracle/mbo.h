@@ -104,6 +104,45 @@ void mbo_step(const mbo_params* p, long P, int nb, int npairs, const int* pa,
               const double* Fext, double* u, double* U0, int nsteps,
               double* diag);
 
+/* ---- Derivatives (reverse mode), for the gradient of a trajectory loss.
+ * The transposed chain rule of the functions above written out; each is
+ * pinned by central finite differences of its forward function. */
+
+/* Phi'(r).  Pinned: finite differences of mbo_phi, sum_j Phi'(x - j) = 0,
+ * sum_j (x - j) Phi'(x - j) = -1. */
+double mbo_phi_deriv(double r);
+
+/* g_i += sum_a W_{i,a} grad_{q_i} (J_i v)_a: the derivative of the
+ * interpolation with respect to the blob positions, contracted with the
+ * blob-space weights W [M][3].  Pinned: finite differences of
+ * mbo_interpolate. */
+void mbo_interpolate_grad(const mbo_params* p, long M, const double* q,
+                          const double* v, const double* W, double* g);
+
+/* Transposed Jacobian of the spring forces (without Fext) applied to Fbar
+ * [M][3]: qbar += (dF/dq)^T Fbar, *kbar += Fbar . dF/dk, r0bar[e] +=
+ * Fbar . dF/dr0_e summed over particles (kbar, r0bar may be NULL).  Pinned:
+ * finite differences of mbo_spring_forces. */
+void mbo_spring_adjoint(long P, int nb, int npairs, const int* pa,
+                        const int* pb, const double* r0, double k,
+                        const double* q, const double* Fbar, double* qbar,
+                        double* kbar, double* r0bar);
+
+/* Loss of an nsteps trajectory and its gradient.  The step is mbo_step's
+ * with per-blob external forces G [M][3] in place of Fext:
+ *   F^n = springs(q^n; k, r0) + G;  v^{n+1} = solve(v^n, S(q^n) F^n);
+ *   u^n = J(q^n) v^{n+1};  q^{n+1} = q^n + dt u^n.
+ * loss = sum_p |U_p - V_p|^2 with U_p the mean of u over particle p's blobs
+ * in the last step and V [P][3] the targets.  Returns the loss and its
+ * gradients with respect to q^0 [M][3], v^0 [3][L^3], G [M][3], k and the
+ * rest lengths r0 [npairs], by the reverse sweep over stored states.
+ * Pinned: central finite differences of the forward loss. */
+void mbo_loss_grad(const mbo_params* p, long P, int nb, int npairs,
+                   const int* pa, const int* pb, const double* r0, double k,
+                   const double* q0, const double* v0, const double* G,
+                   const double* V, int nsteps, double* loss, double* qbar0,
+                   double* vbar0, double* Gbar, double* kbar, double* r0bar);
+
 #ifdef __cplusplus
 }
 #endif

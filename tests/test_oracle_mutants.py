@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mbo.c")
 PINS = ["tests/test_oracle_kernel.py", "tests/test_oracle_fft.py",
         "tests/test_oracle_operators.py", "tests/test_oracle_springs.py",
-        "tests/test_oracle_solver.py", "tests/test_oracle_step.py"]
+        "tests/test_oracle_solver.py", "tests/test_oracle_step.py",
+        "tests/test_oracle_adjoint.py"]
 
 MUTANTS = {
     "kernel_sqrt_sign": ("return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;",
@@ -47,6 +48,17 @@ MUTANTS = {
     "steady_viscosity": ("denom = p->eta * D2;", "denom = D2;"),
     "divergence_index": ("long cy = (z * L + wrap_index(y - 1, L)) * L + x;",
                          "long cy = (z * L + wrap_index(y + 1, L)) * L + x;"),
+    # reverse-mode derivatives
+    "phi_deriv_inner": ("return -r / sqrt(1.0 - 3.0 * r * r);",
+                        "return r / sqrt(1.0 - 3.0 * r * r);"),
+    "interp_grad_axis": ("grad[1] += w[0][ox] * dw[1][oy] * w[2][oz] * val;",
+                         "grad[1] += w[0][ox] * w[1][oy] * dw[2][oz] * val;"),
+    "spring_jacobian_drop_dd": ("double jl = s * lam[c] + t * d[c] * ld;",
+                                "double jl = s * lam[c];"),
+    "adjoint_position_update": ("ubar[i] += p->dt * qbar[i];", "ubar[i] += qbar[i];"),
+    "adjoint_transpose_volume": ("Wt[i] = h3 * ubar[i];", "Wt[i] = ubar[i];"),
+    "adjoint_cn_explicit": ("y[c * N + idx] = a * X[idx] + b * lap;",
+                            "y[c * N + idx] = a * X[idx] - b * lap;"),
 }
 
 
