@@ -156,6 +156,64 @@ mb_status mb_step(mb_grid* grid, const mb_springs* springs,
                   double* u_out, double* U0_out, double* diag_out,
                   int32_t nsteps, void* stream);
 
+/* mb_step with per-blob external forces: F^n = springs(q^n) + Fext/nb +
+ * F_blob (F_blob [M][3] float64 on the device, may be NULL; Fext may be
+ * NULL).  Used by the differentiable trajectory, whose forcing is per blob. */
+mb_status mb_step_ext(mb_grid* grid, const mb_springs* springs,
+                      int64_t nparticles, double* q, void* v,
+                      const double* Fext, const double* F_blob,
+                      double* u_out, double* U0_out, double* diag_out,
+                      int32_t nsteps, void* stream);
+
+/* mb_spring_forces plus per-blob external forces F_blob [M][3] (may be
+ * NULL). */
+mb_status mb_spring_forces_ext(const mb_springs* springs, int64_t nparticles,
+                               const double* q, const double* Fext,
+                               const double* F_blob, double* F_out,
+                               void* stream);
+
+/* ---- Derivatives (reverse mode) of the step, for gradients of losses over
+ * trajectories.  They use that J and S are each other's adjoints (Sec.
+ * Multiblob particle model: S_i = J_i^*, so J^T = h^3 S), that the fluid
+ * solve is self-adjoint (the projection P of eq. vf is Hermitian per
+ * wavevector and commutes with the viscous operator), and that the kernel
+ * of eq. delta is C^1.  All arrays are float64 device arrays; results are
+ * ACCUMULATED into the *_inout / bar arrays (zero them to start). */
+
+/* g_inout[i] += sum_a W[i][a] grad_{q_i} (J_i v)_a: the derivative of the
+ * interpolation (eq. ju) with respect to the blob positions contracted with
+ * blob weights W [M][3].  v: field in the grid's precision. */
+mb_status mb_interpolate_grad(mb_grid* grid, int64_t M, const double* q,
+                              const void* v, const double* W, double* g_inout,
+                              void* stream);
+
+/* Transposed Jacobian of the spring forces (Fig. 1 springs, energy
+ * sum (k/2)(|q_b - q_a| - r0)^2) applied to Fbar [M][3]:
+ * qbar += (dF/dq)^T Fbar;  *kbar += Fbar . dF/dk;  r0bar[e] += Fbar .
+ * dF/dr0_e summed over particles (kbar: 1 double, r0bar: npairs doubles,
+ * each may be NULL).  kbar and r0bar are summed with float64 atomics: their
+ * last bits may vary run to run. */
+mb_status mb_spring_adjoint(const mb_springs* springs, int64_t nparticles,
+                            const double* q, const double* Fbar, double* qbar,
+                            double* kbar, double* r0bar, void* stream);
+
+/* Reverse of one mb_step_ext step on a float64 grid (MB_ERR_UNSUPPORTED on
+ * a mixed grid).  Inputs: the step's starting positions q_n [M][3], the
+ * velocity after its fluid solve v_np1 [3][L^3], its forcing (Fext [P][3],
+ * F_blob [M][3], either may be NULL), and ubar_loss [M][3] (may be NULL), the
+ * loss gradient with respect to this step's blob velocities u^n.  In/out:
+ * qbar [M][3] holds dloss/dq^{n+1} on entry and dloss/dq^n on return; vbar
+ * [3][L^3] likewise dloss/dv^{n+1} -> dloss/dv^n.  Accumulated:
+ * Fblob_bar [M][3] (dloss/dF_blob), kbar (1 double), r0bar (npairs doubles);
+ * each may be NULL.  Allocates its scratch (about 9 L^3 + 9 max_blobs
+ * doubles) on the first call. */
+mb_status mb_step_adjoint(mb_grid* grid, const mb_springs* springs,
+                          int64_t nparticles, const double* q_n,
+                          const void* v_np1, const double* Fext,
+                          const double* F_blob, const double* ubar_loss,
+                          double* qbar, void* vbar, double* Fblob_bar,
+                          double* kbar, double* r0bar, void* stream);
+
 /* Human-readable text for a status. */
 const char* mb_status_string(mb_status status);
 

@@ -9,5 +9,6 @@ icosahedral particle together.  The computation lives in ``libmultiblob.so``
 the seeded input generators.
 """
 from .binding import (Grid, MultiblobError, Springs, mb_fluid_solve,  # noqa: F401
-                      mb_interpolate, mb_spread, mb_spring_forces, mb_step,
-                      spring_forces, status_string)
+                      mb_interpolate, mb_interpolate_grad, mb_spread, mb_spring_adjoint,
+                      mb_spring_forces, mb_spring_forces_ext, mb_step, mb_step_adjoint,
+                      mb_step_ext, spring_adjoint, spring_forces, status_string)

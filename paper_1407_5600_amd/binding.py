@@ -62,6 +62,12 @@ def lib():
             "mb_fluid_solve": ([vp, vp, vp, vp, vp], i32),
             "mb_spring_forces": ([vp, i64, vp, vp, vp, vp], i32),
             "mb_step": ([vp, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp], i32),
+            "mb_step_ext": ([vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
+            "mb_spring_forces_ext": ([vp, i64, vp, vp, vp, vp, vp], i32),
+            "mb_interpolate_grad": ([vp, i64, vp, vp, vp, vp, vp], i32),
+            "mb_spring_adjoint": ([vp, i64, vp, vp, vp, vp, vp, vp], i32),
+            "mb_step_adjoint": ([vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+                                i32),
             "mb_status_string": ([i32], ctypes.c_char_p),
             "mb_grid_set_timing": ([vp, ctypes.c_uint32], i32),
             "mb_grid_kernel_times": ([vp, vp, vp, vp, i32, ctypes.POINTER(i32)], i32),
@@ -78,7 +84,8 @@ def lib():
 EXPORTED = ("mb_grid_create", "mb_grid_destroy", "mb_springs_create",
             "mb_springs_destroy", "mb_spread", "mb_interpolate", "mb_fluid_solve",
             "mb_spring_forces", "mb_step", "mb_status_string", "mb_grid_set_timing",
-            "mb_grid_kernel_times", "mb_kernel_name")
+            "mb_grid_kernel_times", "mb_kernel_name", "mb_step_ext", "mb_spring_forces_ext",
+            "mb_interpolate_grad", "mb_spring_adjoint", "mb_step_adjoint")
 
 
 def status_string(st: int) -> str:
@@ -133,6 +140,7 @@ class Springs:
                                        ctypes.byref(h)), "mb_springs_create")
         self.handle = h
         self.nb = int(nb)
+        self.npairs = len(pa)
         self.k = float(k)
 
     def close(self):
@@ -231,6 +239,56 @@ class Grid:
             _ptr(diag_out, torch.float64, (NDIAG,), "diag_out", self.device),
             int(nsteps), _stream(stream)), "mb_step")
 
+    def step_ext(self, springs, q, v, Fext=None, F_blob=None, nsteps=1, u_out=None,
+                 U0_out=None, diag_out=None, stream=None):
+        """mb_step_ext: mb_step with optional per-blob external forces."""
+        import torch
+        M = q.shape[0]
+        P = M // springs.nb
+        if P * springs.nb != M:
+            raise ValueError("blob count is not a multiple of blobs per particle")
+        _check(lib().mb_step_ext(
+            self.handle, springs.handle, P,
+            _ptr(q, torch.float64, (M, 3), "q", self.device), self._fptr(v, "v"),
+            _ptr(Fext, torch.float64, (P, 3), "Fext", self.device),
+            _ptr(F_blob, torch.float64, (M, 3), "F_blob", self.device),
+            _ptr(u_out, torch.float64, (M, 3), "u_out", self.device),
+            _ptr(U0_out, torch.float64, (P, 3), "U0_out", self.device),
+            _ptr(diag_out, torch.float64, (NDIAG,), "diag_out", self.device),
+            int(nsteps), _stream(stream)), "mb_step_ext")
+
+    def interpolate_grad(self, q, v, W, g_inout=None, stream=None):
+        """mb_interpolate_grad: g += sum_a W_a grad_q (J v)_a (accumulates)."""
+        import torch
+        M = q.shape[0]
+        if g_inout is None:
+            g_inout = torch.zeros((M, 3), dtype=torch.float64, device=q.device)
+        _check(lib().mb_interpolate_grad(
+            self.handle, M, _ptr(q, torch.float64, (M, 3), "q", self.device),
+            self._fptr(v, "v"), _ptr(W, torch.float64, (M, 3), "W", self.device),
+            _ptr(g_inout, torch.float64, (M, 3), "g", self.device), _stream(stream)),
+            "mb_interpolate_grad")
+        return g_inout
+
+    def step_adjoint(self, springs, q_n, v_np1, qbar, vbar, Fext=None, F_blob=None,
+                     ubar_loss=None, Fblob_bar=None, kbar=None, r0bar=None, stream=None):
+        """mb_step_adjoint: reverse one step (qbar, vbar updated in place;
+        Fblob_bar, kbar, r0bar accumulated)."""
+        import torch
+        M = q_n.shape[0]
+        P = M // springs.nb
+        f64 = torch.float64
+        _check(lib().mb_step_adjoint(
+            self.handle, springs.handle, P, _ptr(q_n, f64, (M, 3), "q_n", self.device),
+            self._fptr(v_np1, "v_np1"), _ptr(Fext, f64, (P, 3), "Fext", self.device),
+            _ptr(F_blob, f64, (M, 3), "F_blob", self.device),
+            _ptr(ubar_loss, f64, (M, 3), "ubar_loss", self.device),
+            _ptr(qbar, f64, (M, 3), "qbar", self.device), self._fptr(vbar, "vbar"),
+            _ptr(Fblob_bar, f64, (M, 3), "Fblob_bar", self.device),
+            _ptr(kbar, f64, (1,), "kbar", self.device),
+            _ptr(r0bar, f64, (springs.npairs,), "r0bar", self.device),
+            _stream(stream)), "mb_step_adjoint")
+
     # -- timing ---------------------------------------------------------
     def set_timing(self, kernels=None):
         """Time the named kernels (None: none, "all": every kernel)."""
@@ -260,18 +318,43 @@ class Grid:
         return out
 
 
-def spring_forces(springs, q, Fext, F_out=None, stream=None):
-    """mb_spring_forces: spring forces plus Fext/nb per blob."""
+def spring_forces(springs, q, Fext, F_out=None, stream=None, F_blob=None):
+    """mb_spring_forces (mb_spring_forces_ext with F_blob): spring forces
+    plus Fext/nb (plus F_blob) per blob."""
     import torch
     M = q.shape[0]
     P = M // springs.nb
     if F_out is None:
         F_out = torch.empty((M, 3), dtype=torch.float64, device=q.device)
-    _check(lib().mb_spring_forces(springs.handle, P, _ptr(q, torch.float64, (M, 3), "q"),
-                                  _ptr(Fext, torch.float64, (P, 3), "Fext"),
-                                  _ptr(F_out, torch.float64, (M, 3), "F_out"),
-                                  _stream(stream)), "mb_spring_forces")
+    if F_blob is None:
+        _check(lib().mb_spring_forces(springs.handle, P, _ptr(q, torch.float64, (M, 3), "q"),
+                                      _ptr(Fext, torch.float64, (P, 3), "Fext"),
+                                      _ptr(F_out, torch.float64, (M, 3), "F_out"),
+                                      _stream(stream)), "mb_spring_forces")
+    else:
+        _check(lib().mb_spring_forces_ext(springs.handle, P,
+                                          _ptr(q, torch.float64, (M, 3), "q"),
+                                          _ptr(Fext, torch.float64, (P, 3), "Fext"),
+                                          _ptr(F_blob, torch.float64, (M, 3), "F_blob"),
+                                          _ptr(F_out, torch.float64, (M, 3), "F_out"),
+                                          _stream(stream)), "mb_spring_forces_ext")
     return F_out
+
+
+def spring_adjoint(springs, q, Fbar, qbar, kbar=None, r0bar=None, stream=None):
+    """mb_spring_adjoint: qbar += (dF/dq)^T Fbar; kbar (1,), r0bar (npairs,)
+    accumulate the stiffness and rest-length parts (may be None)."""
+    import torch
+    M = q.shape[0]
+    P = M // springs.nb
+    f64 = torch.float64
+    _check(lib().mb_spring_adjoint(springs.handle, P, _ptr(q, f64, (M, 3), "q"),
+                                   _ptr(Fbar, f64, (M, 3), "Fbar"),
+                                   _ptr(qbar, f64, (M, 3), "qbar"),
+                                   _ptr(kbar, f64, (1,), "kbar"),
+                                   _ptr(r0bar, f64, (springs.npairs,), "r0bar"),
+                                   _stream(stream)), "mb_spring_adjoint")
+    return qbar
 
 
 def kernel_names():
@@ -305,3 +388,28 @@ def mb_spring_forces(springs, q, Fext, F_out=None, stream=None):
 def mb_step(grid, springs, q, v, Fext, nsteps=1, u_out=None, U0_out=None,
             diag_out=None, stream=None):
     return grid.step(springs, q, v, Fext, nsteps, u_out, U0_out, diag_out, stream)
+
+
+def mb_step_ext(grid, springs, q, v, Fext=None, F_blob=None, nsteps=1, u_out=None,
+                U0_out=None, diag_out=None, stream=None):
+    return grid.step_ext(springs, q, v, Fext, F_blob, nsteps, u_out, U0_out, diag_out,
+                         stream)
+
+
+def mb_spring_forces_ext(springs, q, Fext, F_blob, F_out=None, stream=None):
+    return spring_forces(springs, q, Fext, F_out, stream, F_blob)
+
+
+def mb_interpolate_grad(grid, q, v, W, g_inout=None, stream=None):
+    return grid.interpolate_grad(q, v, W, g_inout, stream)
+
+
+def mb_spring_adjoint(springs, q, Fbar, qbar, kbar=None, r0bar=None, stream=None):
+    return spring_adjoint(springs, q, Fbar, qbar, kbar, r0bar, stream)
+
+
+def mb_step_adjoint(grid, springs, q_n, v_np1, qbar, vbar, Fext=None, F_blob=None,
+                    ubar_loss=None, Fblob_bar=None, kbar=None, r0bar=None, stream=None):
+    return grid.step_adjoint(springs, q_n, v_np1, qbar, vbar, Fext, F_blob, ubar_loss,
+                             Fblob_bar, kbar, r0bar, stream)
+

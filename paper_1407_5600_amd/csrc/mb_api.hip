@@ -27,7 +27,7 @@ const char* const kKernelNames[K_NUM] = {
     "springs_scatter", "bin_scatter", "springs",      "spread",
     "fft_x_fwd",   "fft_y_fwd",   "fft_z_spectral",   "fft_y_inv",
     "fft_x_inv",   "interp",      "interp_step",      "u0",
-    "diag",        "fold"};
+    "diag",        "fold",        "interp_grad",      "springs_adjoint"};
 
 bool size_ok(int L) {
     if (L < 8 || L > 512 || L % 8 != 0) return false;
@@ -82,7 +82,7 @@ void free_grid(mb_grid* g) {
     void* ptrs[] = {g->d_tw,    g->d_dsym,  g->d_d2,   g->d_spec,
                     g->d_psum,  g->d_count, g->d_offs, g->d_bsum,
                     g->d_rank,  g->d_perm,  g->d_rec,  g->d_tile_part,
-                    g->d_force_part, g->d_box, g->d_u, g->d_tile};
+                    g->d_force_part, g->d_box, g->d_u, g->d_tile, g->d_adj};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& tp : g->pending) {
@@ -434,9 +434,10 @@ mb_status mb_spring_forces(const mb_springs* sp, int64_t P, const double* q,
                                   (hipStream_t)stream, nullptr));
 }
 
-mb_status mb_step(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
-                  void* v, const double* Fext, double* u_out, double* U0_out,
-                  double* diag_out, int32_t nsteps, void* stream) {
+static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
+                           void* v, const double* Fext, const double* Gblob,
+                           double* u_out, double* U0_out, double* diag_out,
+                           int32_t nsteps, void* stream) {
     if (!g || !sp || !v || P < 0 || nsteps < 0) return MB_ERR_INVALID;
     const int64_t M = P * sp->nb;
     if (M > g->d.max_blobs) return MB_ERR_INVALID;
@@ -461,14 +462,14 @@ mb_status mb_step(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
         if (g->fsz == 4) {
             float* vv = (float*)v;
             e = bin_blobs<float>(g, M, q, s);
-            if (e == hipSuccess) e = scatter_springs<float>(g, sd, P, q, Fext, s);
+            if (e == hipSuccess) e = scatter_springs<float>(g, sd, P, q, Fext, s, Gblob);
             if (e == hipSuccess) e = spread_boxes<float>(g, s);
             if (e == hipSuccess) e = fluid_solve<float>(g, vv, nullptr, vv, s, true);
             if (e == hipSuccess) e = interpolate<float>(g, M, vv, u_dst, q, 1, s);
         } else {
             double* vv = (double*)v;
             e = bin_blobs<double>(g, M, q, s);
-            if (e == hipSuccess) e = scatter_springs<double>(g, sd, P, q, Fext, s);
+            if (e == hipSuccess) e = scatter_springs<double>(g, sd, P, q, Fext, s, Gblob);
             if (e == hipSuccess) e = spread_boxes<double>(g, s);
             if (e == hipSuccess) e = fluid_solve<double>(g, vv, nullptr, vv, s, true);
             if (e == hipSuccess) e = interpolate<double>(g, M, vv, u_dst, q, 1, s);
@@ -478,6 +479,145 @@ mb_status mb_step(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
         if (last && e == hipSuccess && diag_out)
             e = diagnostics(g, M > 0 ? fb : 1, diag_out, s);
     }
+    return from_hip(e);
+}
+
+mb_status mb_step(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
+                  void* v, const double* Fext, double* u_out, double* U0_out,
+                  double* diag_out, int32_t nsteps, void* stream) {
+    return step_impl(g, sp, P, q, v, Fext, nullptr, u_out, U0_out, diag_out, nsteps,
+                     stream);
+}
+
+mb_status mb_step_ext(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
+                      void* v, const double* Fext, const double* F_blob,
+                      double* u_out, double* U0_out, double* diag_out,
+                      int32_t nsteps, void* stream) {
+    if (F_blob && !aligned8(F_blob)) return MB_ERR_INVALID;
+    return step_impl(g, sp, P, q, v, Fext, F_blob, u_out, U0_out, diag_out, nsteps,
+                     stream);
+}
+
+mb_status mb_spring_forces_ext(const mb_springs* sp, int64_t P, const double* q,
+                               const double* Fext, const double* F_blob, double* F_out,
+                               void* stream) {
+    if (!sp || P < 0) return MB_ERR_INVALID;
+    if (P > 0 && (!q || !F_out || !aligned8(q) || !aligned8(F_out))) return MB_ERR_INVALID;
+    if (F_blob && !aligned8(F_blob)) return MB_ERR_INVALID;
+    if ((int64_t)P * sp->nb > ((int64_t)1 << 31) - 1) return MB_ERR_INVALID;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
+    if (cur != sp->device && hipSetDevice(sp->device) != hipSuccess) return MB_ERR_DEVICE;
+    return from_hip(spring_forces(springs_dev(sp), P, q, Fext, F_out, (hipStream_t)stream,
+                                  nullptr, F_blob));
+}
+
+mb_status mb_interpolate_grad(mb_grid* g, int64_t M, const double* q, const void* v,
+                              const double* W, double* g_inout, void* stream) {
+    if (!g || !v || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (M > 0 && (!q || !W || !g_inout || !aligned8(q) || !aligned8(W) || !aligned8(g_inout)))
+        return MB_ERR_INVALID;
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    if (M == 0) return MB_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (g->fsz == 4) {
+        e = bin_blobs<float>(g, M, q, s);
+        if (e == hipSuccess) e = scatter_records<float>(g, M, q, nullptr, s);
+        if (e == hipSuccess) e = interpolate_grad<float>(g, (const float*)v, W, 1.0, g_inout, s);
+    } else {
+        e = bin_blobs<double>(g, M, q, s);
+        if (e == hipSuccess) e = scatter_records<double>(g, M, q, nullptr, s);
+        if (e == hipSuccess)
+            e = interpolate_grad<double>(g, (const double*)v, W, 1.0, g_inout, s);
+    }
+    return from_hip(e);
+}
+
+mb_status mb_spring_adjoint(const mb_springs* sp, int64_t P, const double* q,
+                            const double* Fbar, double* qbar, double* kbar, double* r0bar,
+                            void* stream) {
+    if (!sp || P < 0) return MB_ERR_INVALID;
+    if (P > 0 && (!q || !Fbar || !qbar || !aligned8(q) || !aligned8(Fbar) || !aligned8(qbar)))
+        return MB_ERR_INVALID;
+    if ((kbar && !aligned8(kbar)) || (r0bar && !aligned8(r0bar))) return MB_ERR_INVALID;
+    if ((int64_t)P * sp->nb > ((int64_t)1 << 31) - 1) return MB_ERR_INVALID;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
+    if (cur != sp->device && hipSetDevice(sp->device) != hipSuccess) return MB_ERR_DEVICE;
+    return from_hip(springs_adjoint(springs_dev(sp), P, q, Fbar, qbar, kbar, r0bar,
+                                    (hipStream_t)stream, nullptr));
+}
+
+mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const double* q_n,
+                          const void* v_np1, const double* Fext, const double* F_blob,
+                          const double* ubar_loss, double* qbar, void* vbar,
+                          double* Fblob_bar, double* kbar, double* r0bar, void* stream) {
+    if (!g || !sp || !v_np1 || !vbar || P < 0) return MB_ERR_INVALID;
+    if (g->fsz != 8) return MB_ERR_UNSUPPORTED;
+    const int64_t M = P * sp->nb;
+    if (M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (M > 0 && (!q_n || !qbar || !aligned8(q_n) || !aligned8(qbar))) return MB_ERR_INVALID;
+    if ((F_blob && !aligned8(F_blob)) || (ubar_loss && !aligned8(ubar_loss)) ||
+        (Fblob_bar && !aligned8(Fblob_bar)) || (kbar && !aligned8(kbar)) ||
+        (r0bar && !aligned8(r0bar)) || !aligned8(v_np1) || !aligned8(vbar))
+        return MB_ERR_INVALID;
+    if (sp->device != g->device) return MB_ERR_INVALID;
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    const size_t nf = (size_t)3 * g->N;
+    const size_t nbl = (size_t)3 * std::max<int64_t>(g->d.max_blobs, 1);
+    if (!g->d_adj) {
+        // scratch of the reverse step: fields wbar, fbar, zero; blob arrays
+        // ubar, F, Fbar
+        e = hipMalloc(&g->d_adj, (3 * nf + 3 * nbl) * sizeof(double));
+        if (e == hipSuccess) e = hipMemset(g->d_adj, 0, (3 * nf + 3 * nbl) * sizeof(double));
+        if (e != hipSuccess) {
+            if (g->d_adj) (void)hipFree(g->d_adj);
+            g->d_adj = nullptr;
+            return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
+        }
+    }
+    double* wbar = g->d_adj;
+    double* fbar = wbar + nf;
+    const double* zero = fbar + nf;  // never written after the allocation
+    double* ubar = wbar + 3 * nf;
+    double* F = ubar + nbl;
+    double* Fbar = F + nbl;
+    const double h = g->d.h;
+    const double h3 = h * h * h;
+    const SpringsDev sd = springs_dev(sp);
+    const double* vn1 = (const double*)v_np1;
+    double* vb = (double*)vbar;
+    // q^{n+1} = q^n + dt u^n:  ubar = ubar_loss + dt qbar
+    e = blob_axpy(3 * M, ubar_loss, g->d.dt, qbar, ubar, s);
+    // records of q^n carrying ubar (scale 1: h^3 S ubar = J^T ubar)
+    if (e == hipSuccess) e = bin_blobs<double>(g, M, q_n, s);
+    if (e == hipSuccess) e = scatter_records<double>(g, M, q_n, ubar, s, 1.0);
+    // u^n = J(q^n) v^{n+1}: position part
+    if (e == hipSuccess && M > 0) e = interpolate_grad<double>(g, vn1, ubar, 1.0, qbar, s);
+    // wbar = vbar + J^T ubar
+    if (e == hipSuccess) e = spread_boxes<double>(g, s);
+    if (e == hipSuccess) e = fold_boxes<double>(g, wbar, s, vb);
+    // v^{n+1} = Q (C v^n + f^n): fbar = Q wbar, vbar = C Q wbar (Q and C
+    // commute; steady: vbar = 0)
+    if (e == hipSuccess) e = fluid_solve<double>(g, zero, wbar, fbar, s);
+    if (e == hipSuccess) {
+        if (g->d.mode == MB_STEADY_STOKES) e = hipMemsetAsync(vb, 0, nf * sizeof(double), s);
+        else e = apply_cn<double>(g, fbar, vb, s);
+    }
+    // F^n = springs(q^n) + Fext/nb + G
+    if (e == hipSuccess) e = spring_forces(sd, P, q_n, Fext, F, s, g, F_blob);
+    // f^n = S(q^n) F^n: Fbar = h^-3 J fbar, and the position part
+    if (e == hipSuccess && M > 0)
+        e = interpolate<double>(g, M, fbar, Fbar, nullptr, 0, s, 1.0 / h3);
+    if (e == hipSuccess && M > 0) e = interpolate_grad<double>(g, fbar, F, 1.0 / h3, qbar, s);
+    // springs: qbar, kbar, r0bar; the blob forces: Fblob_bar += Fbar
+    if (e == hipSuccess) e = springs_adjoint(sd, P, q_n, Fbar, qbar, kbar, r0bar, s, g);
+    if (e == hipSuccess && Fblob_bar) e = blob_add(3 * M, Fbar, Fblob_bar, s);
     return from_hip(e);
 }
 

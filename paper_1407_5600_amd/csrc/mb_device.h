@@ -51,6 +51,22 @@ __device__ __forceinline__ void kernel_weights(T t, T w[3]) {
     w[0] = (T(2) - T(3) * t - s) * sixth;
 }
 
+// The weights and their derivatives with respect to t: d/dt Phi(t) =
+// -t/s, d/dt Phi(1 -+ t) = +-1/2 + t/(2s) (Phi is C^1, s >= 1/2 on
+// [-1/2, 1/2]).
+template <typename T>
+__device__ __forceinline__ void kernel_weights_deriv(T t, T w[3], T dw[3]) {
+    const T s = sqrt(T(1) - T(3) * t * t);
+    const T sixth = T(1) / T(6);
+    w[1] = (T(1) + s) * (T(1) / T(3));
+    w[2] = (T(2) + T(3) * t - s) * sixth;
+    w[0] = (T(2) - T(3) * t - s) * sixth;
+    const T r = t / (T(2) * s);
+    dw[1] = -T(2) * r;
+    dw[2] = T(0.5) + r;
+    dw[0] = -T(0.5) + r;
+}
+
 // ---------------------------------------------------------------------------
 // Radix-R DFT of R values in registers: y_k = sum_r v_r W_R^{rk} with
 // W_R = exp(-2 pi i / R) (forward) or its conjugate (inverse).

@@ -30,6 +30,8 @@ enum KernelId : int {
     K_U0,
     K_DIAG,
     K_FOLD,
+    K_INTERP_GRAD,
+    K_SPRINGS_ADJ,
     K_NUM
 };
 
@@ -102,6 +104,7 @@ struct mb_grid {
     mb::Tiles tiles;
     void* d_box;           // [3][tiles][box nodes] spread boxes of the step
     double* d_u;           // [max_blobs][3] blob velocities of the last step
+    double* d_adj;         // reverse-step scratch (allocated on first use)
     double* d_tile_part;   // [tiles][4]  (sum v_a, max |Dv|)
     double* d_force_part;  // [force blocks][3]
     int force_blocks_cap;
@@ -135,20 +138,35 @@ int fft_x_blocks(int L, int precision);
 // returns hipSuccess or the launch error.
 template <typename T>
 hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s);
+// Records of the binned blobs with forces F scaled by fscale (h^-3 when
+// fscale <= 0: a force density).
 template <typename T>
 hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
-                           const double* F, hipStream_t s);
+                           const double* F, hipStream_t s, double fscale = 0.0);
 template <typename T>
 hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
-                           const double* q, const double* Fext, hipStream_t s);
+                           const double* q, const double* Fext, hipStream_t s,
+                           const double* Gblob = nullptr);
 hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
                          const double* Fext, double* F, hipStream_t s,
-                         mb_grid* timing_grid);
+                         mb_grid* timing_grid, const double* Gblob = nullptr);
+// qbar += (dF/dq)^T Fbar; kbar, r0bar (nullable) accumulate the k and rest
+// length parts.
+hipError_t springs_adjoint(const SpringsDev& sp, int64_t P, const double* q,
+                           const double* Fbar, double* qbar, double* kbar,
+                           double* r0bar, hipStream_t s, mb_grid* timing_grid);
+// out = (a ? a : 0) + sc b; y += x (n doubles).
+hipError_t blob_axpy(int64_t n, const double* a, double sc, const double* b, double* out,
+                     hipStream_t s);
+hipError_t blob_add(int64_t n, const double* x, double* y, hipStream_t s);
+// y = (rho/dt) x + (eta/2) L_h x (explicit half of Crank-Nicolson).
+template <typename T>
+hipError_t apply_cn(mb_grid* g, const T* x, T* y, hipStream_t s);
 // Spreading into the per-tile boxes (g->d_box), and the field from them.
 template <typename T>
 hipError_t spread_boxes(mb_grid* g, hipStream_t s);
 template <typename T>
-hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s);
+hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s, const T* add = nullptr);
 // Fluid solve; the force is f, or the boxes of the last spreading when
 // boxed is set (f unused).
 template <typename T>
@@ -158,7 +176,11 @@ hipError_t fluid_solve(mb_grid* g, const T* v_in, const T* f, T* v_out,
 size_t box_elems(const Tiles& t);
 template <typename T>
 hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
-                       double* q_update, int diag, hipStream_t s);
+                       double* q_update, int diag, hipStream_t s, double uscale = 1.0);
+// gout += wscale sum_a W_a grad_q (J v)_a per blob, on the binned records.
+template <typename T>
+hipError_t interpolate_grad(mb_grid* g, const T* v, const double* W, double wscale,
+                            double* gout, hipStream_t s);
 hipError_t particle_means(mb_grid* g, int64_t P, int nb, const double* u,
                           double* U0, hipStream_t s);
 hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,

@@ -243,11 +243,11 @@ k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
 
 // Spring forces of the sp.ppb particles of a block (float64), in two
 // parts.  springs_stage loads the blob positions and the incidence lists
-// into LDS (and each blob's share Fext_p / nb of its particle's force into
-// registers); springs_forces then has thread j (< nblob) sum over the pairs
+// into LDS (and each blob's external force, its share Fext_p / nb of its
+// particle's force plus its own G_i, into registers); springs_forces then has thread j (< nblob) sum over the pairs
 // incident to its blob the pair force on it, k (|d| - r0) d / |d| with
 // d = q_other - q_self (the two blobs of a pair get exactly opposite
-// forces), plus Fext_p / nb.
+// forces), plus the external force.
 struct SpringsBlk {
     int64_t p0;    // first particle
     int npart;     // particles of the block
@@ -260,6 +260,7 @@ struct SpringsBlk {
 __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
                                                     const double* __restrict__ q,
                                                     const double* __restrict__ Fext,
+                                                    const double* __restrict__ Gblob,
                                                     int64_t P, double* smem,
                                                     double fe[3]) {
     SpringsBlk B;
@@ -287,6 +288,12 @@ __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
         fe[0] = f[0] * inv_nb;
         fe[1] = f[1] * inv_nb;
         fe[2] = f[2] * inv_nb;
+    }
+    if (Gblob && (int)threadIdx.x < B.nblob) {
+        const double* gb = Gblob + 3 * (B.p0 * nb + threadIdx.x);
+        fe[0] += gb[0];
+        fe[1] += gb[1];
+        fe[2] += gb[2];
     }
     for (int e = threadIdx.x; e < np; e += BLK) B.r0s[e] = sp.r0[e];
     for (int e = threadIdx.x; e <= nb; e += BLK) B.adj[e] = sp.adj_start[e];
@@ -339,7 +346,8 @@ __device__ __forceinline__ void springs_forces(const SpringsDev& sp, const Sprin
 template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
-                  const double* __restrict__ Fext, int64_t P, double h, int L,
+                  const double* __restrict__ Fext, const double* __restrict__ Gblob,
+                  int64_t P, double h, int L,
                   double inv_vol, const int* __restrict__ offs,
                   const int* __restrict__ tile_of, const int* __restrict__ rank,
                   Rec<T>* __restrict__ rec, int* __restrict__ perm,
@@ -356,7 +364,7 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
         rk = rank[ib];
     }
     double fe[3];
-    const SpringsBlk B = springs_stage(sp, q, Fext, P, smem, fe);
+    const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe);
     const int off = own ? offs[tl] : 0;
     double F[3];
     int64_t i;
@@ -376,10 +384,11 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
 
 __global__ void __launch_bounds__(BLK)
 k_springs(SpringsDev sp, const double* __restrict__ q,
-          const double* __restrict__ Fext, int64_t P, double* __restrict__ Fout) {
+          const double* __restrict__ Fext, const double* __restrict__ Gblob, int64_t P,
+          double* __restrict__ Fout) {
     extern __shared__ double smem[];
     double fe[3];
-    const SpringsBlk B = springs_stage(sp, q, Fext, P, smem, fe);
+    const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe);
     double F[3];
     int64_t i;
     springs_forces(sp, B, fe, F, &i);
@@ -387,6 +396,112 @@ k_springs(SpringsDev sp, const double* __restrict__ q,
     Fout[3 * i] = F[0];
     Fout[3 * i + 1] = F[1];
     Fout[3 * i + 2] = F[2];
+}
+
+// Transposed Jacobian of the spring forces applied to Fbar (float64).  For
+// blob i and each incident pair with other blob o, d = q_o - q_i, the pair
+// force on i is k (1 - r0/|d|) d with the symmetric Jacobian
+// J(d) = k [(1 - r0/|d|) I + r0 d d^T / |d|^3]; since F_i depends on q_i
+// through -J and F_o through +J, qbar_i += sum_o J(d) (Fbar_o - Fbar_i).
+// Per blob also kbar += Fbar_i . (1 - r0/|d|) d and r0bar_e += -k Fbar_i .
+// d/|d| (both ends of a pair together give the pair's full term); the block
+// sums these in LDS and adds them to kbar / r0bar with one float64 atomic
+// per entry (their order, hence the last bits, may vary run to run).
+__global__ void __launch_bounds__(BLK)
+k_springs_adjoint(SpringsDev sp, const double* __restrict__ q,
+                  const double* __restrict__ Fbar, int64_t P,
+                  double* __restrict__ qbar, double* __restrict__ kbar,
+                  double* __restrict__ r0bar) {
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    double fe[3];
+    const SpringsBlk B = springs_stage(sp, q, nullptr, nullptr, P, smem, fe);
+    // Fbar of the block's blobs and the per-pair sums after the positions
+    double* fb = B.qs + 3 * sp.ppb * sp.nb + sp.npairs + 
+                 (sp.nb + 1 + 2 * sp.npairs + 1) / 2;
+    double* rb = fb + 3 * sp.ppb * sp.nb;
+    const int nb = sp.nb;
+    for (int i = threadIdx.x; i < 3 * B.nblob; i += BLK) fb[i] = Fbar[3 * B.p0 * nb + i];
+    for (int e = threadIdx.x; e < sp.npairs; e += BLK) rb[e] = 0.0;
+    __syncthreads();
+    double kb = 0.0;
+    const int j = threadIdx.x;
+    if (j < B.nblob) {
+        const int pl = j / nb;
+        const int b = j - pl * nb;
+        const double* qp = B.qs + 3 * pl * nb;
+        const double* fp = fb + 3 * pl * nb;
+        const double qx = qp[3 * b], qy = qp[3 * b + 1], qz = qp[3 * b + 2];
+        const double fx = fp[3 * b], fy = fp[3 * b + 1], fz = fp[3 * b + 2];
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        const int* inc = B.adj + nb + 1;
+        const int e1 = B.adj[b + 1];
+        for (int x = B.adj[b]; x < e1; ++x) {
+            const int code = inc[x];
+            const int o = code & 0xff;
+            const int e = code >> 8;
+            const double dx = qp[3 * o] - qx, dy = qp[3 * o + 1] - qy, dz = qp[3 * o + 2] - qz;
+            const double len = sqrt(dx * dx + dy * dy + dz * dz);
+            const double r0 = B.r0s[e];
+            const double sc = sp.k * (1.0 - r0 / len);
+            const double tc = sp.k * r0 / (len * len * len);
+            const double lx = fp[3 * o] - fx, ly = fp[3 * o + 1] - fy, lz = fp[3 * o + 2] - fz;
+            const double ld = lx * dx + ly * dy + lz * dz;
+            gx += sc * lx + tc * dx * ld;
+            gy += sc * ly + tc * dy * ld;
+            gz += sc * lz + tc * dz * ld;
+            const double fd = fx * dx + fy * dy + fz * dz;
+            kb += fd * (1.0 - r0 / len);
+            atomicAdd(&rb[e], -sp.k * fd / len);
+        }
+        double* qo = qbar + 3 * (B.p0 * nb + j);
+        qo[0] += gx;
+        qo[1] += gy;
+        qo[2] += gz;
+    }
+    const double kt = block_reduce<false>(kb, red);  // also orders the LDS sums
+    if (threadIdx.x == 0 && kbar) atomicAdd(kbar, kt);
+    if (r0bar)
+        for (int e = threadIdx.x; e < sp.npairs; e += BLK)
+            if (rb[e] != 0.0) atomicAdd(&r0bar[e], rb[e]);
+}
+
+// Blob arrays: out = (a ? a : 0) + s b, and y += x, over n entries.
+__global__ void __launch_bounds__(BLK)
+k_axpy(int64_t n, const double* __restrict__ a, double s, const double* __restrict__ b,
+       double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) out[i] = (a ? a[i] : 0.0) + s * b[i];
+}
+
+__global__ void __launch_bounds__(BLK)
+k_add(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) y[i] += x[i];
+}
+
+// y = c0 x + c1 L_h x per component (7-point periodic Laplacian without the
+// 1/h^2, folded into c1): the explicit half of the Crank-Nicolson step.
+template <typename T>
+__global__ void __launch_bounds__(BLK)
+k_apply_cn(int L, T c0, T c1, const T* __restrict__ x, T* __restrict__ y) {
+    const int64_t N = (int64_t)L * L * L;
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i >= 3 * N) return;
+    const int64_t cb = (i / N) * N;
+    const int64_t r = i - cb;
+    const int xx = (int)(r % L), yy = (int)((r / L) % L), zz = (int)(r / ((int64_t)L * L));
+    const int xm = xx == 0 ? L - 1 : xx - 1, xp = xx == L - 1 ? 0 : xx + 1;
+    const int ym = yy == 0 ? L - 1 : yy - 1, yp = yy == L - 1 ? 0 : yy + 1;
+    const int zm = zz == 0 ? L - 1 : zz - 1, zp = zz == L - 1 ? 0 : zz + 1;
+    const T* X = x + cb;
+    const int64_t row = ((int64_t)zz * L + yy) * L;
+    const T c = X[row + xx];
+    const T lap = (X[row + xm] + X[row + xp]) +
+                  (X[((int64_t)zz * L + ym) * L + xx] + X[((int64_t)zz * L + yp) * L + xx]) +
+                  (X[((int64_t)zm * L + yy) * L + xx] + X[((int64_t)zp * L + yy) * L + xx]) -
+                  T(6) * c;
+    y[i] = c0 * c + c1 * lap;
 }
 
 // ---------------------------------------------------------------------------
@@ -569,10 +684,12 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
     }
 }
 
-// The field from the boxes (the spreading call of the library).
+// The field from the boxes (the spreading call of the library), plus an
+// optional field `add`.
 template <typename T>
 __global__ void __launch_bounds__(BLK)
-k_fold(const T* __restrict__ E, int L, Tiles tl, T* __restrict__ f) {
+k_fold(const T* __restrict__ E, int L, Tiles tl, const T* __restrict__ add,
+       T* __restrict__ f) {
     const int64_t N = (int64_t)L * L * L;
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (i >= 3 * N) return;
@@ -581,7 +698,8 @@ k_fold(const T* __restrict__ E, int L, Tiles tl, T* __restrict__ f) {
     const int x = (int)(rem % L);
     const int y = (int)((rem / L) % L);
     const int z = (int)(rem / ((int64_t)L * L));
-    f[i] = box_sum(E, tl, a, x, y, z);
+    const T val = box_sum(E, tl, a, x, y, z);
+    f[i] = add ? val + add[i] : val;
 }
 
 // Interpolation: one block per tile.  The velocity on nodes [lo-1, hi+2]
@@ -590,13 +708,14 @@ k_fold(const T* __restrict__ E, int L, Tiles tl, T* __restrict__ f) {
 // float64 ones (LDS size); then every record of the tile's cells gathers its
 // 27 nodes per component.  u (and the move of the blob by dt u) is written
 // once per blob for each thread's first record, per component for the rest
-// (tiles with more records than threads).  With part the block also writes
-// its float64 sum of each component and the max |Dv| over its cells.
+// (tiles with more records than threads), scaled by uscale.  With part the
+// block also writes its float64 sum of each component and the max |Dv| over
+// its cells.
 template <typename T, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
 k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
          const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
-         double* __restrict__ u_out, double* __restrict__ q, double dt,
+         double* __restrict__ u_out, double uscale, double* __restrict__ q, double dt,
          double inv_h, double* __restrict__ part) {
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
     constexpr int EV = EX * EY * EZ;
@@ -687,7 +806,7 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
                         acc += (w[2][oz] * w[1][oy]) * sxv;
                     }
                 }
-                ua[c] = (double)acc;
+                ua[c] = uscale * (double)acc;
             }
             if (k < BLK) {
 #pragma unroll
@@ -745,6 +864,106 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
         }
         const double m = block_reduce<true>(dmax, red);
         if (threadIdx.x == 0) part[4 * tile + 3] = m;
+    }
+}
+
+// Position derivative of the interpolation, contracted with blob weights:
+// g_i += wscale sum_a W_{i,a} grad_{q_i} (J_i v)_a.  One block per tile as in
+// k_interp (same staged field, one component at a time); per record and
+// component the 27-node gather also forms the three derivative sums, with
+// d/dq_b of a weight = (1/h) d/dt of it (kernel_weights_deriv).  W and g are
+// indexed by blob; each blob belongs to one record, so g is updated without
+// atomics.
+template <typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(BLK)
+k_interp_grad(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
+              const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
+              const double* __restrict__ W, double wscale, double inv_h,
+              double* __restrict__ gout) {
+    constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
+    constexpr int EV = EX * EY * EZ;
+    constexpr int RP = BLK / EX;
+    constexpr int NR = (EY * EZ + RP - 1) / RP;
+    __shared__ T vt[EV];
+    __shared__ int rowoff[EY * EZ];
+    const TileBox tb = tile_box(tl, L);
+    const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
+    const int N = L * L * L;
+    for (int r = threadIdx.x; r < EY * EZ; r += BLK) {
+        const int ey = r % EY, ez = r / EY;
+        rowoff[r] = (wrapL(tb.lo[2] - 1 + ez, L) * L + wrapL(tb.lo[1] - 1 + ey, L)) * L;
+    }
+    const int first = offs[tile];
+    const int total = offs[tile + 1] - first;
+    const int sx = threadIdx.x % EX;
+    const int sr = threadIdx.x / EX;
+    const int gx = wrapL(tb.lo[0] - 1 + sx, L);
+    __syncthreads();
+    for (int k0 = 0; k0 < total; k0 += BLK) {
+        const int k = k0 + threadIdx.x;
+        const bool has = k < total;
+        Rec<T> r{};
+        int64_t i = 0;
+        double wgt[3] = {0.0, 0.0, 0.0};
+        if (has) {
+            r = rec[first + k];
+            i = perm[first + k];
+            wgt[0] = W[3 * i];
+            wgt[1] = W[3 * i + 1];
+            wgt[2] = W[3 * i + 2];
+        }
+        double gr[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a) {
+            __syncthreads();  // the previous component's gathers are done
+            if (sr < RP) {
+                const T* va = v + (int64_t)a * N + gx;
+                T ld[NR];
+#pragma unroll
+                for (int kk = 0; kk < NR; ++kk) {
+                    const int rr = sr + kk * RP;
+                    ld[kk] = va[rowoff[rr < EY * EZ ? rr : sr]];
+                }
+#pragma unroll
+                for (int kk = 0; kk < NR; ++kk) {
+                    const int rr = sr + kk * RP;
+                    if (rr < EY * EZ) vt[rr * EX + sx] = ld[kk];
+                }
+            }
+            __syncthreads();
+            if (!has) continue;
+            T w[3][3], dw[3][3];
+            int e0[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                kernel_weights_deriv<T>(a == b ? r.ts[b] : r.tu[b], w[b], dw[b]);
+                const int cc = (int)((r.cell >> (9 * b)) & 511u) - tb.lo[b];
+                const int up = (int)((r.cell >> (27 + b)) & 1u);
+                e0[b] = a == b ? cc : cc + up;
+            }
+            const T* base = vt + (e0[2] * EY + e0[1]) * EX + e0[0];
+            T dx = T(0), dy = T(0), dz = T(0);
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz) {
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy) {
+                    const T* row = base + (oz * EY + oy) * EX;
+                    const T sxv = w[0][0] * row[0] + w[0][1] * row[1] + w[0][2] * row[2];
+                    const T dsx = dw[0][0] * row[0] + dw[0][1] * row[1] + dw[0][2] * row[2];
+                    dx += (w[2][oz] * w[1][oy]) * dsx;
+                    dy += (w[2][oz] * dw[1][oy]) * sxv;
+                    dz += (dw[2][oz] * w[1][oy]) * sxv;
+                }
+            }
+            const double c = wscale * inv_h * wgt[a];
+            gr[0] += c * (double)dx;
+            gr[1] += c * (double)dy;
+            gr[2] += c * (double)dz;
+        }
+        if (has) {
+            gout[3 * i] += gr[0];
+            gout[3 * i + 1] += gr[1];
+            gout[3 * i + 2] += gr[2];
+        }
     }
 }
 
@@ -808,11 +1027,12 @@ hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
 
 template <typename T>
 hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
-                           const double* F, hipStream_t s) {
+                           const double* F, hipStream_t s, double fscale) {
     if (M == 0) return hipSuccess;
     const double h = g->d.h;
+    const double sc = fscale > 0.0 ? fscale : 1.0 / (h * h * h);
     MB_LAUNCH(g, K_BIN_SCATTER, s, k_bin_scatter<T>, blocks_for(M), BLK, 0, q, F,
-              M, h, g->L, 1.0 / (h * h * h), g->d_offs, g->d_tile, g->d_rank,
+              M, h, g->L, sc, g->d_offs, g->d_tile, g->d_rank,
               (Rec<T>*)g->d_rec, g->d_perm);
     g->perm_m = M;
     return hipGetLastError();
@@ -820,12 +1040,13 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
 
 template <typename T>
 hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
-                           const double* q, const double* Fext, hipStream_t s) {
+                           const double* q, const double* Fext, hipStream_t s,
+                           const double* Gblob) {
     const int64_t M = P * sp.nb;
     if (M == 0) return hipSuccess;
     const double h = g->d.h;
     MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, springs_blocks(sp, P), BLK,
-              springs_lds(sp), sp, q, Fext, P, h, g->L, 1.0 / (h * h * h), g->d_offs,
+              springs_lds(sp), sp, q, Fext, Gblob, P, h, g->L, 1.0 / (h * h * h), g->d_offs,
               g->d_tile, g->d_rank, (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part);
     g->perm_m = M;
     return hipGetLastError();
@@ -833,13 +1054,53 @@ hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
 
 hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
                          const double* Fext, double* F, hipStream_t s,
-                         mb_grid* tg) {
+                         mb_grid* tg, const double* Gblob) {
     const int64_t M = P * sp.nb;
     if (M == 0) return hipSuccess;
     MB_LAUNCH(tg, K_SPRINGS, s, k_springs, springs_blocks(sp, P), BLK, springs_lds(sp),
-              sp, q, Fext, P, F);
+              sp, q, Fext, Gblob, P, F);
     return hipGetLastError();
 }
+
+size_t springs_adjoint_lds(const SpringsDev& sp) {
+    return springs_lds(sp) + (size_t)(3 * sp.ppb * sp.nb + sp.npairs) * sizeof(double) +
+           sizeof(double);
+}
+
+hipError_t springs_adjoint(const SpringsDev& sp, int64_t P, const double* q,
+                           const double* Fbar, double* qbar, double* kbar,
+                           double* r0bar, hipStream_t s, mb_grid* tg) {
+    const int64_t M = P * sp.nb;
+    if (M == 0) return hipSuccess;
+    MB_LAUNCH(tg, K_SPRINGS_ADJ, s, k_springs_adjoint, springs_blocks(sp, P), BLK,
+              springs_adjoint_lds(sp), sp, q, Fbar, P, qbar, kbar, r0bar);
+    return hipGetLastError();
+}
+
+hipError_t blob_axpy(int64_t n, const double* a, double sc, const double* b, double* out,
+                     hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n)), dim3(BLK), 0, s, n, a, sc, b, out);
+    return hipGetLastError();
+}
+
+hipError_t blob_add(int64_t n, const double* x, double* y, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(BLK), 0, s, n, x, y);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t apply_cn(mb_grid* g, const T* x, T* y, hipStream_t s) {
+    const double h = g->d.h;
+    const T c0 = (T)(g->d.rho / g->d.dt);
+    const T c1 = (T)(0.5 * g->d.eta / (h * h));
+    hipLaunchKernelGGL(k_apply_cn<T>, dim3(blocks_for(3 * g->N)), dim3(BLK), 0, s, g->L, c0,
+                       c1, x, y);
+    return hipGetLastError();
+}
+template hipError_t apply_cn<float>(mb_grid*, const float*, float*, hipStream_t);
+template hipError_t apply_cn<double>(mb_grid*, const double*, double*, hipStream_t);
 
 int springs_blocks(const SpringsDev& sp, int64_t P) {
     return (int)((P + sp.ppb - 1) / sp.ppb);
@@ -867,30 +1128,49 @@ hipError_t spread_boxes(mb_grid* g, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s) {
+hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s, const T* add) {
     MB_LAUNCH(g, K_FOLD, s, k_fold<T>, blocks_for(3 * g->N), BLK, 0,
-              (const T*)g->d_box, g->L, g->tiles, f);
+              (const T*)g->d_box, g->L, g->tiles, add, f);
     return hipGetLastError();
 }
 
 template <typename T, int TX>
-static void launch_interp(mb_grid* g, const T* v, double* u_out, double* q,
-                          double* part, int kid, hipStream_t s) {
+static void launch_interp(mb_grid* g, const T* v, double* u_out, double uscale,
+                          double* q, double* part, int kid, hipStream_t s) {
     MB_LAUNCH(g, kid, s, (k_interp<T, TX, 8, 8>), g->tiles.n, BLK, 0,
               (const Rec<T>*)g->d_rec, g->d_perm, g->d_offs, g->L, g->tiles, v,
-              u_out, q, g->d.dt, 1.0 / g->d.h, part);
+              u_out, uscale, q, g->d.dt, 1.0 / g->d.h, part);
 }
 
 template <typename T>
 hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
-                       double* q_update, int diag, hipStream_t s) {
+                       double* q_update, int diag, hipStream_t s, double uscale) {
     (void)M;
     double* part = diag ? g->d_tile_part : nullptr;
     const int kid = q_update ? K_INTERP_STEP : K_INTERP;
     switch (g->tiles.tx) {
-        case 32: launch_interp<T, 32>(g, v, u_out, q_update, part, kid, s); break;
-        case 16: launch_interp<T, 16>(g, v, u_out, q_update, part, kid, s); break;
-        default: launch_interp<T, 8>(g, v, u_out, q_update, part, kid, s); break;
+        case 32: launch_interp<T, 32>(g, v, u_out, uscale, q_update, part, kid, s); break;
+        case 16: launch_interp<T, 16>(g, v, u_out, uscale, q_update, part, kid, s); break;
+        default: launch_interp<T, 8>(g, v, u_out, uscale, q_update, part, kid, s); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int TX>
+static void launch_interp_grad(mb_grid* g, const T* v, const double* W, double wscale,
+                               double* gout, hipStream_t s) {
+    MB_LAUNCH(g, K_INTERP_GRAD, s, (k_interp_grad<T, TX, 8, 8>), g->tiles.n, BLK, 0,
+              (const Rec<T>*)g->d_rec, g->d_perm, g->d_offs, g->L, g->tiles, v, W, wscale,
+              1.0 / g->d.h, gout);
+}
+
+template <typename T>
+hipError_t interpolate_grad(mb_grid* g, const T* v, const double* W, double wscale,
+                            double* gout, hipStream_t s) {
+    switch (g->tiles.tx) {
+        case 32: launch_interp_grad<T, 32>(g, v, W, wscale, gout, s); break;
+        case 16: launch_interp_grad<T, 16>(g, v, W, wscale, gout, s); break;
+        default: launch_interp_grad<T, 8>(g, v, W, wscale, gout, s); break;
     }
     return hipGetLastError();
 }
@@ -915,16 +1195,18 @@ hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,
 // Explicit instantiations.
 template hipError_t bin_blobs<float>(mb_grid*, int64_t, const double*, hipStream_t);
 template hipError_t bin_blobs<double>(mb_grid*, int64_t, const double*, hipStream_t);
-template hipError_t scatter_records<float>(mb_grid*, int64_t, const double*, const double*, hipStream_t);
-template hipError_t scatter_records<double>(mb_grid*, int64_t, const double*, const double*, hipStream_t);
-template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t);
-template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t);
+template hipError_t scatter_records<float>(mb_grid*, int64_t, const double*, const double*, hipStream_t, double);
+template hipError_t scatter_records<double>(mb_grid*, int64_t, const double*, const double*, hipStream_t, double);
+template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*);
+template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*);
 template hipError_t spread_boxes<float>(mb_grid*, hipStream_t);
 template hipError_t spread_boxes<double>(mb_grid*, hipStream_t);
-template hipError_t fold_boxes<float>(mb_grid*, float*, hipStream_t);
-template hipError_t fold_boxes<double>(mb_grid*, double*, hipStream_t);
-template hipError_t interpolate<float>(mb_grid*, int64_t, const float*, double*, double*, int, hipStream_t);
-template hipError_t interpolate<double>(mb_grid*, int64_t, const double*, double*, double*, int, hipStream_t);
+template hipError_t fold_boxes<float>(mb_grid*, float*, hipStream_t, const float*);
+template hipError_t fold_boxes<double>(mb_grid*, double*, hipStream_t, const double*);
+template hipError_t interpolate<float>(mb_grid*, int64_t, const float*, double*, double*, int, hipStream_t, double);
+template hipError_t interpolate<double>(mb_grid*, int64_t, const double*, double*, double*, int, hipStream_t, double);
+template hipError_t interpolate_grad<float>(mb_grid*, const float*, const double*, double, double*, hipStream_t);
+template hipError_t interpolate_grad<double>(mb_grid*, const double*, const double*, double, double*, hipStream_t);
 
 size_t box_elems(const Tiles& t) {
     return (size_t)3 * t.n * (t.tx + 3) * (t.ty + 3) * (t.tz + 3);

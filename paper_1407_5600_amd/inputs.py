@@ -302,11 +302,21 @@ def pair(seed: int = 3, L: int = 32, sep: float | None = None) -> Workload:
 
 
 def diff(seed: int = 4) -> Workload:
-    """64^3 box with 16 particles placed by random sequential addition."""
+    """Differentiation case: 64^3 box, 16 particles placed by random
+    sequential addition, 100 steps of dt = 0.01; per-particle forces N(0, 1)
+    (split over the blobs as the initial per-blob forces) and target
+    velocities V ~ N(0, 0.1^2) per component (extra["V"]); the centres and
+    rotations are in extra so the template can be rescaled."""
     rng = np.random.default_rng(seed)
     c = rsa_centres(rng, 64.0, 16)
     F = rng.standard_normal((16, 3))
-    return _make("diff", 64, c, rng, True, F, 100)
+    R = random_rotations(rng, 16)
+    V = 0.1 * rng.standard_normal((16, 3))
+    tmpl = icosahedron_template(1.0)
+    pa, pb, r0 = pair_table(tmpl)
+    q = place_particles(c, tmpl, R)
+    return Workload("diff", 64, 1.0, 1.0, 1.0, 0.01, 100, q, F, tmpl.shape[0], pa, pb, r0,
+                    100.0, tmpl, {"centres": c, "rotations": R, "V": V})
 
 
 def random_suspension(seed: int, L: int, P: int, phi_cap: float = 0.3,
