@@ -102,6 +102,18 @@ typedef struct mb_springs mb_springs; /* opaque; owns the pair table */
  * scratch.  *out is set to NULL on error. */
 mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out);
 
+/* A grid holding a batch of nbox independent periodic boxes of the same
+ * description (1 <= nbox <= 65536), each call advancing all of them in one
+ * launch per kernel: the pair-mobility sweeps of the paper's lubrication and
+ * pass-by set-ups run many small boxes at once.  Layouts in every call on
+ * such a grid: fields [nbox][3][L][L][L]; blob arrays [nbox * Mb][3] with
+ * box b holding blobs b*Mb .. b*Mb+Mb-1 (the same Mb in every box; calls
+ * reject M not divisible by nbox); particle arrays likewise (P divisible by
+ * nbox).  max_blobs counts the blobs of all boxes.  Diagnostics of mb_step
+ * sum over the boxes.  mb_grid_create is the case nbox = 1. */
+mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox,
+                               mb_grid** out);
+
 /* Release a grid (synchronises its device first).  NULL is accepted. */
 mb_status mb_grid_destroy(mb_grid* grid);
 
@@ -171,6 +183,20 @@ mb_status mb_spring_forces_ext(const mb_springs* springs, int64_t nparticles,
                                const double* q, const double* Fext,
                                const double* F_blob, double* F_out,
                                void* stream);
+
+/* nsteps steps of each of ngrids grids (as mb_step_ext, no per-step
+ * outputs), with one step of every grid captured once into a HIP graph and
+ * the graph launched nsteps times on a private stream ordered after
+ * `stream`; returns when the steps are done.  Launch-bound workloads (many
+ * small boxes, several size classes) then pay one graph launch per step.
+ * Arrays per grid as in mb_step_ext (Fext and F_blob entries may be NULL).
+ * Grids with no blobs are allowed; timing hooks are off during the capture. */
+mb_status mb_step_graph(int32_t ngrids, mb_grid* const* grids,
+                        const mb_springs* const* springs,
+                        const int64_t* nparticles, double* const* q,
+                        void* const* v, const double* const* Fext,
+                        const double* const* F_blob, int32_t nsteps,
+                        void* stream);
 
 /* ---- Derivatives (reverse mode) of the step, for gradients of losses over
  * trajectories.  They use that J and S are each other's adjoints (Sec.

@@ -54,6 +54,8 @@ def lib():
         vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         sig = {
             "mb_grid_create": ([ctypes.POINTER(GridDesc), ctypes.POINTER(vp)], i32),
+            "mb_grid_create_batch": ([ctypes.POINTER(GridDesc), i32, ctypes.POINTER(vp)], i32),
+            "mb_step_graph": ([i32, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
             "mb_grid_destroy": ([vp], i32),
             "mb_springs_create": ([i32, i32, vp, vp, vp, d, ctypes.POINTER(vp)], i32),
             "mb_springs_destroy": ([vp], i32),
@@ -85,7 +87,8 @@ EXPORTED = ("mb_grid_create", "mb_grid_destroy", "mb_springs_create",
             "mb_springs_destroy", "mb_spread", "mb_interpolate", "mb_fluid_solve",
             "mb_spring_forces", "mb_step", "mb_status_string", "mb_grid_set_timing",
             "mb_grid_kernel_times", "mb_kernel_name", "mb_step_ext", "mb_spring_forces_ext",
-            "mb_interpolate_grad", "mb_spring_adjoint", "mb_step_adjoint")
+            "mb_interpolate_grad", "mb_spring_adjoint", "mb_step_adjoint",
+            "mb_grid_create_batch", "mb_step_graph")
 
 
 def status_string(st: int) -> str:
@@ -159,15 +162,21 @@ class Grid:
     """A periodic MAC grid with its FFT tables and scratch (mb_grid_create)."""
 
     def __init__(self, L, h=1.0, rho=1.0, eta=1.0, dt=0.01, precision="fp64",
-                 mode="unsteady", zero_mean=False, max_blobs=0):
+                 mode="unsteady", zero_mean=False, max_blobs=0, nbox=1):
         import torch
         prec = {"fp64": MB_FP64, "mixed": MB_MIXED}[precision]
         md = {"unsteady": MB_UNSTEADY_CN, "steady": MB_STEADY_STOKES}[mode]
         self.desc = GridDesc(int(L), prec, md, int(bool(zero_mean)), float(h), float(rho),
                              float(eta), float(dt), int(max_blobs))
         h_ = ctypes.c_void_p()
-        _check(lib().mb_grid_create(ctypes.byref(self.desc), ctypes.byref(h_)), "mb_grid_create")
+        if nbox == 1:
+            _check(lib().mb_grid_create(ctypes.byref(self.desc), ctypes.byref(h_)),
+                   "mb_grid_create")
+        else:
+            _check(lib().mb_grid_create_batch(ctypes.byref(self.desc), int(nbox),
+                                              ctypes.byref(h_)), "mb_grid_create_batch")
         self.handle = h_
+        self.nbox = int(nbox)
         self.L = int(L)
         self.precision = precision
         self.field_dtype = torch.float64 if prec == MB_FP64 else torch.float32
@@ -185,14 +194,20 @@ class Grid:
             pass
 
     # -- helpers --------------------------------------------------------
+    @property
+    def field_shape(self):
+        """(3, L, L, L), or (nbox, 3, L, L, L) for a batch of boxes."""
+        s = (3, self.L, self.L, self.L)
+        return s if self.nbox == 1 else (self.nbox,) + s
+
     def field(self, zero=True):
         import torch
-        shape = (3, self.L, self.L, self.L)
         dev = torch.device("cuda", self.device)
-        return (torch.zeros if zero else torch.empty)(shape, dtype=self.field_dtype, device=dev)
+        return (torch.zeros if zero else torch.empty)(self.field_shape, dtype=self.field_dtype,
+                                                      device=dev)
 
     def _fptr(self, t, name):
-        return _ptr(t, self.field_dtype, (3, self.L, self.L, self.L), name, self.device)
+        return _ptr(t, self.field_dtype, self.field_shape, name, self.device)
 
     # -- calls ----------------------------------------------------------
     def spread(self, q, F, f_out=None, stream=None):
@@ -357,6 +372,31 @@ def spring_adjoint(springs, q, Fbar, qbar, kbar=None, r0bar=None, stream=None):
     return qbar
 
 
+def step_graph(grids, springs, qs, vs, Fexts=None, F_blobs=None, nsteps=1, stream=None):
+    """mb_step_graph: nsteps steps of several grids, one step of each captured
+    into a HIP graph and replayed (returns when done)."""
+    import torch
+    n = len(grids)
+    G = (ctypes.c_void_p * n)(*[g.handle.value for g in grids])
+    S = (ctypes.c_void_p * n)(*[sp.handle.value for sp in springs])
+    P = (ctypes.c_int64 * n)(*[q.shape[0] // sp.nb for q, sp in zip(qs, springs)])
+    f64 = torch.float64
+    Q = (ctypes.c_void_p * n)(*[_ptr(q, f64, (q.shape[0], 3), "q", g.device).value
+                                for q, g in zip(qs, grids)])
+    V = (ctypes.c_void_p * n)(*[g._fptr(v, "v").value for v, g in zip(vs, grids)])
+
+    def opt(ts, shape_of, name):
+        if ts is None:
+            return None
+        return (ctypes.c_void_p * n)(*[None if t is None else
+                                       _ptr(t, f64, shape_of(i), name, grids[i].device).value
+                                       for i, t in enumerate(ts)])
+    FE = opt(Fexts, lambda i: (P[i], 3), "Fext")
+    FB = opt(F_blobs, lambda i: (qs[i].shape[0], 3), "F_blob")
+    _check(lib().mb_step_graph(n, G, S, P, Q, V, FE, FB, int(nsteps), _stream(stream)),
+           "mb_step_graph")
+
+
 def kernel_names():
     out = []
     i = 0
@@ -412,4 +452,8 @@ def mb_step_adjoint(grid, springs, q_n, v_np1, qbar, vbar, Fext=None, F_blob=Non
                     ubar_loss=None, Fblob_bar=None, kbar=None, r0bar=None, stream=None):
     return grid.step_adjoint(springs, q_n, v_np1, qbar, vbar, Fext, F_blob, ubar_loss,
                              Fblob_bar, kbar, r0bar, stream)
+
+
+def mb_step_graph(grids, springs, qs, vs, Fexts=None, F_blobs=None, nsteps=1, stream=None):
+    return step_graph(grids, springs, qs, vs, Fexts, F_blobs, nsteps, stream)
 

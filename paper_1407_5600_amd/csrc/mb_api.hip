@@ -170,9 +170,13 @@ const char* mb_kernel_name(int32_t id) {
 }
 
 mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
+    return mb_grid_create_batch(desc, 1, out);
+}
+
+mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox, mb_grid** out) {
     if (!out) return MB_ERR_INVALID;
     *out = nullptr;
-    if (!desc) return MB_ERR_INVALID;
+    if (!desc || nbox < 1 || nbox > 65536) return MB_ERR_INVALID;
     const mb_grid_desc d = *desc;
     if (!size_ok(d.L)) return MB_ERR_INVALID;
     if (d.precision != MB_FP64 && d.precision != MB_MIXED) return MB_ERR_INVALID;
@@ -213,11 +217,15 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     t.ntz = L / t.tz;
     t.n = t.ntx * t.nty * t.ntz;
     t.remap = (t.n % 8 == 0 && t.n >= 64) ? 1 : 0;
+    t.nbox = nbox;
     g->tiles = t;
     g->rec_size = record_size(d.precision);
     // springs blocks hold at least one particle of at least one blob
     g->force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
-    g->nscan = (t.n + 4095) / 4096;
+    const int64_t ntiles = (int64_t)t.n * nbox;
+    if (ntiles + 1 > ((int64_t)1 << 30) || (int64_t)3 * g->N * nbox > ((int64_t)1 << 40))
+        return MB_ERR_INVALID;
+    g->nscan = (int)((ntiles + 4095) / 4096);
     g->perm_m = -1;
 
     const size_t cbytes = 2 * g->fsz;
@@ -228,22 +236,22 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
     alloc(&g->d_tw, (size_t)L * cbytes);
     alloc(&g->d_dsym, (size_t)L * cbytes);
     alloc(&g->d_d2, (size_t)L * g->fsz);
-    alloc(&g->d_spec, (size_t)3 * L * L * g->NC * cbytes);
-    alloc((void**)&g->d_psum, (size_t)g->nblk_x * 2 * sizeof(double));
-    alloc((void**)&g->d_count, (size_t)t.n * sizeof(int));
-    alloc((void**)&g->d_offs, (size_t)(t.n + 1) * sizeof(int));
+    alloc(&g->d_spec, (size_t)nbox * 3 * L * L * g->NC * cbytes);
+    alloc((void**)&g->d_psum, (size_t)nbox * g->nblk_x * 2 * sizeof(double));
+    alloc((void**)&g->d_count, (size_t)ntiles * sizeof(int));
+    alloc((void**)&g->d_offs, (size_t)(ntiles + 1) * sizeof(int));
     alloc((void**)&g->d_bsum, (size_t)g->nscan * sizeof(int));
     alloc((void**)&g->d_tile, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc((void**)&g->d_rank, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc((void**)&g->d_perm, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc(&g->d_rec, (size_t)std::max<int64_t>(d.max_blobs, 1) * g->rec_size);
-    alloc((void**)&g->d_tile_part, (size_t)t.n * 4 * sizeof(double));
+    alloc((void**)&g->d_tile_part, (size_t)ntiles * 4 * sizeof(double));
     alloc(&g->d_box, box_elems(t) * g->fsz);
     alloc((void**)&g->d_u, (size_t)std::max<int64_t>(d.max_blobs, 1) * 3 * sizeof(double));
     alloc((void**)&g->d_force_part, (size_t)g->force_blocks_cap * 3 * sizeof(double));
-    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)t.n * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)ntiles * sizeof(int));
     if (e == hipSuccess) e = hipMemset(g->d_force_part, 0, (size_t)g->force_blocks_cap * 3 * sizeof(double));
-    if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)t.n * 4 * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)ntiles * 4 * sizeof(double));
     if (e == hipSuccess) {
         if (d.precision == MB_MIXED) {
             std::vector<float> tw, ds, d2;
@@ -364,6 +372,7 @@ mb_status mb_springs_destroy(mb_springs* sp) {
 mb_status mb_spread(mb_grid* g, int64_t M, const double* q, const double* F,
                     void* f_out, void* stream) {
     if (!g || !f_out || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (M % g->tiles.nbox) return MB_ERR_INVALID;  // the same number of blobs per box
     if (M > 0 && (!q || !F || !aligned8(q) || !aligned8(F))) return MB_ERR_INVALID;
     if (!aligned8(f_out) && g->fsz == 8) return MB_ERR_INVALID;
     mb_status st = enter(g);
@@ -387,6 +396,7 @@ mb_status mb_spread(mb_grid* g, int64_t M, const double* q, const double* F,
 mb_status mb_interpolate(mb_grid* g, int64_t M, const double* q, const void* v,
                          double* u_out, void* stream) {
     if (!g || !v || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (M % g->tiles.nbox) return MB_ERR_INVALID;
     if (M > 0 && (!q || !u_out || !aligned8(q) || !aligned8(u_out))) return MB_ERR_INVALID;
     mb_status st = enter(g);
     if (st != MB_OK) return st;
@@ -441,6 +451,7 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
     if (!g || !sp || !v || P < 0 || nsteps < 0) return MB_ERR_INVALID;
     const int64_t M = P * sp->nb;
     if (M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (P % g->tiles.nbox) return MB_ERR_INVALID;  // the same particles per box
     if (M > 0 && (!q || !aligned8(q))) return MB_ERR_INVALID;
     if (sp->device != g->device) return MB_ERR_INVALID;
     mb_status st = enter(g);
@@ -449,7 +460,7 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
     hipStream_t s = (hipStream_t)stream;
     const SpringsDev sd = springs_dev(sp);
     const int fb = springs_blocks(sd, P);
-    if (M == 0) {
+    if (M == 0 && diag_out) {
         // no blobs: the force partials of the diagnostics are zero
         hipError_t e0 = hipMemsetAsync(g->d_force_part, 0, 3 * sizeof(double), s);
         if (e0 != hipSuccess) return from_hip(e0);
@@ -498,6 +509,79 @@ mb_status mb_step_ext(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
                      stream);
 }
 
+mb_status mb_step_graph(int32_t ngrids, mb_grid* const* grids,
+                        const mb_springs* const* springs, const int64_t* nparticles,
+                        double* const* q, void* const* v, const double* const* Fext,
+                        const double* const* F_blob, int32_t nsteps, void* stream) {
+    if (ngrids < 1 || !grids || !springs || !nparticles || !q || !v || nsteps < 0)
+        return MB_ERR_INVALID;
+    for (int i = 0; i < ngrids; ++i) {
+        mb_grid* g = grids[i];
+        const mb_springs* sp = springs[i];
+        if (!g || !sp || !v[i] || nparticles[i] < 0) return MB_ERR_INVALID;
+        const int64_t M = nparticles[i] * sp->nb;
+        if (M > g->d.max_blobs || nparticles[i] % g->tiles.nbox) return MB_ERR_INVALID;
+        if (M > 0 && (!q[i] || !aligned8(q[i]))) return MB_ERR_INVALID;
+        if (F_blob && F_blob[i] && !aligned8(F_blob[i])) return MB_ERR_INVALID;
+        if (sp->device != g->device || g->device != grids[0]->device) return MB_ERR_INVALID;
+    }
+    mb_status st = enter(grids[0]);
+    if (st != MB_OK) return st;
+    if (nsteps == 0) return MB_OK;
+    auto one_step = [&](hipStream_t s) -> mb_status {
+        for (int i = 0; i < ngrids; ++i) {
+            mb_status r = step_impl(grids[i], springs[i], nparticles[i], q[i], v[i],
+                                    Fext ? Fext[i] : nullptr, F_blob ? F_blob[i] : nullptr,
+                                    nullptr, nullptr, nullptr, 1, (void*)s);
+            if (r != MB_OK) return r;
+        }
+        return MB_OK;
+    };
+    hipStream_t caller = (hipStream_t)stream;
+    int done = 0;
+    // an eager first step when a grid has no sorted order from an earlier
+    // binning of these blobs, so that the captured binning uses it
+    bool warm = true;
+    for (int i = 0; i < ngrids; ++i)
+        if (grids[i]->perm_m != nparticles[i] * springs[i]->nb) warm = false;
+    if (!warm) {
+        st = one_step(caller);
+        if (st != MB_OK) return st;
+        done = 1;
+    }
+    if (done == nsteps) return MB_OK;
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint32_t> timing(ngrids);
+    for (int i = 0; i < ngrids; ++i) {
+        timing[i] = grids[i]->timing;
+        grids[i]->timing = 0;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = one_step(cs);
+        hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (st == MB_OK) e = ec;
+    }
+    if (e == hipSuccess && st == MB_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (int n = done; n < nsteps && e == hipSuccess && st == MB_OK; ++n)
+        e = hipGraphLaunch(exec, cs);
+    if (e == hipSuccess && st == MB_OK) e = hipStreamSynchronize(cs);
+    for (int i = 0; i < ngrids; ++i) grids[i]->timing = timing[i];
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev) (void)hipEventDestroy(ev);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (st != MB_OK) return st;
+    return from_hip(e);
+}
+
 mb_status mb_spring_forces_ext(const mb_springs* sp, int64_t P, const double* q,
                                const double* Fext, const double* F_blob, double* F_out,
                                void* stream) {
@@ -515,6 +599,7 @@ mb_status mb_spring_forces_ext(const mb_springs* sp, int64_t P, const double* q,
 mb_status mb_interpolate_grad(mb_grid* g, int64_t M, const double* q, const void* v,
                               const double* W, double* g_inout, void* stream) {
     if (!g || !v || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (M % g->tiles.nbox) return MB_ERR_INVALID;
     if (M > 0 && (!q || !W || !g_inout || !aligned8(q) || !aligned8(W) || !aligned8(g_inout)))
         return MB_ERR_INVALID;
     mb_status st = enter(g);
@@ -558,6 +643,7 @@ mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const dou
     if (g->fsz != 8) return MB_ERR_UNSUPPORTED;
     const int64_t M = P * sp->nb;
     if (M > g->d.max_blobs) return MB_ERR_INVALID;
+    if (P % g->tiles.nbox) return MB_ERR_INVALID;
     if (M > 0 && (!q_n || !qbar || !aligned8(q_n) || !aligned8(qbar))) return MB_ERR_INVALID;
     if ((F_blob && !aligned8(F_blob)) || (ubar_loss && !aligned8(ubar_loss)) ||
         (Fblob_bar && !aligned8(Fblob_bar)) || (kbar && !aligned8(kbar)) ||
@@ -568,7 +654,7 @@ mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const dou
     if (st != MB_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    const size_t nf = (size_t)3 * g->N;
+    const size_t nf = (size_t)3 * g->N * g->tiles.nbox;
     const size_t nbl = (size_t)3 * std::max<int64_t>(g->d.max_blobs, 1);
     if (!g->d_adj) {
         // scratch of the reverse step: fields wbar, fbar, zero; blob arrays

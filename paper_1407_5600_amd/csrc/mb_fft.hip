@@ -220,11 +220,16 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
     __shared__ cplx<T> tws[L];
     __shared__ double red[16];
     const int tid = threadIdx.x;
-    const int yb = blockIdx.x % (L / R);
-    const int cz = blockIdx.x / (L / R);  // c * L + z
+    // blocks of a box are consecutive (G::NBX per box)
+    const int box = blockIdx.x / G::NBX;
+    const int lb = blockIdx.x - box * G::NBX;
+    const int yb = lb % (L / R);
+    const int cz = lb / (L / R);  // c * L + z
     const int z = cz % L;
     const int cbase = (cz - z) * L * L;   // component offset (elements)
     const int y0 = yb * R;
+    v += (size_t)box * 3 * L * L * L;
+    A += (size_t)box * 3 * L * NC * L;
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
     double sv = 0.0, sf = 0.0;
     const int zm = (z == 0 ? L - 1 : z - 1), zp = (z == L - 1 ? 0 : z + 1);
@@ -232,8 +237,10 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
     const T* Ec = nullptr;
     AxisSrc bz{};
     if (BOX) {
-        Ec = f + (size_t)(cz / L) * tl.n * box_volume(tl);
+        Ec = f + ((size_t)box * 3 + cz / L) * tl.n * box_volume(tl);
         bz = box_src_z(tl, z);
+    } else {
+        f += (size_t)box * 3 * L * L * L;
     }
 #pragma unroll
     for (int kk = 0; kk < EPT; ++kk) {
@@ -322,7 +329,7 @@ k_y(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw) {
     __shared__ cplx<T> tws[L];
     const int tid = threadIdx.x;
     const int ch = blockIdx.x % G::NCHY;
-    const int cz = blockIdx.x / G::NCHY;
+    const int cz = blockIdx.x / G::NCHY;  // (box * 3 + c) * L + z
     const int kx0 = ch * W;
     const int wc = NC - kx0 < W ? NC - kx0 : W;
     cplx<T>* base = A + ((size_t)cz * NC + kx0) * L;
@@ -359,9 +366,14 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     __shared__ double red[16];
     __shared__ double mean_new[3];
     const int tid = threadIdx.x;
-    const int ch = blockIdx.x % (L / W);
-    const int kx = blockIdx.x / (L / W);
+    // blocks of a box are consecutive (NC L / W per box)
+    const int box = blockIdx.x / (NC * (L / W));
+    const int lblk = blockIdx.x - box * (NC * (L / W));
+    const int ch = lblk % (L / W);
+    const int kx = lblk / (L / W);
     const int ky0 = ch * W;
+    A += (size_t)box * 3 * L * NC * L;
+    psum += (size_t)box * G::NBX * 2;
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
     if (kx == 0 && ch == 0) {
         constexpr int per_c = G::NBX / 3;
@@ -439,7 +451,7 @@ k_x_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     __shared__ cplx<T> tws[L];
     const int tid = threadIdx.x;
     const int yb = blockIdx.x % (L / R);
-    const int cz = blockIdx.x / (L / R);
+    const int cz = blockIdx.x / (L / R);  // (box * 3 + c) * L + z
     const int y0 = yb * R;
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
     const cplx<T>* in = A + (size_t)cz * NC * L + y0;
@@ -502,8 +514,9 @@ hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, bool boxed, T* v_o
     const T a = steady ? T(0) : (T)(g->d.rho / g->d.dt);
     const T b = steady ? T(0) : (T)(0.5 * g->d.eta / (h * h));
     const T* fin = boxed ? (const T*)g->d_box : f;
-#define MB_XF(BX, ST)                                                              \
-    MB_LAUNCH(g, K_FFT_X_FWD, s, (k_x_fwd<T, L, BX, ST>), G::NBX, G::TX, 0, v_in, fin, \
+    const int nbox = g->tiles.nbox;
+#define MB_XF(BX, ST)                                                                     \
+    MB_LAUNCH(g, K_FFT_X_FWD, s, (k_x_fwd<T, L, BX, ST>), G::NBX * nbox, G::TX, 0, v_in, fin, \
               g->tiles, tw, a, b, A, g->d_psum)
     if (boxed) {
         if (steady) MB_XF(true, true);
@@ -513,17 +526,18 @@ hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, bool boxed, T* v_o
         else MB_XF(false, false);
     }
 #undef MB_XF
-    MB_LAUNCH(g, K_FFT_Y_FWD, s, (k_y<T, L, false>), 3 * L * G::NCHY, G::TY, 0, A, tw);
+    MB_LAUNCH(g, K_FFT_Y_FWD, s, (k_y<T, L, false>), 3 * L * G::NCHY * nbox, G::TY, 0, A,
+              tw);
     const T c0 = steady ? T(0) : (T)(g->d.rho / g->d.dt * N);
     const T c1 = steady ? (T)(g->d.eta * N) : (T)(0.5 * g->d.eta * N);
     const double mv = steady ? 0.0 : 1.0 / N;
     const double mf = steady ? 0.0 : g->d.dt / g->d.rho / N;
     const int zm = (steady || g->d.zero_mean) ? 1 : 0;
-    MB_LAUNCH(g, K_FFT_Z_SPECTRAL, s, (k_z_solve<T, L>), G::NC * (L / G::WZ), G::TZ, 0,
+    MB_LAUNCH(g, K_FFT_Z_SPECTRAL, s, (k_z_solve<T, L>), G::NC * (L / G::WZ) * nbox, G::TZ, 0,
               A, tw, (const cplx<T>*)g->d_dsym, (const T*)g->d_d2, c0, c1, zm,
               g->d_psum, mv, mf);
-    MB_LAUNCH(g, K_FFT_Y_INV, s, (k_y<T, L, true>), 3 * L * G::NCHY, G::TY, 0, A, tw);
-    MB_LAUNCH(g, K_FFT_X_INV, s, (k_x_inv<T, L>), G::NBX, G::TX, 0, A, tw, v_out);
+    MB_LAUNCH(g, K_FFT_Y_INV, s, (k_y<T, L, true>), 3 * L * G::NCHY * nbox, G::TY, 0, A, tw);
+    MB_LAUNCH(g, K_FFT_X_INV, s, (k_x_inv<T, L>), G::NBX * nbox, G::TX, 0, A, tw, v_out);
     return hipGetLastError();
 }
 

@@ -53,8 +53,9 @@ struct SpringsDev {
 struct Tiles {
     int tx, ty, tz;     // tile extent in cells
     int ntx, nty, ntz;  // tiles per axis
-    int n;              // total tiles
+    int n;              // tiles per box
     int remap;          // 1: XCD-aware block -> tile mapping
+    int nbox;           // boxes of the grid (a batch of equal boxes)
 };
 
 struct TimerPair {
@@ -81,7 +82,7 @@ struct mb_grid {
     mb_grid_desc d;
     int device;
     int L, NC;          // cells per side, complex columns L/2 + 1
-    int64_t N;          // L^3
+    int64_t N;          // L^3 (cells of one box)
     size_t fsz;         // bytes per scalar (8 or 4)
     // FFT
     void* d_tw;         // twiddles W_L^k, k < L (cplx<T>)

@@ -112,12 +112,13 @@ __device__ int scan_tile_lds(int* s, int* scratch) {
 // otherwise): a block counts its blobs of tiles [t0, t0 + 64) in LDS (t0 the
 // tile of its first blob) and adds each such count to the global count with
 // one atomic; other blobs take a global atomic each.  rank is the blob's
-// place among its tile's blobs, in no particular order.
+// place among its tile's blobs, in no particular order.  With a batch of
+// boxes, blob i belongs to box i / mbox and tiles are numbered box by box.
 constexpr int TILE_WIN = 64;
 
 __global__ void __launch_bounds__(BLK)
 k_tile_count(const double* __restrict__ q, const int* __restrict__ order,
-             int64_t M, double h, int L, Tiles tl, int* __restrict__ count,
+             int64_t M, int64_t mbox, double h, int L, Tiles tl, int* __restrict__ count,
              int* __restrict__ tile_of, int* __restrict__ rank) {
     __shared__ int lcount[TILE_WIN];
     __shared__ int lbase[TILE_WIN];
@@ -129,7 +130,7 @@ k_tile_count(const double* __restrict__ q, const int* __restrict__ order,
     if (j < M) {
         i = order ? order[j] : j;
         const Geom g = blob_geom(q, i, h, L);
-        t = tile_linear(g.c, tl);
+        t = (int)(i / mbox) * tl.n + tile_linear(g.c, tl);  // box i / mbox
     }
     if (threadIdx.x == 0) t0s = t;  // block 0's first blob exists (M > 0)
     __syncthreads();
@@ -484,10 +485,10 @@ k_add(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
 // 1/h^2, folded into c1): the explicit half of the Crank-Nicolson step.
 template <typename T>
 __global__ void __launch_bounds__(BLK)
-k_apply_cn(int L, T c0, T c1, const T* __restrict__ x, T* __restrict__ y) {
+k_apply_cn(int L, int nbox, T c0, T c1, const T* __restrict__ x, T* __restrict__ y) {
     const int64_t N = (int64_t)L * L * L;
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    if (i >= 3 * N) return;
+    if (i >= 3 * N * nbox) return;
     const int64_t cb = (i / N) * N;
     const int64_t r = i - cb;
     const int xx = (int)(r % L), yy = (int)((r / L) % L), zz = (int)(r / ((int64_t)L * L));
@@ -509,15 +510,24 @@ k_apply_cn(int L, T c0, T c1, const T* __restrict__ x, T* __restrict__ y) {
 struct TileBox {
     int lo[3];
     int full[3];
+    int box;   // box of the batch
+    int tile;  // tile within the box
+    int gt;    // tile over the batch: box * tiles per box + tile
 };
 
+// Block -> (box, tile): the blocks of a box are consecutive; within a box
+// the XCD-aware remap gives each XCD a contiguous range of tiles.
 __device__ __forceinline__ TileBox tile_box(const Tiles& t, int L) {
-    int b = blockIdx.x;
-    if (t.remap) b = xcd_remap(b, t.n);
+    const int b = blockIdx.x;
     TileBox tb;
-    const int ix = b % t.ntx;
-    const int iy = (b / t.ntx) % t.nty;
-    const int iz = b / (t.ntx * t.nty);
+    tb.box = b / t.n;
+    int local = b - tb.box * t.n;
+    if (t.remap) local = xcd_remap(local, t.n);
+    tb.tile = local;
+    tb.gt = tb.box * t.n + local;
+    const int ix = local % t.ntx;
+    const int iy = (local / t.ntx) % t.nty;
+    const int iz = local / (t.ntx * t.nty);
     tb.lo[0] = ix * t.tx;
     tb.lo[1] = iy * t.ty;
     tb.lo[2] = iz * t.tz;
@@ -584,10 +594,10 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
     unsigned int* acc32 = reinterpret_cast<unsigned int*>(acc);
     double* accd = reinterpret_cast<double*>(acc);
     const TileBox tb = tile_box(tl, L);
-    const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
+    const int tile = tb.tile;
     for (int i = threadIdx.x; i < EV; i += BLK) acc[i] = 0ull;
-    const int first = offs[tile];
-    const int total = offs[tile + 1] - first;
+    const int first = offs[tb.gt];
+    const int total = offs[tb.gt + 1] - first;
     const Rec<T>* trec = rec + first;
     // this thread's first record is kept in registers for all components
     Rec<T> r0{};
@@ -665,7 +675,7 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
         }
         __syncthreads();
         // write the box and clear it for the next component
-        T* Ea = E + ((size_t)a * tl.n + tile) * EV;
+        T* Ea = E + ((size_t)(tb.box * 3 + a) * tl.n + tile) * EV;
         for (int i = threadIdx.x; i < EV; i += BLK) {
             T val;
             if (F32 && mode == 0) {
@@ -692,13 +702,15 @@ k_fold(const T* __restrict__ E, int L, Tiles tl, const T* __restrict__ add,
        T* __restrict__ f) {
     const int64_t N = (int64_t)L * L * L;
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    if (i >= 3 * N) return;
-    const int a = (int)(i / N);
-    const int64_t rem = i - a * N;
+    if (i >= 3 * N * tl.nbox) return;
+    const int64_t bc = i / N;  // box * 3 + component
+    const int box = (int)(bc / 3);
+    const int a = (int)(bc - 3 * box);
+    const int64_t rem = i - bc * N;
     const int x = (int)(rem % L);
     const int y = (int)((rem / L) % L);
     const int z = (int)(rem / ((int64_t)L * L));
-    const T val = box_sum(E, tl, a, x, y, z);
+    const T val = box_sum(E + (size_t)box * 3 * tl.n * box_volume(tl), tl, a, x, y, z);
     f[i] = add ? val + add[i] : val;
 }
 
@@ -728,8 +740,9 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     __shared__ int rowoff[EY * EZ];
     __shared__ double red[16];
     const TileBox tb = tile_box(tl, L);
-    const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
+    const int tile = tb.gt;
     const int N = L * L * L;  // 3 L^3 < 2^31 for L <= 512
+    v += (size_t)tb.box * 3 * N;
     for (int r = threadIdx.x; r < EY * EZ; r += BLK) {
         const int ey = r % EY, ez = r / EY;
         rowoff[r] = (wrapL(tb.lo[2] - 1 + ez, L) * L + wrapL(tb.lo[1] - 1 + ey, L)) * L;
@@ -887,8 +900,9 @@ k_interp_grad(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     __shared__ T vt[EV];
     __shared__ int rowoff[EY * EZ];
     const TileBox tb = tile_box(tl, L);
-    const int tile = tl.remap ? xcd_remap(blockIdx.x, tl.n) : blockIdx.x;
+    const int tile = tb.gt;
     const int N = L * L * L;
+    v += (size_t)tb.box * 3 * N;
     for (int r = threadIdx.x; r < EY * EZ; r += BLK) {
         const int ey = r % EY, ez = r / EY;
         rowoff[r] = (wrapL(tb.lo[2] - 1 + ez, L) * L + wrapL(tb.lo[1] - 1 + ey, L)) * L;
@@ -1010,12 +1024,13 @@ static inline unsigned blocks_for(int64_t n) {
 
 template <typename T>
 hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
-    const int nt = g->tiles.n;
+    const int nt = g->tiles.n * g->tiles.nbox;
     if (M > 0) {
         // the previous sorted order, when it is a permutation of these blobs
         const int* order = g->perm_m == M ? g->d_perm : nullptr;
         MB_LAUNCH(g, K_BIN_COUNT, s, k_tile_count, blocks_for(M), BLK, 0, q, order, M,
-                  g->d.h, g->L, g->tiles, g->d_count, g->d_tile, g->d_rank);
+                  M / g->tiles.nbox, g->d.h, g->L, g->tiles, g->d_count, g->d_tile,
+                  g->d_rank);
     }
     if (g->nscan > 1)
         MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
@@ -1095,8 +1110,8 @@ hipError_t apply_cn(mb_grid* g, const T* x, T* y, hipStream_t s) {
     const double h = g->d.h;
     const T c0 = (T)(g->d.rho / g->d.dt);
     const T c1 = (T)(0.5 * g->d.eta / (h * h));
-    hipLaunchKernelGGL(k_apply_cn<T>, dim3(blocks_for(3 * g->N)), dim3(BLK), 0, s, g->L, c0,
-                       c1, x, y);
+    hipLaunchKernelGGL(k_apply_cn<T>, dim3(blocks_for(3 * g->N * g->tiles.nbox)), dim3(BLK), 0,
+                       s, g->L, g->tiles.nbox, c0, c1, x, y);
     return hipGetLastError();
 }
 template hipError_t apply_cn<float>(mb_grid*, const float*, float*, hipStream_t);
@@ -1113,7 +1128,7 @@ size_t springs_lds(const SpringsDev& sp) {
 
 template <typename T, int TX>
 static void launch_spread(mb_grid* g, hipStream_t s) {
-    MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, TX, 8, 8>), g->tiles.n, BLK, 0,
+    MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, TX, 8, 8>), g->tiles.n * g->tiles.nbox, BLK, 0,
               (const Rec<T>*)g->d_rec, g->d_offs, g->L, g->tiles, (T*)g->d_box);
 }
 
@@ -1129,7 +1144,7 @@ hipError_t spread_boxes(mb_grid* g, hipStream_t s) {
 
 template <typename T>
 hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s, const T* add) {
-    MB_LAUNCH(g, K_FOLD, s, k_fold<T>, blocks_for(3 * g->N), BLK, 0,
+    MB_LAUNCH(g, K_FOLD, s, k_fold<T>, blocks_for(3 * g->N * g->tiles.nbox), BLK, 0,
               (const T*)g->d_box, g->L, g->tiles, add, f);
     return hipGetLastError();
 }
@@ -1137,7 +1152,7 @@ hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s, const T* add) {
 template <typename T, int TX>
 static void launch_interp(mb_grid* g, const T* v, double* u_out, double uscale,
                           double* q, double* part, int kid, hipStream_t s) {
-    MB_LAUNCH(g, kid, s, (k_interp<T, TX, 8, 8>), g->tiles.n, BLK, 0,
+    MB_LAUNCH(g, kid, s, (k_interp<T, TX, 8, 8>), g->tiles.n * g->tiles.nbox, BLK, 0,
               (const Rec<T>*)g->d_rec, g->d_perm, g->d_offs, g->L, g->tiles, v,
               u_out, uscale, q, g->d.dt, 1.0 / g->d.h, part);
 }
@@ -1159,7 +1174,8 @@ hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
 template <typename T, int TX>
 static void launch_interp_grad(mb_grid* g, const T* v, const double* W, double wscale,
                                double* gout, hipStream_t s) {
-    MB_LAUNCH(g, K_INTERP_GRAD, s, (k_interp_grad<T, TX, 8, 8>), g->tiles.n, BLK, 0,
+    MB_LAUNCH(g, K_INTERP_GRAD, s, (k_interp_grad<T, TX, 8, 8>), g->tiles.n * g->tiles.nbox,
+              BLK, 0,
               (const Rec<T>*)g->d_rec, g->d_perm, g->d_offs, g->L, g->tiles, v, W, wscale,
               1.0 / g->d.h, gout);
 }
@@ -1187,7 +1203,7 @@ hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,
                        hipStream_t s) {
     const double h = g->d.h;
     const double scale = g->d.rho * h * h * h;
-    MB_LAUNCH(g, K_DIAG, s, k_diag, 1, BLK, 0, g->d_tile_part, g->tiles.n,
+    MB_LAUNCH(g, K_DIAG, s, k_diag, 1, BLK, 0, g->d_tile_part, g->tiles.n * g->tiles.nbox,
               g->d_force_part, force_blocks, scale, diag);
     return hipGetLastError();
 }
@@ -1209,7 +1225,7 @@ template hipError_t interpolate_grad<float>(mb_grid*, const float*, const double
 template hipError_t interpolate_grad<double>(mb_grid*, const double*, const double*, double, double*, hipStream_t);
 
 size_t box_elems(const Tiles& t) {
-    return (size_t)3 * t.n * (t.tx + 3) * (t.ty + 3) * (t.tz + 3);
+    return (size_t)3 * t.nbox * t.n * (t.tx + 3) * (t.ty + 3) * (t.tz + 3);
 }
 
 size_t record_size(int precision) {

@@ -319,6 +319,27 @@ def diff(seed: int = 4) -> Workload:
                     100.0, tmpl, {"centres": c, "rotations": R, "V": V})
 
 
+def pair_sweep(seed: int = 3, nbox: int = 512, sizes=(24, 32, 48, 64),
+               sep_range=(2.0, 6.0)) -> list:
+    """Batched pair-mobility sweep: nbox independent periodic boxes with
+    edges drawn uniformly from `sizes`, each with two particles separated
+    along x by a distance uniform in sep_range, centred in the box, forces
+    +-(1, 0, 0), dt = 0.01, 500 steps.  Returns one dict per box with L, q
+    (26, 3), Fext (2, 3), sep."""
+    rng = np.random.default_rng(seed)
+    tmpl = icosahedron_template(1.0)
+    Ls = rng.choice(np.asarray(sizes), size=nbox)
+    seps = rng.uniform(sep_range[0], sep_range[1], size=nbox)
+    F = np.array([[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0]])
+    boxes = []
+    for L, sep in zip(Ls, seps):
+        mid = np.full(3, L / 2.0) + rng.uniform(-0.5, 0.5, size=3)
+        c = np.stack([mid - [sep / 2, 0, 0], mid + [sep / 2, 0, 0]])
+        boxes.append({"L": int(L), "sep": float(sep), "q": place_particles(c, tmpl),
+                      "Fext": F.copy()})
+    return boxes
+
+
 def random_suspension(seed: int, L: int, P: int, phi_cap: float = 0.3,
                       rotate: bool = True, spread_box: bool = True) -> Workload:
     """A smaller seeded suspension for parity cases: P particles by RSA."""
