@@ -17,8 +17,13 @@ roofline with the kernel's algorithmic bytes.  The oracle (float64, one CPU
 thread) is timed on a bounded sample of the same workload as the CPU
 baseline.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
-GPU.
+Also measured (key "batch"): the pair-mobility sweep, 512 boxes of edge
+24/32/48/64 with two particles each, grouped by edge into four grids of equal
+boxes and advanced by a graph-captured step of all four, against the same
+boxes advanced one grid per box.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: the step has a one-GPU
+path only.
 """
 import argparse
 import json
@@ -146,6 +151,77 @@ def cpu_baseline(w, nsteps):
             "seconds": dt}
 
 
+def bench_batch(torch, nbox, steps, sample=32):
+    """Pair-mobility sweep: nbox boxes of edge 24/32/48/64 with two particles
+    each, mixed precision, grouped by edge into four batch grids stepped by
+    one graph-captured step per time step; against the same boxes stepped one
+    grid per box (a sample of them, eager)."""
+    import numpy as np
+    from paper_1407_5600_amd import Grid, Springs, inputs
+    from paper_1407_5600_amd.binding import step_graph
+    boxes = inputs.pair_sweep(nbox=nbox)
+    tmpl = inputs.icosahedron_template(1.0)
+    pa, pb, r0 = inputs.pair_table(tmpl)
+    sp = Springs(len(tmpl), pa, pb, r0, 100.0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    grids, qs, vs, fs, order = [], [], [], [], []
+    for L in sorted({b["L"] for b in boxes}):
+        idx = [i for i, b in enumerate(boxes) if b["L"] == L]
+        g = Grid(L, precision="mixed", max_blobs=26 * len(idx), nbox=len(idx))
+        grids.append(g)
+        qs.append(dev(np.concatenate([boxes[i]["q"] for i in idx])))
+        vs.append(g.field())
+        fs.append(dev(np.concatenate([boxes[i]["Fext"] for i in idx])))
+        order.append(idx)
+    cells = sum(b["L"] ** 3 for b in boxes)
+    step_graph(grids, [sp] * len(grids), qs, vs, fs, None, 2)  # warm-up, capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_graph(grids, [sp] * len(grids), qs, vs, fs, None, steps)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for g, q, v, F in zip(grids, qs, vs, fs):
+        g.step(sp, q, v, F, steps)
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / steps
+    # relative velocity U1 - U2 per box after the run (one more step)
+    rel_u = []
+    for g, q, v, F, idx in zip(grids, qs, vs, fs, order):
+        U0 = torch.empty((2 * len(idx), 3), dtype=torch.float64, device="cuda")
+        g.step(sp, q, v, F, 1, U0_out=U0)
+        rel_u.append((U0[0::2, 0] - U0[1::2, 0]).cpu().numpy())
+    # one grid per box, a sample of the boxes
+    samp = boxes[:sample]
+    sg = [Grid(b["L"], precision="mixed", max_blobs=26) for b in samp]
+    sq = [dev(b["q"]) for b in samp]
+    sv = [g.field() for g in sg]
+    sf = [dev(b["Fext"]) for b in samp]
+    for g, q, v, F in zip(sg, sq, sv, sf):
+        g.step(sp, q, v, F, 2)
+    torch.cuda.synchronize()
+    ns = max(5, steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(ns):
+        for g, q, v, F in zip(sg, sq, sv, sf):
+            g.step(sp, q, v, F, 1)
+    torch.cuda.synchronize()
+    per_box_step = (time.perf_counter() - t0) / (ns * len(samp))
+    sample_cells = sum(b["L"] ** 3 for b in samp)
+    return {"workload": f"pair sweep: {nbox} boxes of edge 24/32/48/64 (seeded), 2 particles "
+                        f"each at x-separation U[2,6], forces +-(1,0,0), mixed",
+            "boxes": nbox, "cells": int(cells), "steps": steps,
+            "batched_graph_ms_per_step": round(t_batch * 1e3, 4),
+            "box_steps_per_s": round(nbox / t_batch, 1),
+            "batched_eager_ms_per_step": round(t_eager * 1e3, 4),
+            "one_grid_per_box_ms_per_box_step": round(per_box_step * 1e3, 4),
+            "one_grid_per_box_sample": f"{len(samp)} boxes ({sample_cells} cells), eager",
+            "speedup_vs_one_grid_per_box": round(per_box_step * nbox / t_batch, 2),
+            "relative_velocity_x": {"mean": float(np.mean(np.concatenate(rel_u))),
+                                    "min": float(np.min(np.concatenate(rel_u))),
+                                    "max": float(np.max(np.concatenate(rel_u)))}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,12 +232,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="run one precision (profiling)")
+    ap.add_argument("--batch-boxes", type=int, default=512,
+                    help="boxes of the batched pair-sweep measurement (0: skip it)")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 2^28 bytes, the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the step runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 
@@ -228,6 +307,10 @@ def main():
     }
     if "fp64" in res:
         out["kernels_fp64"] = {k: round(ms, 5) for k, ms in res["fp64"]["per_step_ms"].items()}
+    if args.batch_boxes > 0 and args.only is None:
+        print(f"[bench] batched pair sweep ({args.batch_boxes} boxes)", file=sys.stderr,
+              flush=True)
+        out["batch"] = bench_batch(torch, args.batch_boxes, args.batch_steps)
     if not args.no_cpu_baseline and args.workload != "large":
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
