@@ -363,6 +363,21 @@ void mbo_step(const mbo_params* p, long P, int nb, int npairs, const int* pa,
               const double* Fext, double* u, double* U0, int nsteps,
               double* diag)
 {
+    mbo_step_forced(p, P, nb, npairs, pa, pb, r0, k, q, v, Fext, NULL, u, U0,
+                    nsteps, diag);
+}
+
+/* The step with a force density f_fluid [3][L][L][L] acting on the fluid
+ * (NULL: none) added to the spread blob forces before the solve: the
+ * periodic forcing f0 sin(k_j y) x of the viscosity measurement (Sec.
+ * Stresslet and Viscosity) enters the momentum equation (eq. vf) as a body
+ * force density on the fluid. */
+void mbo_step_forced(const mbo_params* p, long P, int nb, int npairs,
+                     const int* pa, const int* pb, const double* r0, double k,
+                     double* q, double* v, const double* Fext,
+                     const double* f_fluid, double* u, double* U0, int nsteps,
+                     double* diag)
+{
     const long L = p->L;
     const long N = L * L * L;
     const long M = P * nb;
@@ -372,6 +387,9 @@ void mbo_step(const mbo_params* p, long P, int nb, int npairs, const int* pa,
     for (int n = 0; n < nsteps; ++n) {
         mbo_spring_forces(P, nb, npairs, pa, pb, r0, k, q, Fext, F);
         mbo_spread(p, M, q, F, f);
+        if (f_fluid)
+            for (long j = 0; j < 3 * N; ++j)
+                f[j] += f_fluid[j];
         mbo_fluid_solve(p, v, f, v);
         mbo_interpolate(p, M, q, v, uu);
         for (long i = 0; i < 3 * M; ++i)

@@ -104,6 +104,15 @@ void mbo_step(const mbo_params* p, long P, int nb, int npairs, const int* pa,
               const double* Fext, double* u, double* U0, int nsteps,
               double* diag);
 
+/* mbo_step with a force density f_fluid [3][L][L][L] on the fluid (may be
+ * NULL) added to S(q^n) F^n in every step: the periodic forcing of the
+ * viscosity measurement (Sec. Stresslet and Viscosity). */
+void mbo_step_forced(const mbo_params* p, long P, int nb, int npairs,
+                     const int* pa, const int* pb, const double* r0, double k,
+                     double* q, double* v, const double* Fext,
+                     const double* f_fluid, double* u, double* U0, int nsteps,
+                     double* diag);
+
 /* ---- Derivatives (reverse mode), for the gradient of a trajectory loss.
  * The transposed chain rule of the functions above written out; each is
  * pinned by central finite differences of its forward function. */

@@ -44,3 +44,21 @@ def test_single_workload():
     assert w.L == 32 and w.M == 13 and w.P == 1
     assert np.allclose(w.Fext, [[1, 0, 0]])
     assert len(w.pa) == 78
+
+
+def test_hard_sphere_centres_no_overlap_and_moved():
+    """Monte Carlo hard-sphere configurations: n centres in the box, every
+    minimum-image pair at least 2R apart, and the sweeps moved the spheres
+    away from their starting configuration."""
+    from paper_1407_5600_amd import inputs as I
+    L, R = 24.0, 1.62
+    n = I.particles_for_fraction(L, 0.15, R)
+    c0 = I.hard_sphere_centres(np.random.default_rng(5), L, n, R, sweeps=0)
+    c = I.hard_sphere_centres(np.random.default_rng(5), L, n, R, sweeps=10)
+    assert c.shape == (n, 3) and np.all((c >= 0) & (c < L))
+    d = c[:, None] - c[None]
+    d -= L * np.round(d / L)
+    r = np.sqrt((d * d).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    assert r.min() >= 2 * R
+    assert np.abs(c - c0).max() > 0.1
