@@ -177,6 +177,20 @@ mb_status mb_step_ext(mb_grid* grid, const mb_springs* springs,
                       double* u_out, double* U0_out, double* diag_out,
                       int32_t nsteps, void* stream);
 
+/* mb_step_ext with a force density f_fluid acting on the fluid besides the
+ * spread blob forces: the solve of each step takes f = S(q^n) F^n + f_fluid.
+ * It drives the periodic forcing f = f0 sin(k_j y) x of the viscosity
+ * measurement (Sec. Stresslet and Viscosity).  f_fluid: [3][L][L][L]
+ * ([nbox][3][L][L][L] for a batch), the grid's precision, on the device,
+ * not NULL, unchanged by the call.  The first call allocates one field of
+ * scratch in the grid (kept until mb_grid_destroy; MB_ERR_NOMEM if that
+ * fails).  The diagnostics' sum F covers the blob forces only. */
+mb_status mb_step_forced(mb_grid* grid, const mb_springs* springs,
+                         int64_t nparticles, double* q, void* v,
+                         const double* Fext, const double* F_blob,
+                         const void* f_fluid, double* u_out, double* U0_out,
+                         double* diag_out, int32_t nsteps, void* stream);
+
 /* mb_spring_forces plus per-blob external forces F_blob [M][3] (may be
  * NULL). */
 mb_status mb_spring_forces_ext(const mb_springs* springs, int64_t nparticles,

@@ -11,4 +11,4 @@ the seeded input generators.
 from .binding import (Grid, MultiblobError, Springs, mb_fluid_solve,  # noqa: F401
                       mb_interpolate, mb_interpolate_grad, mb_spread, mb_spring_adjoint,
                       mb_spring_forces, mb_spring_forces_ext, mb_step, mb_step_adjoint,
-                      mb_step_ext, spring_adjoint, spring_forces, status_string)
+                      mb_step_ext, mb_step_forced, spring_adjoint, spring_forces, status_string)

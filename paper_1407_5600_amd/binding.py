@@ -65,6 +65,7 @@ def lib():
             "mb_spring_forces": ([vp, i64, vp, vp, vp, vp], i32),
             "mb_step": ([vp, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp], i32),
             "mb_step_ext": ([vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
+            "mb_step_forced": ([vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
             "mb_spring_forces_ext": ([vp, i64, vp, vp, vp, vp, vp], i32),
             "mb_interpolate_grad": ([vp, i64, vp, vp, vp, vp, vp], i32),
             "mb_spring_adjoint": ([vp, i64, vp, vp, vp, vp, vp, vp], i32),
@@ -88,7 +89,7 @@ EXPORTED = ("mb_grid_create", "mb_grid_destroy", "mb_springs_create",
             "mb_spring_forces", "mb_step", "mb_status_string", "mb_grid_set_timing",
             "mb_grid_kernel_times", "mb_kernel_name", "mb_step_ext", "mb_spring_forces_ext",
             "mb_interpolate_grad", "mb_spring_adjoint", "mb_step_adjoint",
-            "mb_grid_create_batch", "mb_step_graph")
+            "mb_grid_create_batch", "mb_step_graph", "mb_step_forced")
 
 
 def status_string(st: int) -> str:
@@ -272,6 +273,27 @@ class Grid:
             _ptr(diag_out, torch.float64, (NDIAG,), "diag_out", self.device),
             int(nsteps), _stream(stream)), "mb_step_ext")
 
+    def step_forced(self, springs, q, v, f_fluid, Fext=None, F_blob=None, nsteps=1,
+                    u_out=None, U0_out=None, diag_out=None, stream=None):
+        """mb_step_forced: mb_step_ext with a force density f_fluid on the fluid."""
+        import torch
+        M = q.shape[0]
+        P = M // springs.nb
+        if P * springs.nb != M:
+            raise ValueError("blob count is not a multiple of blobs per particle")
+        if f_fluid is None:
+            raise ValueError("f_fluid is required")
+        _check(lib().mb_step_forced(
+            self.handle, springs.handle, P,
+            _ptr(q, torch.float64, (M, 3), "q", self.device), self._fptr(v, "v"),
+            _ptr(Fext, torch.float64, (P, 3), "Fext", self.device),
+            _ptr(F_blob, torch.float64, (M, 3), "F_blob", self.device),
+            self._fptr(f_fluid, "f_fluid"),
+            _ptr(u_out, torch.float64, (M, 3), "u_out", self.device),
+            _ptr(U0_out, torch.float64, (P, 3), "U0_out", self.device),
+            _ptr(diag_out, torch.float64, (NDIAG,), "diag_out", self.device),
+            int(nsteps), _stream(stream)), "mb_step_forced")
+
     def interpolate_grad(self, q, v, W, g_inout=None, stream=None):
         """mb_interpolate_grad: g += sum_a W_a grad_q (J v)_a (accumulates)."""
         import torch
@@ -434,6 +456,12 @@ def mb_step_ext(grid, springs, q, v, Fext=None, F_blob=None, nsteps=1, u_out=Non
                 U0_out=None, diag_out=None, stream=None):
     return grid.step_ext(springs, q, v, Fext, F_blob, nsteps, u_out, U0_out, diag_out,
                          stream)
+
+
+def mb_step_forced(grid, springs, q, v, f_fluid, Fext=None, F_blob=None, nsteps=1,
+                   u_out=None, U0_out=None, diag_out=None, stream=None):
+    return grid.step_forced(springs, q, v, f_fluid, Fext, F_blob, nsteps, u_out, U0_out,
+                            diag_out, stream)
 
 
 def mb_spring_forces_ext(springs, q, Fext, F_blob, F_out=None, stream=None):

@@ -82,7 +82,8 @@ void free_grid(mb_grid* g) {
     void* ptrs[] = {g->d_tw,    g->d_dsym,  g->d_d2,   g->d_spec,
                     g->d_psum,  g->d_count, g->d_offs, g->d_bsum,
                     g->d_rank,  g->d_perm,  g->d_rec,  g->d_tile_part,
-                    g->d_force_part, g->d_box, g->d_u, g->d_tile, g->d_adj};
+                    g->d_force_part, g->d_box, g->d_u, g->d_tile, g->d_adj,
+                    g->d_ffield};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& tp : g->pending) {
@@ -447,7 +448,7 @@ mb_status mb_spring_forces(const mb_springs* sp, int64_t P, const double* q,
 static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
                            void* v, const double* Fext, const double* Gblob,
                            double* u_out, double* U0_out, double* diag_out,
-                           int32_t nsteps, void* stream) {
+                           int32_t nsteps, void* stream, const void* ffluid = nullptr) {
     if (!g || !sp || !v || P < 0 || nsteps < 0) return MB_ERR_INVALID;
     const int64_t M = P * sp->nb;
     if (M > g->d.max_blobs) return MB_ERR_INVALID;
@@ -466,23 +467,37 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
         if (e0 != hipSuccess) return from_hip(e0);
     }
     hipError_t e = hipSuccess;
+    if (ffluid && !g->d_ffield) {
+        e = hipMalloc(&g->d_ffield, (size_t)3 * g->N * g->tiles.nbox * g->fsz);
+        if (e != hipSuccess) {
+            g->d_ffield = nullptr;
+            return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
+        }
+    }
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
         const bool last = n == nsteps - 1;
         double* u_dst = nullptr;
         if (last) u_dst = u_out ? u_out : (U0_out ? g->d_u : nullptr);
+        // with a fluid force the spread boxes are folded into a field with
+        // it added, and the solve reads that field
         if (g->fsz == 4) {
             float* vv = (float*)v;
+            float* ff = (float*)g->d_ffield;
             e = bin_blobs<float>(g, M, q, s);
             if (e == hipSuccess) e = scatter_springs<float>(g, sd, P, q, Fext, s, Gblob);
             if (e == hipSuccess) e = spread_boxes<float>(g, s);
-            if (e == hipSuccess) e = fluid_solve<float>(g, vv, nullptr, vv, s, true);
+            if (e == hipSuccess && ffluid) e = fold_boxes<float>(g, ff, s, (const float*)ffluid);
+            if (e == hipSuccess) e = fluid_solve<float>(g, vv, ff, vv, s, !ffluid);
             if (e == hipSuccess) e = interpolate<float>(g, M, vv, u_dst, q, 1, s);
         } else {
             double* vv = (double*)v;
+            double* ff = (double*)g->d_ffield;
             e = bin_blobs<double>(g, M, q, s);
             if (e == hipSuccess) e = scatter_springs<double>(g, sd, P, q, Fext, s, Gblob);
             if (e == hipSuccess) e = spread_boxes<double>(g, s);
-            if (e == hipSuccess) e = fluid_solve<double>(g, vv, nullptr, vv, s, true);
+            if (e == hipSuccess && ffluid)
+                e = fold_boxes<double>(g, ff, s, (const double*)ffluid);
+            if (e == hipSuccess) e = fluid_solve<double>(g, vv, ff, vv, s, !ffluid);
             if (e == hipSuccess) e = interpolate<double>(g, M, vv, u_dst, q, 1, s);
         }
         if (last && e == hipSuccess && U0_out)
@@ -507,6 +522,16 @@ mb_status mb_step_ext(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
     if (F_blob && !aligned8(F_blob)) return MB_ERR_INVALID;
     return step_impl(g, sp, P, q, v, Fext, F_blob, u_out, U0_out, diag_out, nsteps,
                      stream);
+}
+
+mb_status mb_step_forced(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
+                         void* v, const double* Fext, const double* F_blob,
+                         const void* f_fluid, double* u_out, double* U0_out,
+                         double* diag_out, int32_t nsteps, void* stream) {
+    if (F_blob && !aligned8(F_blob)) return MB_ERR_INVALID;
+    if (!f_fluid || ((uintptr_t)f_fluid & (g ? g->fsz - 1 : 7))) return MB_ERR_INVALID;
+    return step_impl(g, sp, P, q, v, Fext, F_blob, u_out, U0_out, diag_out, nsteps,
+                     stream, f_fluid);
 }
 
 mb_status mb_step_graph(int32_t ngrids, mb_grid* const* grids,

@@ -106,6 +106,7 @@ struct mb_grid {
     void* d_box;           // [3][tiles][box nodes] spread boxes of the step
     double* d_u;           // [max_blobs][3] blob velocities of the last step
     double* d_adj;         // reverse-step scratch (allocated on first use)
+    void* d_ffield;        // force field of forced steps (allocated on first use)
     double* d_tile_part;   // [tiles][4]  (sum v_a, max |Dv|)
     double* d_force_part;  // [force blocks][3]
     int force_blocks_cap;

@@ -205,6 +205,33 @@ def lattice_centres(rng: np.random.Generator, L: float, n: int,
     return c % L
 
 
+def hard_sphere_centres(rng: np.random.Generator, L: float, n: int, radius: float,
+                        sweeps: int = 20, step: float | None = None) -> np.ndarray:
+    """Equilibrium hard-sphere configuration of n spheres of ``radius`` in a
+    periodic box (the Monte Carlo preparation of the viscosity measurement,
+    Sec. Stresslet and Viscosity): random sequential addition (or a lattice
+    start when that is too dense for it), then ``sweeps`` Metropolis sweeps
+    of single-sphere moves, uniform in +-step per axis, rejected on overlap.
+    The step defaults to a fifth of the mean free spacing."""
+    dmin = 2.0 * radius
+    phi = n * 4.0 / 3.0 * math.pi * radius ** 3 / L ** 3
+    c = (rsa_centres(rng, L, n, dmin=dmin) if phi < 0.3
+         else lattice_centres(rng, L, n, dmin=dmin))
+    if step is None:
+        step = 0.2 * max((L ** 3 / max(n, 1)) ** (1.0 / 3.0) - dmin, 0.05 * dmin)
+    d2min = dmin * dmin
+    for _ in range(sweeps):
+        for i in rng.permutation(n):
+            trial = (c[i] + rng.uniform(-step, step, size=3)) % L
+            d = c - trial
+            d -= L * np.round(d / L)
+            r2 = (d * d).sum(1)
+            r2[i] = np.inf
+            if r2.min() >= d2min:
+                c[i] = trial
+    return c
+
+
 def place_particles(centres: np.ndarray, template: np.ndarray,
                     rotations: np.ndarray | None = None) -> np.ndarray:
     """Blob positions (P * nb, 3), blob nb*p + b of particle p."""
