@@ -146,12 +146,14 @@ def fluid_solve(prm, v, f):
     return out
 
 
-def step(prm, springs, q, v, Fext, nsteps=1, f_fluid=None):
+def step(prm, springs, q, v, Fext, nsteps=1, f_fluid=None, scheme="euler"):
     """Run ``nsteps`` time steps in place on copies of q and v.
 
     springs: dict with keys nb, pa, pb, r0, k.  f_fluid: optional force
     density (3, L, L, L) on the fluid added to the spread blob forces in
     every step (the periodic forcing of Sec. Stresslet and Viscosity).
+    scheme: "euler" (first order: force and interpolation at q^n) or
+    "midpoint" (the second-order predictor-corrector, mbo_step_midpoint).
     Returns a dict with the new q, v and the last step's u, U0 and
     diagnostics {Pi_x, Pi_y, Pi_z, sumF_x, sumF_y, sumF_z, max|Dv|}.
     """
@@ -167,11 +169,10 @@ def step(prm, springs, q, v, Fext, nsteps=1, f_fluid=None):
     U0 = np.zeros((P, 3))
     diag = np.zeros(7)
     ff = None if f_fluid is None else _f64(f_fluid, (3, prm.L, prm.L, prm.L))
-    lib().mbo_step_forced(ctypes.byref(prm), ctypes.c_long(P), ctypes.c_int(nb),
-                          ctypes.c_int(len(pa)), _p(pa), _p(pb), _p(r0),
-                          ctypes.c_double(springs["k"]), _p(q), _p(v), _p(Fext),
-                          None if ff is None else _p(ff), _p(u), _p(U0),
-                          ctypes.c_int(nsteps), _p(diag))
+    fn = {"euler": lib().mbo_step_forced, "midpoint": lib().mbo_step_midpoint}[scheme]
+    fn(ctypes.byref(prm), ctypes.c_long(P), ctypes.c_int(nb), ctypes.c_int(len(pa)),
+       _p(pa), _p(pb), _p(r0), ctypes.c_double(springs["k"]), _p(q), _p(v), _p(Fext),
+       None if ff is None else _p(ff), _p(u), _p(U0), ctypes.c_int(nsteps), _p(diag))
     return {"q": q, "v": v, "u": u, "U0": U0, "diag": diag}
 
 

@@ -113,6 +113,19 @@ void mbo_step_forced(const mbo_params* p, long P, int nb, int npairs,
                      const double* f_fluid, double* u, double* U0, int nsteps,
                      double* diag);
 
+/* Second-order step: a midpoint predictor-corrector rebuilt from eqs. vf,
+ * ju and blob1 (m_e = 0), the inertial coupling scheme the paper cites
+ * without printing it.  Unsteady: q* = q^n + (dt/2) J(q^n) v^n; v^{n+1} by
+ * the Crank-Nicolson solve from v^n with f = S(q*) F(q*); q^{n+1} = q^n +
+ * dt J(q*) (v^n + v^{n+1})/2.  Steady: the explicit midpoint rule with two
+ * steady solves, at q^n and at q*.  Arguments and outputs as
+ * mbo_step_forced. */
+void mbo_step_midpoint(const mbo_params* p, long P, int nb, int npairs,
+                       const int* pa, const int* pb, const double* r0, double k,
+                       double* q, double* v, const double* Fext,
+                       const double* f_fluid, double* u, double* U0, int nsteps,
+                       double* diag);
+
 /* ---- Derivatives (reverse mode), for the gradient of a trajectory loss.
  * The transposed chain rule of the functions above written out; each is
  * pinned by central finite differences of its forward function. */

@@ -3,7 +3,7 @@ oracle's C source, compiled on the CPU, and the oracle's pin tests are run
 against it in a subprocess; every mutant must fail at least one pin.  This
 shows that the pins tie down every part of the oracle (kernel, staggering,
 spreading, interpolation, springs, DFT, projection, Crank-Nicolson, mean
-mode)."""
+mode, derivatives, fluid forcing, the second-order step)."""
 import os
 import subprocess
 import sys
@@ -15,7 +15,8 @@ SRC = os.path.join(ROOT, "oracle", "mbo.c")
 PINS = ["tests/test_oracle_kernel.py", "tests/test_oracle_fft.py",
         "tests/test_oracle_operators.py", "tests/test_oracle_springs.py",
         "tests/test_oracle_solver.py", "tests/test_oracle_step.py",
-        "tests/test_oracle_adjoint.py"]
+        "tests/test_oracle_adjoint.py", "tests/test_oracle_stokes.py",
+        "tests/test_oracle_midpoint.py"]
 
 MUTANTS = {
     "kernel_sqrt_sign": ("return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;",
@@ -59,6 +60,13 @@ MUTANTS = {
     "adjoint_transpose_volume": ("Wt[i] = h3 * ubar[i];", "Wt[i] = ubar[i];"),
     "adjoint_cn_explicit": ("y[c * N + idx] = a * X[idx] + b * lap;",
                             "y[c * N + idx] = a * X[idx] - b * lap;"),
+    # fluid forcing and the second-order step
+    "forced_drop_fluid_force": ("f[j] += f_fluid[j];", "f[j] += 0.0 * f_fluid[j];"),
+    "midpoint_predictor_full_step": ("qs[i] = q[i] + 0.5 * dt * ua[i];",
+                                     "qs[i] = q[i] + dt * ua[i];"),
+    "midpoint_forces_at_start": ("mbo_spring_forces(P, nb, npairs, pa, pb, r0, k, qs, Fext, F);",
+                                 "mbo_spring_forces(P, nb, npairs, pa, pb, r0, k, q, Fext, F);"),
+    "midpoint_no_trapezoid": ("vn[j] = 0.5 * (vn[j] + v[j]);", "vn[j] = v[j];"),
 }
 
 
