@@ -74,6 +74,21 @@ typedef enum {
                              runs, Sec. Stresslet and viscosity) */
 } mb_mode;
 
+typedef enum {
+    MB_SCHEME_EULER = 0,    /* first order (the default): the forces, the
+                               spreading and the interpolation at q^n, the
+                               blobs moved by dt J(q^n) v^{n+1} */
+    MB_SCHEME_MIDPOINT = 1  /* second order: a midpoint predictor-corrector
+                               rebuilt from eqs. vf, ju and blob1 with m_e =
+                               0 (the inertial coupling scheme the paper
+                               uses is cited, not printed):
+                               q* = q^n + (dt/2) J(q^n) v^n;  v^{n+1} from
+                               v^n with f = S(q*) F(q*);  q^{n+1} = q^n +
+                               dt J(q*) (v^n + v^{n+1})/2.  In
+                               MB_STEADY_STOKES the explicit midpoint rule
+                               with a steady solve at q^n and one at q*. */
+} mb_scheme;
+
 /* Grid description.  L = 2^a 3^b with 8 <= L <= 512 and L a multiple of 8;
  * h > 0, dt > 0; rho > 0 in MB_UNSTEADY_CN; eta > 0 in MB_STEADY_STOKES
  * (eta = 0 is allowed in MB_UNSTEADY_CN: ideal fluid).  zero_mean = 1 holds
@@ -265,6 +280,18 @@ const char* mb_status_string(mb_status status);
  * (ids are stable; names from mb_kernel_name) and returns the number of ids
  * in *n_out.  Setting a mask clears the accumulators. */
 mb_status mb_grid_set_timing(mb_grid* grid, uint32_t kernel_mask);
+
+/* Time-stepping scheme of the grid's steps (mb_step, mb_step_ext,
+ * mb_step_forced, mb_step_graph); MB_SCHEME_EULER after creation.  The
+ * midpoint scheme allocates 6 max_blobs float64 of scratch in the grid at
+ * its first step (MB_ERR_NOMEM if that fails) and costs, per step, one more
+ * binning and two more interpolations (unsteady), or a second force
+ * evaluation, spreading and solve (steady).  u_out then receives the
+ * velocity of the update, J(q*)(v^n + v^{n+1})/2 (steady: J(q*) v(q*)), and
+ * the diagnostics' sum F the forces at q*.  mb_step_adjoint differentiates
+ * the first-order scheme only (MB_ERR_UNSUPPORTED otherwise).
+ * MB_ERR_INVALID for an unknown scheme. */
+mb_status mb_grid_set_scheme(mb_grid* grid, int32_t scheme);
 mb_status mb_grid_kernel_times(mb_grid* grid, void* stream, double* ms_out,
                                int64_t* launches_out, int32_t cap,
                                int32_t* n_out);

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libmultiblob.so")
 MB_OK, MB_ERR_INVALID, MB_ERR_UNSUPPORTED, MB_ERR_NOMEM, MB_ERR_DEVICE = 0, -1, -2, -3, -4
 MB_FP64, MB_MIXED = 0, 1
 MB_UNSTEADY_CN, MB_STEADY_STOKES = 0, 1
+MB_SCHEME_EULER, MB_SCHEME_MIDPOINT = 0, 1
+SCHEMES = {"euler": MB_SCHEME_EULER, "midpoint": MB_SCHEME_MIDPOINT}
 NDIAG = 7
 
 
@@ -73,6 +75,7 @@ def lib():
                                 i32),
             "mb_status_string": ([i32], ctypes.c_char_p),
             "mb_grid_set_timing": ([vp, ctypes.c_uint32], i32),
+            "mb_grid_set_scheme": ([vp, i32], i32),
             "mb_grid_kernel_times": ([vp, vp, vp, vp, i32, ctypes.POINTER(i32)], i32),
             "mb_kernel_name": ([i32], ctypes.c_char_p),
         }
@@ -89,7 +92,8 @@ EXPORTED = ("mb_grid_create", "mb_grid_destroy", "mb_springs_create",
             "mb_spring_forces", "mb_step", "mb_status_string", "mb_grid_set_timing",
             "mb_grid_kernel_times", "mb_kernel_name", "mb_step_ext", "mb_spring_forces_ext",
             "mb_interpolate_grad", "mb_spring_adjoint", "mb_step_adjoint",
-            "mb_grid_create_batch", "mb_step_graph", "mb_step_forced")
+            "mb_grid_create_batch", "mb_step_graph", "mb_step_forced",
+            "mb_grid_set_scheme")
 
 
 def status_string(st: int) -> str:
@@ -163,7 +167,7 @@ class Grid:
     """A periodic MAC grid with its FFT tables and scratch (mb_grid_create)."""
 
     def __init__(self, L, h=1.0, rho=1.0, eta=1.0, dt=0.01, precision="fp64",
-                 mode="unsteady", zero_mean=False, max_blobs=0, nbox=1):
+                 mode="unsteady", zero_mean=False, max_blobs=0, nbox=1, scheme="euler"):
         import torch
         prec = {"fp64": MB_FP64, "mixed": MB_MIXED}[precision]
         md = {"unsteady": MB_UNSTEADY_CN, "steady": MB_STEADY_STOKES}[mode]
@@ -182,6 +186,14 @@ class Grid:
         self.precision = precision
         self.field_dtype = torch.float64 if prec == MB_FP64 else torch.float32
         self.device = torch.cuda.current_device()
+        self.scheme = "euler"
+        if scheme != "euler":
+            self.set_scheme(scheme)
+
+    def set_scheme(self, scheme):
+        """mb_grid_set_scheme: "euler" (first order) or "midpoint" (second)."""
+        _check(lib().mb_grid_set_scheme(self.handle, SCHEMES[scheme]), "mb_grid_set_scheme")
+        self.scheme = scheme
 
     def close(self):
         if self.handle:

@@ -83,7 +83,7 @@ void free_grid(mb_grid* g) {
                     g->d_psum,  g->d_count, g->d_offs, g->d_bsum,
                     g->d_rank,  g->d_perm,  g->d_rec,  g->d_tile_part,
                     g->d_force_part, g->d_box, g->d_u, g->d_tile, g->d_adj,
-                    g->d_ffield};
+                    g->d_ffield, g->d_mid};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& tp : g->pending) {
@@ -445,6 +445,67 @@ mb_status mb_spring_forces(const mb_springs* sp, int64_t P, const double* q,
                                   (hipStream_t)stream, nullptr));
 }
 
+// One step of the grid's scheme on fields of type T (u_dst: blob velocities
+// of the step, or null).
+extern "C++" {
+template <typename T>
+static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t M,
+                            double* q, T* v, const double* Fext, const double* Gblob,
+                            const T* ffluid, double* u_dst, hipStream_t s) {
+    T* ff = (T*)g->d_ffield;
+    // forces at positions x, spread into the boxes (and folded with the
+    // fluid force when there is one)
+    auto forces = [&](const double* x) {
+        hipError_t e = bin_blobs<T>(g, M, x, s);
+        if (e == hipSuccess) e = scatter_springs<T>(g, sd, P, x, Fext, s, Gblob);
+        if (e == hipSuccess) e = spread_boxes<T>(g, s);
+        if (e == hipSuccess && ffluid) e = fold_boxes<T>(g, ff, s, ffluid);
+        return e;
+    };
+    auto solve = [&]() { return fluid_solve<T>(g, v, ff, v, s, !ffluid); };
+    hipError_t e;
+    if (g->scheme == MB_SCHEME_EULER) {
+        e = forces(q);
+        if (e == hipSuccess) e = solve();
+        if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 1, s);
+        return e;
+    }
+    // midpoint predictor-corrector: q* in d_mid, the second half of the
+    // interpolated velocity in d_mid + 3 max_blobs
+    double* qs = g->d_mid;
+    double* u2 = g->d_mid + 3 * std::max<int64_t>(g->d.max_blobs, 1);
+    e = blob_axpy(3 * M, nullptr, 1.0, q, qs, s);  // q* = q^n
+    if (g->d.mode == MB_STEADY_STOKES) {
+        // q* += (dt/2) J(q^n) v(q^n);  q += dt J(q*) v(q*)
+        if (e == hipSuccess) e = forces(q);
+        if (e == hipSuccess) e = solve();
+        if (e == hipSuccess) e = interpolate<T>(g, M, v, nullptr, qs, 0, s, 0.5);
+        if (e == hipSuccess) e = forces(qs);
+        if (e == hipSuccess) e = solve();
+        if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 1, s);
+        return e;
+    }
+    // q* += (dt/2) J(q^n) v^n on the records of q^n
+    if (e == hipSuccess) e = bin_blobs<T>(g, M, q, s);
+    if (e == hipSuccess) e = scatter_records<T>(g, M, q, nullptr, s);
+    if (e == hipSuccess) e = interpolate<T>(g, M, v, nullptr, qs, 0, s, 0.5);
+    // forces at q*; q += (dt/2) J(q*) v^n; solve; q += (dt/2) J(q*) v^{n+1}
+    if (e == hipSuccess) e = forces(qs);
+    if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 0, s, 0.5);
+    if (e == hipSuccess) e = solve();
+    if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst ? u2 : nullptr, q, 1, s, 0.5);
+    if (e == hipSuccess && u_dst) e = blob_add(3 * M, u2, u_dst, s);
+    return e;
+}
+}  // extern "C++"
+
+static hipError_t alloc_lazy(void** p, size_t bytes) {
+    if (*p) return hipSuccess;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+}
+
 static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
                            void* v, const double* Fext, const double* Gblob,
                            double* u_out, double* U0_out, double* diag_out,
@@ -461,45 +522,27 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
     hipStream_t s = (hipStream_t)stream;
     const SpringsDev sd = springs_dev(sp);
     const int fb = springs_blocks(sd, P);
+    hipError_t e = hipSuccess;
+    if (ffluid) e = alloc_lazy(&g->d_ffield, (size_t)3 * g->N * g->tiles.nbox * g->fsz);
+    if (e == hipSuccess && g->scheme == MB_SCHEME_MIDPOINT)
+        e = alloc_lazy((void**)&g->d_mid,
+                       (size_t)6 * std::max<int64_t>(g->d.max_blobs, 1) * sizeof(double));
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
     if (M == 0 && diag_out) {
         // no blobs: the force partials of the diagnostics are zero
-        hipError_t e0 = hipMemsetAsync(g->d_force_part, 0, 3 * sizeof(double), s);
-        if (e0 != hipSuccess) return from_hip(e0);
-    }
-    hipError_t e = hipSuccess;
-    if (ffluid && !g->d_ffield) {
-        e = hipMalloc(&g->d_ffield, (size_t)3 * g->N * g->tiles.nbox * g->fsz);
-        if (e != hipSuccess) {
-            g->d_ffield = nullptr;
-            return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
-        }
+        e = hipMemsetAsync(g->d_force_part, 0, 3 * sizeof(double), s);
+        if (e != hipSuccess) return from_hip(e);
     }
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
         const bool last = n == nsteps - 1;
         double* u_dst = nullptr;
         if (last) u_dst = u_out ? u_out : (U0_out ? g->d_u : nullptr);
-        // with a fluid force the spread boxes are folded into a field with
-        // it added, and the solve reads that field
-        if (g->fsz == 4) {
-            float* vv = (float*)v;
-            float* ff = (float*)g->d_ffield;
-            e = bin_blobs<float>(g, M, q, s);
-            if (e == hipSuccess) e = scatter_springs<float>(g, sd, P, q, Fext, s, Gblob);
-            if (e == hipSuccess) e = spread_boxes<float>(g, s);
-            if (e == hipSuccess && ffluid) e = fold_boxes<float>(g, ff, s, (const float*)ffluid);
-            if (e == hipSuccess) e = fluid_solve<float>(g, vv, ff, vv, s, !ffluid);
-            if (e == hipSuccess) e = interpolate<float>(g, M, vv, u_dst, q, 1, s);
-        } else {
-            double* vv = (double*)v;
-            double* ff = (double*)g->d_ffield;
-            e = bin_blobs<double>(g, M, q, s);
-            if (e == hipSuccess) e = scatter_springs<double>(g, sd, P, q, Fext, s, Gblob);
-            if (e == hipSuccess) e = spread_boxes<double>(g, s);
-            if (e == hipSuccess && ffluid)
-                e = fold_boxes<double>(g, ff, s, (const double*)ffluid);
-            if (e == hipSuccess) e = fluid_solve<double>(g, vv, ff, vv, s, !ffluid);
-            if (e == hipSuccess) e = interpolate<double>(g, M, vv, u_dst, q, 1, s);
-        }
+        if (g->fsz == 4)
+            e = step_once<float>(g, sd, P, M, q, (float*)v, Fext, Gblob, (const float*)ffluid,
+                                 u_dst, s);
+        else
+            e = step_once<double>(g, sd, P, M, q, (double*)v, Fext, Gblob,
+                                  (const double*)ffluid, u_dst, s);
         if (last && e == hipSuccess && U0_out)
             e = particle_means(g, P, sp->nb, u_dst, U0_out, s);
         if (last && e == hipSuccess && diag_out)
@@ -665,7 +708,7 @@ mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const dou
                           const double* ubar_loss, double* qbar, void* vbar,
                           double* Fblob_bar, double* kbar, double* r0bar, void* stream) {
     if (!g || !sp || !v_np1 || !vbar || P < 0) return MB_ERR_INVALID;
-    if (g->fsz != 8) return MB_ERR_UNSUPPORTED;
+    if (g->fsz != 8 || g->scheme != MB_SCHEME_EULER) return MB_ERR_UNSUPPORTED;
     const int64_t M = P * sp->nb;
     if (M > g->d.max_blobs) return MB_ERR_INVALID;
     if (P % g->tiles.nbox) return MB_ERR_INVALID;
@@ -730,6 +773,13 @@ mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const dou
     if (e == hipSuccess) e = springs_adjoint(sd, P, q_n, Fbar, qbar, kbar, r0bar, s, g);
     if (e == hipSuccess && Fblob_bar) e = blob_add(3 * M, Fbar, Fblob_bar, s);
     return from_hip(e);
+}
+
+mb_status mb_grid_set_scheme(mb_grid* g, int32_t scheme) {
+    if (!g || (scheme != MB_SCHEME_EULER && scheme != MB_SCHEME_MIDPOINT))
+        return MB_ERR_INVALID;
+    g->scheme = scheme;
+    return MB_OK;
 }
 
 mb_status mb_grid_set_timing(mb_grid* g, uint32_t kernel_mask) {

@@ -107,6 +107,8 @@ struct mb_grid {
     double* d_u;           // [max_blobs][3] blob velocities of the last step
     double* d_adj;         // reverse-step scratch (allocated on first use)
     void* d_ffield;        // force field of forced steps (allocated on first use)
+    double* d_mid;         // midpoint scheme: q* and a velocity per blob (first use)
+    int scheme;            // mb_scheme of the steps
     double* d_tile_part;   // [tiles][4]  (sum v_a, max |Dv|)
     double* d_force_part;  // [force blocks][3]
     int force_blocks_cap;
