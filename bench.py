@@ -17,7 +17,10 @@ roofline with the kernel's algorithmic bytes.  The oracle (float64, one CPU
 thread) is timed on a bounded sample of the same workload as the CPU
 baseline.
 
-Also measured (key "batch"): the pair-mobility sweep, 512 boxes of edge
+Also measured: the second-order (midpoint) scheme's step rate on the same
+workload (key "midpoint"); the steady-Stokes measurements (hydrodynamic
+radius against d, suspension viscosity) timed whole (key "stokes"); and
+(key "batch") the pair-mobility sweep, 512 boxes of edge
 24/32/48/64 with two particles each, grouped by edge into four grids of equal
 boxes and advanced by a graph-captured step of all four, against the same
 boxes advanced one grid per box.
@@ -137,6 +140,63 @@ def bench_precision(torch, w, prec, steps, warmup, live_kernel=None):
     }
 
 
+def bench_midpoint(torch, w, steps, warmup):
+    """Step rate of the second-order (midpoint) scheme on the same workload."""
+    from paper_1407_5600_amd import Grid, Springs
+    out = {}
+    for prec in ("mixed", "fp64"):
+        g = Grid(w.L, h=w.h, rho=w.rho, eta=w.eta, dt=w.dt, precision=prec, max_blobs=w.M,
+                 scheme="midpoint")
+        sp = Springs(w.nb, w.pa, w.pb, w.r0, w.k)
+        q = torch.from_numpy(w.q.copy()).cuda()
+        v = g.field()
+        Fe = torch.from_numpy(w.Fext).cuda()
+        run_steps(torch, g, sp, q, v, Fe, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_steps(torch, g, sp, q, v, Fe, steps)
+        torch.cuda.synchronize()
+        out[prec + "_steps_per_s"] = round(steps / (time.perf_counter() - t0), 2)
+    return out
+
+
+def bench_stokes(torch, oracle_sample=True):
+    """The steady-Stokes measurements at their default sizes, timed whole
+    (input generation excluded), with box-steps/s; the oracle timed on a few
+    steps of one such box."""
+    from paper_1407_5600_amd import stokes
+    rh = stokes.hydrodynamic_radius()
+    vis = stokes.viscosity()
+    out = {
+        "hydrodynamic_radius": {
+            "boxes": len(rh["d"]) * rh["orientations"], "L": rh["L"], "steps": rh["steps"],
+            "seconds": round(rh["seconds"], 4),
+            "box_steps_per_s": round(len(rh["d"]) * rh["orientations"] * rh["steps"]
+                                     / rh["seconds"], 1),
+            "R_H": {str(d["d"]): round(d["R_H"], 4) for d in rh["d"]}},
+        "viscosity": {
+            "boxes": len(vis["phi"]) * vis["configs"], "L": vis["L"], "steps": vis["steps"],
+            "seconds": round(vis["seconds"], 4),
+            "box_steps_per_s": round(len(vis["phi"]) * vis["configs"] * vis["steps"]
+                                     / vis["seconds"], 1),
+            "eta_rel": {str(p["phi"]): round(p["eta_rel"], 4) for p in vis["phi"]}},
+    }
+    if oracle_sample:
+        import numpy as np
+        import oracle
+        from paper_1407_5600_amd import inputs
+        setup = stokes.radius_setup((1.0,), rh["L"], 1)[0]
+        pa, pb, r0 = inputs.pair_table(setup[1])
+        prm = oracle.params(rh["L"], dt=rh["dt"], steady=True, zero_mean=True)
+        n = 5
+        t0 = time.perf_counter()
+        oracle.step(prm, {"nb": 13, "pa": pa, "pb": pb, "r0": r0, "k": 100.0}, setup[2],
+                    np.zeros((3, rh["L"], rh["L"], rh["L"])), setup[3], n)
+        out["oracle_box_steps_per_s"] = round(n / (time.perf_counter() - t0), 2)
+        out["oracle_sample"] = f"{n} float64 steps of one {rh['L']}^3 radius box, one thread"
+    return out
+
+
 def cpu_baseline(w, nsteps):
     import numpy as np
     import oracle
@@ -235,6 +295,8 @@ def main():
     ap.add_argument("--batch-boxes", type=int, default=512,
                     help="boxes of the batched pair-sweep measurement (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the midpoint-scheme and steady-Stokes measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 2^28 bytes, the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -307,6 +369,11 @@ def main():
     }
     if "fp64" in res:
         out["kernels_fp64"] = {k: round(ms, 5) for k, ms in res["fp64"]["per_step_ms"].items()}
+    if args.only is None and args.workload == "dense" and not args.no_extras:
+        print("[bench] midpoint scheme", file=sys.stderr, flush=True)
+        out["midpoint"] = bench_midpoint(torch, w, max(10, args.steps // 4), 5)
+        print("[bench] steady-Stokes measurements", file=sys.stderr, flush=True)
+        out["stokes"] = bench_stokes(torch, oracle_sample=not args.no_cpu_baseline)
     if args.batch_boxes > 0 and args.only is None:
         print(f"[bench] batched pair sweep ({args.batch_boxes} boxes)", file=sys.stderr,
               flush=True)
