@@ -292,6 +292,29 @@ mb_status mb_grid_set_timing(mb_grid* grid, uint32_t kernel_mask);
  * the first-order scheme only (MB_ERR_UNSUPPORTED otherwise).
  * MB_ERR_INVALID for an unknown scheme. */
 mb_status mb_grid_set_scheme(mb_grid* grid, int32_t scheme);
+
+/* Tiles of the binning, spreading and interpolation: boxes of tx x ty x tz
+ * cells, one workgroup each (the binning sorts blobs by tile).  Shapes with
+ * kernels: 16x8x8 (the default when 16 divides L, else 8x8x8), 8x8x8,
+ * 32x8x8, 16x16x8, 16x8x16, 8x16x16; each extent must divide L
+ * (MB_ERR_INVALID otherwise).  Results do not depend on the shape beyond
+ * rounding (the fixed-point scale of the spreading is per tile).  The call
+ * waits for the device and reallocates the grid's tile scratch
+ * (MB_ERR_NOMEM if that fails). */
+mb_status mb_grid_set_tiles(mb_grid* grid, int32_t tx, int32_t ty, int32_t tz);
+/* The current tile shape into shape_out[3]. */
+mb_status mb_grid_get_tiles(const mb_grid* grid, int32_t* shape_out);
+
+/* Tile autotuner: times `nsteps` steps (after one untimed step) of the given
+ * state with every tile shape that fits L, on copies of q and v (the
+ * caller's q and v are not changed), keeps the fastest shape in the grid
+ * and writes it to shape_out[3] (may be NULL).  Arguments as mb_step
+ * (nsteps >= 1); synchronises `stream`.  Allocates the copies for the
+ * duration of the call (MB_ERR_NOMEM if that fails). */
+mb_status mb_grid_autotune(mb_grid* grid, const mb_springs* springs,
+                           int64_t nparticles, const double* q, const void* v,
+                           const double* Fext, int32_t nsteps, void* stream,
+                           int32_t* shape_out);
 mb_status mb_grid_kernel_times(mb_grid* grid, void* stream, double* ms_out,
                                int64_t* launches_out, int32_t cap,
                                int32_t* n_out);

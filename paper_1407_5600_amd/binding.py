@@ -76,6 +76,9 @@ def lib():
             "mb_status_string": ([i32], ctypes.c_char_p),
             "mb_grid_set_timing": ([vp, ctypes.c_uint32], i32),
             "mb_grid_set_scheme": ([vp, i32], i32),
+            "mb_grid_set_tiles": ([vp, i32, i32, i32], i32),
+            "mb_grid_get_tiles": ([vp, vp], i32),
+            "mb_grid_autotune": ([vp, vp, i64, vp, vp, vp, i32, vp, vp], i32),
             "mb_grid_kernel_times": ([vp, vp, vp, vp, i32, ctypes.POINTER(i32)], i32),
             "mb_kernel_name": ([i32], ctypes.c_char_p),
         }
@@ -93,7 +96,8 @@ EXPORTED = ("mb_grid_create", "mb_grid_destroy", "mb_springs_create",
             "mb_grid_kernel_times", "mb_kernel_name", "mb_step_ext", "mb_spring_forces_ext",
             "mb_interpolate_grad", "mb_spring_adjoint", "mb_step_adjoint",
             "mb_grid_create_batch", "mb_step_graph", "mb_step_forced",
-            "mb_grid_set_scheme")
+            "mb_grid_set_scheme", "mb_grid_set_tiles", "mb_grid_get_tiles",
+            "mb_grid_autotune")
 
 
 def status_string(st: int) -> str:
@@ -189,6 +193,31 @@ class Grid:
         self.scheme = "euler"
         if scheme != "euler":
             self.set_scheme(scheme)
+
+    @property
+    def tiles(self):
+        """Tile shape (tx, ty, tz) of the binning, spreading and interpolation."""
+        out = (ctypes.c_int32 * 3)()
+        _check(lib().mb_grid_get_tiles(self.handle, out), "mb_grid_get_tiles")
+        return tuple(out)
+
+    def set_tiles(self, tx, ty, tz):
+        """mb_grid_set_tiles."""
+        _check(lib().mb_grid_set_tiles(self.handle, int(tx), int(ty), int(tz)),
+               "mb_grid_set_tiles")
+
+    def autotune(self, springs, q, v, Fext=None, nsteps=10, stream=None):
+        """mb_grid_autotune: time every tile shape on copies of (q, v), keep
+        the fastest; returns it."""
+        import torch
+        M = q.shape[0]
+        P = M // springs.nb
+        out = (ctypes.c_int32 * 3)()
+        _check(lib().mb_grid_autotune(
+            self.handle, springs.handle, P, _ptr(q, torch.float64, (M, 3), "q", self.device),
+            self._fptr(v, "v"), _ptr(Fext, torch.float64, (P, 3), "Fext", self.device),
+            int(nsteps), _stream(stream), out), "mb_grid_autotune")
+        return tuple(out)
 
     def set_scheme(self, scheme):
         """mb_grid_set_scheme: "euler" (first order) or "midpoint" (second)."""

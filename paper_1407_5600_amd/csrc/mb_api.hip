@@ -77,6 +77,44 @@ void upload_tables(mb_grid* g, std::vector<T>& tw, std::vector<T>& ds,
     }
 }
 
+// Tile geometry of a box of edge L cut into tiles of tx x ty x tz cells.
+Tiles make_tiles(int L, int nbox, int tx, int ty, int tz) {
+    Tiles t{};
+    t.tx = tx;
+    t.ty = ty;
+    t.tz = tz;
+    t.ntx = L / tx;
+    t.nty = L / ty;
+    t.ntz = L / tz;
+    t.n = t.ntx * t.nty * t.ntz;
+    t.remap = (t.n % 8 == 0 && t.n >= 64) ? 1 : 0;
+    t.nbox = nbox;
+    return t;
+}
+
+// (Re)allocates the scratch indexed by tile for g->tiles: counts (zeroed),
+// offsets, scan block sums, diagnostics partials (zeroed) and the spread
+// boxes.  The caller has synchronised any work using the old buffers.
+hipError_t alloc_tile_buffers(mb_grid* g) {
+    void* old[] = {g->d_count, g->d_offs, g->d_bsum, g->d_tile_part, g->d_box};
+    for (void* p : old)
+        if (p) (void)hipFree(p);
+    g->d_count = g->d_offs = g->d_bsum = nullptr;
+    g->d_tile_part = nullptr;
+    g->d_box = nullptr;
+    const int64_t ntiles = (int64_t)g->tiles.n * g->tiles.nbox;
+    g->nscan = (int)((ntiles + 4095) / 4096);
+    hipError_t e = hipMalloc((void**)&g->d_count, (size_t)ntiles * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&g->d_offs, (size_t)(ntiles + 1) * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&g->d_bsum, (size_t)g->nscan * sizeof(int));
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&g->d_tile_part, (size_t)ntiles * 4 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&g->d_box, box_elems(g->tiles) * g->fsz);
+    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)ntiles * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)ntiles * 4 * sizeof(double));
+    return e;
+}
+
 void free_grid(mb_grid* g) {
     if (!g) return;
     void* ptrs[] = {g->d_tw,    g->d_dsym,  g->d_d2,   g->d_spec,
@@ -203,30 +241,18 @@ mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox, mb_grid**
     g->fsz = d.precision == MB_MIXED ? 4 : 8;
     const int L = d.L;
     g->nblk_x = fft_x_blocks(L, d.precision);
-    // tiles: x extent 16 or 8 (dividing L), y and z extent 8
-    Tiles t{};
-    t.tx = (L % 16 == 0) ? 16 : 8;
-    // tuning override: MB_TILE_X = 8, 16 or 32 (must divide L)
-    if (const char* e = std::getenv("MB_TILE_X")) {
-        const int v = std::atoi(e);
-        if ((v == 8 || v == 16 || v == 32) && L % v == 0) t.tx = v;
-    }
-    t.ty = 8;
-    t.tz = 8;
-    t.ntx = L / t.tx;
-    t.nty = L / t.ty;
-    t.ntz = L / t.tz;
-    t.n = t.ntx * t.nty * t.ntz;
-    t.remap = (t.n % 8 == 0 && t.n >= 64) ? 1 : 0;
-    t.nbox = nbox;
+    // tiles: x extent 16 or 8 (dividing L), y and z extent 8 (mb_grid_set_tiles
+    // and mb_grid_autotune choose others)
+    const Tiles t = make_tiles(L, nbox, (L % 16 == 0) ? 16 : 8, 8, 8);
     g->tiles = t;
     g->rec_size = record_size(d.precision);
     // springs blocks hold at least one particle of at least one blob
     g->force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
     const int64_t ntiles = (int64_t)t.n * nbox;
-    if (ntiles + 1 > ((int64_t)1 << 30) || (int64_t)3 * g->N * nbox > ((int64_t)1 << 40))
+    if (ntiles + 1 > ((int64_t)1 << 30) || (int64_t)3 * g->N * nbox > ((int64_t)1 << 40)) {
+        delete g;
         return MB_ERR_INVALID;
-    g->nscan = (int)((ntiles + 4095) / 4096);
+    }
     g->perm_m = -1;
 
     const size_t cbytes = 2 * g->fsz;
@@ -239,20 +265,14 @@ mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox, mb_grid**
     alloc(&g->d_d2, (size_t)L * g->fsz);
     alloc(&g->d_spec, (size_t)nbox * 3 * L * L * g->NC * cbytes);
     alloc((void**)&g->d_psum, (size_t)nbox * g->nblk_x * 2 * sizeof(double));
-    alloc((void**)&g->d_count, (size_t)ntiles * sizeof(int));
-    alloc((void**)&g->d_offs, (size_t)(ntiles + 1) * sizeof(int));
-    alloc((void**)&g->d_bsum, (size_t)g->nscan * sizeof(int));
+    if (e == hipSuccess) e = alloc_tile_buffers(g);
     alloc((void**)&g->d_tile, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc((void**)&g->d_rank, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc((void**)&g->d_perm, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
     alloc(&g->d_rec, (size_t)std::max<int64_t>(d.max_blobs, 1) * g->rec_size);
-    alloc((void**)&g->d_tile_part, (size_t)ntiles * 4 * sizeof(double));
-    alloc(&g->d_box, box_elems(t) * g->fsz);
     alloc((void**)&g->d_u, (size_t)std::max<int64_t>(d.max_blobs, 1) * 3 * sizeof(double));
     alloc((void**)&g->d_force_part, (size_t)g->force_blocks_cap * 3 * sizeof(double));
-    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)ntiles * sizeof(int));
     if (e == hipSuccess) e = hipMemset(g->d_force_part, 0, (size_t)g->force_blocks_cap * 3 * sizeof(double));
-    if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)ntiles * 4 * sizeof(double));
     if (e == hipSuccess) {
         if (d.precision == MB_MIXED) {
             std::vector<float> tw, ds, d2;
@@ -779,6 +799,111 @@ mb_status mb_grid_set_scheme(mb_grid* g, int32_t scheme) {
     if (!g || (scheme != MB_SCHEME_EULER && scheme != MB_SCHEME_MIDPOINT))
         return MB_ERR_INVALID;
     g->scheme = scheme;
+    return MB_OK;
+}
+
+static bool tiles_fit(int L, int tx, int ty, int tz) {
+    return tile_shape_supported(tx, ty, tz) && L % tx == 0 && L % ty == 0 && L % tz == 0;
+}
+
+// Switch g to tiles of tx x ty x tz cells (waits for the device first).
+static mb_status set_tiles(mb_grid* g, int tx, int ty, int tz) {
+    if (g->tiles.tx == tx && g->tiles.ty == ty && g->tiles.tz == tz) return MB_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return from_hip(e);
+    g->tiles = make_tiles(g->L, g->tiles.nbox, tx, ty, tz);
+    e = alloc_tile_buffers(g);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : from_hip(e);
+    return MB_OK;
+}
+
+mb_status mb_grid_set_tiles(mb_grid* g, int32_t tx, int32_t ty, int32_t tz) {
+    if (!g || !tiles_fit(g->L, tx, ty, tz)) return MB_ERR_INVALID;
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    return set_tiles(g, tx, ty, tz);
+}
+
+mb_status mb_grid_get_tiles(const mb_grid* g, int32_t* shape_out) {
+    if (!g || !shape_out) return MB_ERR_INVALID;
+    shape_out[0] = g->tiles.tx;
+    shape_out[1] = g->tiles.ty;
+    shape_out[2] = g->tiles.tz;
+    return MB_OK;
+}
+
+mb_status mb_grid_autotune(mb_grid* g, const mb_springs* sp, int64_t P, const double* q,
+                           const void* v, const double* Fext, int32_t nsteps, void* stream,
+                           int32_t* shape_out) {
+    if (!g || !sp || !v || P < 0 || nsteps < 1) return MB_ERR_INVALID;
+    const int64_t M = P * sp->nb;
+    if (M > g->d.max_blobs || P % g->tiles.nbox || sp->device != g->device)
+        return MB_ERR_INVALID;
+    if (M > 0 && (!q || !aligned8(q))) return MB_ERR_INVALID;
+    mb_status st = enter(g);
+    if (st != MB_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t qbytes = (size_t)std::max<int64_t>(M, 1) * 3 * sizeof(double);
+    const size_t vbytes = (size_t)3 * g->N * g->tiles.nbox * g->fsz;
+    double* qc = nullptr;
+    void* vc = nullptr;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    hipError_t e = hipMalloc((void**)&qc, qbytes);
+    if (e == hipSuccess) e = hipMalloc(&vc, vbytes);
+    if (e == hipSuccess) e = hipEventCreate(&ea);
+    if (e == hipSuccess) e = hipEventCreate(&eb);
+    const uint32_t timing = g->timing;
+    g->timing = 0;
+    const Tiles start = g->tiles;
+    int best[3] = {start.tx, start.ty, start.tz};
+    float best_ms = 0.0f;
+    bool have = false;
+    // every candidate steps copies of the same state: one untimed step
+    // (binning from the previous order), then nsteps timed ones
+    auto trial = [&](int tx, int ty, int tz) {
+        if (e != hipSuccess || st != MB_OK) return;
+        st = set_tiles(g, tx, ty, tz);
+        if (st != MB_OK) return;
+        if (M > 0) e = hipMemcpyAsync(qc, q, (size_t)M * 3 * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(vc, v, vbytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return;
+        st = step_impl(g, sp, P, qc, vc, Fext, nullptr, nullptr, nullptr, nullptr, 1, s);
+        if (st != MB_OK) return;
+        e = hipEventRecord(ea, s);
+        if (e == hipSuccess)
+            st = step_impl(g, sp, P, qc, vc, Fext, nullptr, nullptr, nullptr, nullptr, nsteps, s);
+        if (st != MB_OK) return;
+        e = hipEventRecord(eb, s);
+        if (e == hipSuccess) e = hipEventSynchronize(eb);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+        if (e == hipSuccess && (!have || ms < best_ms)) {
+            have = true;
+            best_ms = ms;
+            best[0] = tx;
+            best[1] = ty;
+            best[2] = tz;
+        }
+    };
+#define MB_SHAPE(X, Y, Z) \
+    if (tiles_fit(g->L, X, Y, Z)) trial(X, Y, Z);
+    MB_TILE_SHAPES(MB_SHAPE)
+#undef MB_SHAPE
+    g->timing = timing;
+    if (e == hipSuccess && st == MB_OK) st = set_tiles(g, best[0], best[1], best[2]);
+    else (void)set_tiles(g, start.tx, start.ty, start.tz);
+    if (ea) (void)hipEventDestroy(ea);
+    if (eb) (void)hipEventDestroy(eb);
+    if (qc) (void)hipFree(qc);
+    if (vc) (void)hipFree(vc);
+    if (st != MB_OK) return st;
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : from_hip(e);
+    if (shape_out) {
+        shape_out[0] = best[0];
+        shape_out[1] = best[1];
+        shape_out[2] = best[2];
+    }
     return MB_OK;
 }
 

@@ -58,6 +58,13 @@ struct Tiles {
     int nbox;           // boxes of the grid (a batch of equal boxes)
 };
 
+// Tile shapes (tx, ty, tz) with instantiated spreading and interpolation
+// kernels: the LDS of the float32 interpolation (three components of the
+// (tx+3)(ty+3)(tz+3) box) stays under 64 KB.
+#define MB_TILE_SHAPES(X) X(16, 8, 8) X(8, 8, 8) X(32, 8, 8) X(16, 16, 8) X(16, 8, 16) X(8, 16, 16)
+
+bool tile_shape_supported(int tx, int ty, int tz);
+
 struct TimerPair {
     hipEvent_t a, b;
     int id;

@@ -1126,20 +1126,37 @@ size_t springs_lds(const SpringsDev& sp) {
            (size_t)(sp.nb + 1 + 2 * sp.npairs) * sizeof(int);
 }
 
-template <typename T, int TX>
-static void launch_spread(mb_grid* g, hipStream_t s) {
-    MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, TX, 8, 8>), g->tiles.n * g->tiles.nbox, BLK, 0,
-              (const Rec<T>*)g->d_rec, g->d_offs, g->L, g->tiles, (T*)g->d_box);
+// Tile shapes with instantiated spreading and interpolation kernels (cells
+// per axis; each a power of two dividing L).  fn receives the extents as
+// integral constants; false when the shape has no kernels.
+template <typename Fn>
+static bool with_tile_shape(const Tiles& t, Fn&& fn) {
+#define MB_SHAPE(X, Y, Z)                                                         \
+    if (t.tx == X && t.ty == Y && t.tz == Z) {                                    \
+        fn(std::integral_constant<int, X>{}, std::integral_constant<int, Y>{},    \
+           std::integral_constant<int, Z>{});                                     \
+        return true;                                                              \
+    }
+    MB_TILE_SHAPES(MB_SHAPE)
+#undef MB_SHAPE
+    return false;
+}
+
+bool tile_shape_supported(int tx, int ty, int tz) {
+#define MB_SHAPE(X, Y, Z) if (tx == X && ty == Y && tz == Z) return true;
+    MB_TILE_SHAPES(MB_SHAPE)
+#undef MB_SHAPE
+    return false;
 }
 
 template <typename T>
 hipError_t spread_boxes(mb_grid* g, hipStream_t s) {
-    switch (g->tiles.tx) {
-        case 32: launch_spread<T, 32>(g, s); break;
-        case 16: launch_spread<T, 16>(g, s); break;
-        default: launch_spread<T, 8>(g, s); break;
-    }
-    return hipGetLastError();
+    const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
+        MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
+                  g->tiles.n * g->tiles.nbox, BLK, 0, (const Rec<T>*)g->d_rec, g->d_offs,
+                  g->L, g->tiles, (T*)g->d_box);
+    });
+    return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -1149,46 +1166,30 @@ hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s, const T* add) {
     return hipGetLastError();
 }
 
-template <typename T, int TX>
-static void launch_interp(mb_grid* g, const T* v, double* u_out, double uscale,
-                          double* q, double* part, int kid, hipStream_t s) {
-    MB_LAUNCH(g, kid, s, (k_interp<T, TX, 8, 8>), g->tiles.n * g->tiles.nbox, BLK, 0,
-              (const Rec<T>*)g->d_rec, g->d_perm, g->d_offs, g->L, g->tiles, v,
-              u_out, uscale, q, g->d.dt, 1.0 / g->d.h, part);
-}
-
 template <typename T>
 hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
                        double* q_update, int diag, hipStream_t s, double uscale) {
     (void)M;
     double* part = diag ? g->d_tile_part : nullptr;
     const int kid = q_update ? K_INTERP_STEP : K_INTERP;
-    switch (g->tiles.tx) {
-        case 32: launch_interp<T, 32>(g, v, u_out, uscale, q_update, part, kid, s); break;
-        case 16: launch_interp<T, 16>(g, v, u_out, uscale, q_update, part, kid, s); break;
-        default: launch_interp<T, 8>(g, v, u_out, uscale, q_update, part, kid, s); break;
-    }
-    return hipGetLastError();
-}
-
-template <typename T, int TX>
-static void launch_interp_grad(mb_grid* g, const T* v, const double* W, double wscale,
-                               double* gout, hipStream_t s) {
-    MB_LAUNCH(g, K_INTERP_GRAD, s, (k_interp_grad<T, TX, 8, 8>), g->tiles.n * g->tiles.nbox,
-              BLK, 0,
-              (const Rec<T>*)g->d_rec, g->d_perm, g->d_offs, g->L, g->tiles, v, W, wscale,
-              1.0 / g->d.h, gout);
+    const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
+        MB_LAUNCH(g, kid, s, (k_interp<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
+                  g->tiles.n * g->tiles.nbox, BLK, 0, (const Rec<T>*)g->d_rec, g->d_perm,
+                  g->d_offs, g->L, g->tiles, v, u_out, uscale, q_update, g->d.dt,
+                  1.0 / g->d.h, part);
+    });
+    return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t interpolate_grad(mb_grid* g, const T* v, const double* W, double wscale,
                             double* gout, hipStream_t s) {
-    switch (g->tiles.tx) {
-        case 32: launch_interp_grad<T, 32>(g, v, W, wscale, gout, s); break;
-        case 16: launch_interp_grad<T, 16>(g, v, W, wscale, gout, s); break;
-        default: launch_interp_grad<T, 8>(g, v, W, wscale, gout, s); break;
-    }
-    return hipGetLastError();
+    const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
+        MB_LAUNCH(g, K_INTERP_GRAD, s, (k_interp_grad<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
+                  g->tiles.n * g->tiles.nbox, BLK, 0, (const Rec<T>*)g->d_rec, g->d_perm,
+                  g->d_offs, g->L, g->tiles, v, W, wscale, 1.0 / g->d.h, gout);
+    });
+    return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 
