@@ -17,8 +17,10 @@ roofline with the kernel's algorithmic bytes.  The oracle (float64, one CPU
 thread) is timed on a bounded sample of the same workload as the CPU
 baseline.
 
-Also measured: the second-order (midpoint) scheme's step rate on the same
-workload (key "midpoint"); the steady-Stokes measurements (hydrodynamic
+Also measured: the large suspension (256^3, phi = 0.4, 5,084,807 blobs),
+100 steps in each precision from the same state, with the mixed result's
+error against the float64 one (key "large"); the second-order (midpoint)
+scheme's step rate on the same workload (key "midpoint"); the steady-Stokes measurements (hydrodynamic
 radius against d, suspension viscosity) timed whole (key "stokes"); and
 (key "batch") the pair-mobility sweep, 512 boxes of edge
 24/32/48/64 with two particles each, grouped by edge into four grids of equal
@@ -57,6 +59,7 @@ def algorithmic_bytes(L, M, P, prec, steady=False):
         "springs_scatter": 24 * M + 24 * P + 12 * M + rec * M,
         "spread": rec * M + field,
         "fft_x_fwd": (1 if steady else 2) * field + spec,
+        "fft_xy_inv": spec + field,  # inverse y and x in one plane pass
         "fft_y_fwd": 2 * spec,
         "fft_z_spectral": 2 * spec,
         "fft_y_inv": 2 * spec,
@@ -157,6 +160,51 @@ def bench_midpoint(torch, w, steps, warmup):
         run_steps(torch, g, sp, q, v, Fe, steps)
         torch.cuda.synchronize()
         out[prec + "_steps_per_s"] = round(steps / (time.perf_counter() - t0), 2)
+    return out
+
+
+def bench_large(torch, steps):
+    """The large suspension (256^3, phi = 0.4, 391,139 particles, 5,084,807
+    blobs): `steps` steps from rest in each precision from the same state,
+    timed, and the mixed result's error against the float64 one (norm-wise
+    relative: displacements, final fluid velocity, last-step particle
+    velocities)."""
+    import numpy as np
+    from paper_1407_5600_amd import Grid, Springs, inputs
+    w = inputs.cached("large")
+    out = {"workload": f"large suspension {w.L}^3 h=1, {w.P} particles x {w.nb} blobs "
+                       f"({w.M} blobs), phi={w.extra.get('phi', '')}, dt={w.dt}, k={w.k}",
+           "steps": steps}
+    fin = {}
+    for prec in ("mixed", "fp64"):
+        g = Grid(w.L, h=w.h, rho=w.rho, eta=w.eta, dt=w.dt, precision=prec, max_blobs=w.M)
+        sp = Springs(w.nb, w.pa, w.pb, w.r0, w.k)
+        Fe = torch.from_numpy(w.Fext).cuda()
+        # one untimed step on a copy of the state (first binning)
+        qw = torch.from_numpy(w.q.copy()).cuda()
+        vw = g.field()
+        g.step(sp, qw, vw, Fe, 1)
+        del qw, vw
+        q = torch.from_numpy(w.q.copy()).cuda()
+        v = g.field()
+        U0 = torch.zeros((w.P, 3), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(sp, q, v, Fe, steps, U0_out=U0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec + "_steps_per_s"] = round(steps / dt, 2)
+        fin[prec] = {"dq": q.cpu().numpy() - w.q, "v": v.double().cpu().numpy(),
+                     "U0": U0.cpu().numpy()}
+        del g, sp, q, v, U0, Fe
+        torch.cuda.empty_cache()
+
+    def rel(a, b):
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+    out["mixed_over_fp64"] = round(out["mixed_steps_per_s"] / out["fp64_steps_per_s"], 3)
+    out["mixed_vs_fp64_rel_err"] = {k: rel(fin["mixed"][k], fin["fp64"][k])
+                                    for k in ("dq", "v", "U0")}
     return out
 
 
@@ -295,6 +343,8 @@ def main():
     ap.add_argument("--batch-boxes", type=int, default=512,
                     help="boxes of the batched pair-sweep measurement (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--large-steps", type=int, default=100,
+                    help="steps per precision of the 256^3 phi = 0.4 suspension (0: skip it)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the midpoint-scheme and steady-Stokes measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -369,6 +419,10 @@ def main():
     }
     if "fp64" in res:
         out["kernels_fp64"] = {k: round(ms, 5) for k, ms in res["fp64"]["per_step_ms"].items()}
+    if args.only is None and args.workload == "dense" and args.large_steps > 0:
+        print(f"[bench] large suspension ({args.large_steps} steps per precision)",
+              file=sys.stderr, flush=True)
+        out["large"] = bench_large(torch, args.large_steps)
     if args.only is None and args.workload == "dense" and not args.no_extras:
         print("[bench] midpoint scheme", file=sys.stderr, flush=True)
         out["midpoint"] = bench_midpoint(torch, w, max(10, args.steps // 4), 5)

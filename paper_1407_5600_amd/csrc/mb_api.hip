@@ -27,7 +27,8 @@ const char* const kKernelNames[K_NUM] = {
     "springs_scatter", "bin_scatter", "springs",      "spread",
     "fft_x_fwd",   "fft_y_fwd",   "fft_z_spectral",   "fft_y_inv",
     "fft_x_inv",   "interp",      "interp_step",      "u0",
-    "diag",        "fold",        "interp_grad",      "springs_adjoint"};
+    "diag",        "fold",        "interp_grad",      "springs_adjoint",
+    "fft_xy_inv"};
 
 bool size_ok(int L) {
     if (L < 8 || L > 512 || L % 8 != 0) return false;

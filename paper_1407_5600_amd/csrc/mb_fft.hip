@@ -162,6 +162,22 @@ __device__ __forceinline__ void line_fft(cplx<T>* buf, const cplx<T>* tw, int ti
     __syncthreads();
 }
 
+// In-place transform of NLINES lines of length N held in LDS at
+// buf[idx(line, e)] (any layout), every stage in LDS; ends with a barrier.
+template <typename T, int N, bool INV, int NLINES, int NTHR, bool LFAST, int S = 0,
+          typename IX>
+__device__ __forceinline__ void lds_fft(cplx<T>* buf, const cplx<T>* tw, int tid,
+                                        const IX& idx) {
+    if constexpr (S < nstages(N)) {
+        auto ld = [buf, &idx](int line, int e) { return buf[idx(line, e)]; };
+        auto st = [buf, &idx](int line, int e, cplx<T> x) { buf[idx(line, e)] = x; };
+        stage_io<T, N, radix_at(N, S), ns_at(N, S), INV, NLINES, NTHR, LFAST, true>(tw, tid,
+                                                                                   ld, st);
+        __syncthreads();
+        lds_fft<T, N, INV, NLINES, NTHR, LFAST, S + 1>(buf, tw, tid, idx);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launch geometry per size.
 constexpr int largest_even_divisor(int L, int cap) {
@@ -180,9 +196,12 @@ constexpr int cols_y(int L) {
     const int nc = L / 2 + 1;
     return w < nc ? w : nc;
 }
-// ky columns per block of the z pass (a divisor of L; LDS <= 64 KB)
+// ky columns per block of the z pass (a divisor of L; LDS <= 64 KB).  At
+// 128^3 eight columns give 1,040 blocks of 384 threads, which fill the CUs
+// in one round (sixteen gave 520 blocks of 768 threads: two per CU, and a
+// nearly empty second round).
 #ifndef MB_ZCOLS
-#define MB_ZCOLS 16
+#define MB_ZCOLS 8
 #endif
 template <typename T>
 constexpr int cols_z(int L) {
@@ -206,6 +225,18 @@ struct Geo {
     static constexpr int WZ = cols_z<T>(L);
     static constexpr int TZ = 3 * WZ * L / EPT;
     static constexpr int NBX = 3 * L * (L / R);  // blocks of an x pass
+    static_assert(NBX % 8 == 0, "x-pass blocks are remapped over the 8 XCDs");
+    // inverse plane pass (y and x together, one (component, z) plane per
+    // block): the plane as H = L/2 complex columns, row stride PS (room for
+    // the padded column H of the staged half spectrum, odd)
+    static constexpr int H = L / 2;
+    static constexpr int PS = (lpad(H) + 1) | 1;
+    static constexpr int PLANE_BYTES = L * PS * 2 * (int)sizeof(T);
+    // used when two planes fit in a CU's 160 KB of LDS
+    static constexpr bool XY = PLANE_BYTES <= 72 * 1024;
+    static constexpr int TXY_RAW = ((L * H / 16 + WAVE - 1) / WAVE) * WAVE;
+    static constexpr int TXY = TXY_RAW > 512 ? 512 : TXY_RAW;  // threads
+    static constexpr int NBXY = 3 * L;                         // blocks per box
 };
 
 // ---------------------------------------------------------------------------
@@ -220,9 +251,12 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
     __shared__ cplx<T> tws[L];
     __shared__ double red[16];
     const int tid = threadIdx.x;
-    // blocks of a box are consecutive (G::NBX per box)
+    // blocks of a box are consecutive (G::NBX per box, a multiple of 8);
+    // within a box each XCD takes a contiguous range of (c, z, y) rows, so
+    // the rows of the Laplacian's z and y neighbours, read by adjacent
+    // blocks, are found in that XCD's L2
     const int box = blockIdx.x / G::NBX;
-    const int lb = blockIdx.x - box * G::NBX;
+    const int lb = xcd_remap(blockIdx.x - box * G::NBX, G::NBX);
     const int yb = lb % (L / R);
     const int cz = lb / (L / R);  // c * L + z
     const int z = cz % L;
@@ -313,8 +347,9 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
     const double ts = block_reduce<false>(sv, red);
     const double tf = block_reduce<false>(sf, red);
     if (tid == 0) {
-        psum[2 * blockIdx.x] = ts;
-        psum[2 * blockIdx.x + 1] = tf;
+        const size_t pb = (size_t)box * G::NBX + lb;  // component-major order
+        psum[2 * pb] = ts;
+        psum[2 * pb + 1] = tf;
     }
 }
 
@@ -356,7 +391,7 @@ template <typename T, int L>
 __global__ void __launch_bounds__((Geo<T, L>::TZ))
 k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
           const cplx<T>* __restrict__ dsym, const T* __restrict__ d2, T c0, T c1,
-          int zero_mean_mode, const double* __restrict__ psum, double mv,
+          int zero_mean_mode, const double* __restrict__ psum, int per_c, double mv,
           double mf) {
     using G = Geo<T, L>;
     constexpr int NC = G::NC, W = G::WZ, NTHR = G::TZ, LS = G::LS;
@@ -366,17 +401,20 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     __shared__ double red[16];
     __shared__ double mean_new[3];
     const int tid = threadIdx.x;
-    // blocks of a box are consecutive (NC L / W per box)
-    const int box = blockIdx.x / (NC * (L / W));
-    const int lblk = blockIdx.x - box * (NC * (L / W));
+    // blocks of a box are consecutive (NC L / W per box); when their count
+    // is a multiple of 8 each XCD takes a contiguous range, so the blocks
+    // sharing the cache lines of a ky segment meet in one L2
+    constexpr int NZB = NC * (L / W);
+    const int box = blockIdx.x / NZB;
+    const int lblk = NZB % 8 == 0 ? xcd_remap(blockIdx.x - box * NZB, NZB)
+                                  : blockIdx.x - box * NZB;
     const int ch = lblk % (L / W);
     const int kx = lblk / (L / W);
     const int ky0 = ch * W;
     A += (size_t)box * 3 * L * NC * L;
-    psum += (size_t)box * G::NBX * 2;
+    psum += (size_t)box * 3 * per_c * 2;  // per_c partials per component
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
     if (kx == 0 && ch == 0) {
-        constexpr int per_c = G::NBX / 3;
         for (int c = 0; c < 3; ++c) {
             double s = 0.0;
             for (int i = tid; i < per_c; i += NTHR) {
@@ -502,6 +540,100 @@ k_x_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     line_fft_io<T, L, true, NL, LS, NTHR, false, false, false>(buf, tws, tid, ld, st);
 }
 
+// Inverse plane pass: y and x together for one (component, z) plane per
+// block, the plane held in LDS.  The real plane v[y][x] is produced as H =
+// L/2 complex columns Z[y][j] = v[y][2j] + i v[y][2j+1]: from the half
+// spectrum F[kx][ky] (kx = 0..H, layout A[c][z][kx][ky] of the z pass),
+//   Z'[ky][k] = E' + i O',  E' = F[ky][k] + conj F[-ky][H-k],
+//   O' = (F[ky][k] - conj F[-ky][H-k]) W^-k   (W = e^{-2 pi i / L}),
+// the spectra of the even and odd samples (F[ky][k + H] = conj F[-ky][H-k]
+// for a real plane), then inverse transforms along y (L points) and j
+// (H points); Z[y][j] is the row pair (v[y][2j], v[y][2j+1]), unnormalised
+// like the rest of the solve.  Element (row, column) of the plane sits at
+// row * PS + lpad(column).
+template <typename T, int L>
+__global__ void __launch_bounds__((Geo<T, L>::TXY))
+k_xy_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
+         T* __restrict__ vout) {
+    using G = Geo<T, L>;
+    constexpr int H = G::H, PS = G::PS, NC = G::NC, NTHR = G::TXY;
+    __shared__ cplx<T> buf[L * PS];
+    __shared__ cplx<T> tws[L];
+    __shared__ cplx<T> twh[H];
+    const int tid = threadIdx.x;
+    const int cz = blockIdx.x;  // (box * 3 + c) * L + z
+    for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
+    for (int i = tid; i < H; i += NTHR) twh[i] = tw[2 * i];
+    // stage the half spectrum: F[kx][ky] at row ky, column kx (0..H)
+    const cplx<T>* in = A + (size_t)cz * NC * L;
+    {
+        // every load of the thread issued before the LDS stores (at most 17
+        // complex values per thread: K <= (L/2 + 1) L / NTHR)
+        constexpr int K = (NC * L + NTHR - 1) / NTHR;
+        cplx<T> ld[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = tid + k * NTHR;
+            ld[k] = in[e < NC * L ? e : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = tid + k * NTHR;
+            if (e < NC * L) {
+                const int kx = e / L;
+                const int ky = e - kx * L;
+                buf[ky * PS + lpad(kx)] = ld[k];
+            }
+        }
+    }
+    __syncthreads();
+    // Z'[ky][k] in place.  Slot (ky, k) and its partner (-ky, H - k) are
+    // formed from each other, so each work item owns both (k = 1 .. H/2;
+    // at k = H/2 only ky <= L/2); column 0 pairs with column H:
+    // Z'[ky][0] = F[ky][0] + conj F[-ky][H] + i (F[ky][0] - conj F[-ky][H]).
+    {
+        constexpr int NPAIR = L * (H / 2);  // items (ky, k), k = 1 .. H/2 (k = H/2: ky <= L/2)
+        for (int e = tid; e < NPAIR + L / 2 + 1; e += NTHR) {
+            if (e < NPAIR) {
+                const int k = 1 + e / L;
+                const int ky = e - (k - 1) * L;
+                if (k == H / 2 && ky > L / 2) continue;
+                const int kyn = ky == 0 ? 0 : L - ky;
+                const int kn = H - k;
+                const cplx<T> F1 = buf[ky * PS + lpad(k)];
+                const cplx<T> F2 = buf[kyn * PS + lpad(kn)];
+                // slot (ky, k): F1 with conj F2; slot (-ky, H-k): F2 with conj F1
+                const cplx<T> w1 = cconj(tws[k]);   // W^-k
+                const cplx<T> w2 = cconj(tws[kn]);  // W^-(H-k)
+                const cplx<T> e1 = cadd(F1, cconj(F2)), o1 = cmul(csub(F1, cconj(F2)), w1);
+                const cplx<T> e2 = cadd(F2, cconj(F1)), o2 = cmul(csub(F2, cconj(F1)), w2);
+                buf[ky * PS + lpad(k)] = cplx<T>{e1.x - o1.y, e1.y + o1.x};
+                if (kyn != ky || kn != k)
+                    buf[kyn * PS + lpad(kn)] = cplx<T>{e2.x - o2.y, e2.y + o2.x};
+            } else {
+                const int ky = e - NPAIR;  // 0 .. L/2
+                const int kyn = ky == 0 ? 0 : L - ky;
+                const cplx<T> Fa0 = buf[ky * PS + lpad(0)], FaH = buf[ky * PS + lpad(H)];
+                const cplx<T> Fb0 = buf[kyn * PS + lpad(0)], FbH = buf[kyn * PS + lpad(H)];
+                const cplx<T> e1 = cadd(Fa0, cconj(FbH)), o1 = csub(Fa0, cconj(FbH));
+                const cplx<T> e2 = cadd(Fb0, cconj(FaH)), o2 = csub(Fb0, cconj(FaH));
+                buf[ky * PS + lpad(0)] = cplx<T>{e1.x - o1.y, e1.y + o1.x};
+                if (kyn != ky) buf[kyn * PS + lpad(0)] = cplx<T>{e2.x - o2.y, e2.y + o2.x};
+            }
+        }
+    }
+    __syncthreads();
+    auto col = [](int line, int e) { return e * PS + lpad(line); };
+    lds_fft<T, L, true, H, NTHR, true>(buf, tws, tid, col);
+    // along x; the last stage stores each complex Z'[y][j] as the real pair
+    // v[y][2j], v[y][2j+1]
+    cplx<T>* out = reinterpret_cast<cplx<T>*>(vout + (size_t)cz * L * L);
+    const cplx<T>* lb = buf;
+    auto ldl = [lb](int line, int e) { return lb[line * PS + lpad(e)]; };
+    auto gst = [out](int line, int e, cplx<T> x) { out[line * H + e] = x; };
+    line_fft_io<T, H, true, L, PS, NTHR, false, true, false>(buf, twh, tid, ldl, gst);
+}
+
 template <typename T, int L>
 hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, bool boxed, T* v_out,
                        hipStream_t s) {
@@ -535,9 +667,15 @@ hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, bool boxed, T* v_o
     const int zm = (steady || g->d.zero_mean) ? 1 : 0;
     MB_LAUNCH(g, K_FFT_Z_SPECTRAL, s, (k_z_solve<T, L>), G::NC * (L / G::WZ) * nbox, G::TZ, 0,
               A, tw, (const cplx<T>*)g->d_dsym, (const T*)g->d_d2, c0, c1, zm,
-              g->d_psum, mv, mf);
-    MB_LAUNCH(g, K_FFT_Y_INV, s, (k_y<T, L, true>), 3 * L * G::NCHY * nbox, G::TY, 0, A, tw);
-    MB_LAUNCH(g, K_FFT_X_INV, s, (k_x_inv<T, L>), G::NBX * nbox, G::TX, 0, A, tw, v_out);
+              g->d_psum, G::NBX / 3, mv, mf);
+    if constexpr (G::XY) {
+        MB_LAUNCH(g, K_FFT_XY_INV, s, (k_xy_inv<T, L>), G::NBXY * nbox, G::TXY, 0, A, tw,
+                  v_out);
+    } else {
+        MB_LAUNCH(g, K_FFT_Y_INV, s, (k_y<T, L, true>), 3 * L * G::NCHY * nbox, G::TY, 0, A,
+                  tw);
+        MB_LAUNCH(g, K_FFT_X_INV, s, (k_x_inv<T, L>), G::NBX * nbox, G::TX, 0, A, tw, v_out);
+    }
     return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ enum KernelId : int {
     K_FOLD,
     K_INTERP_GRAD,
     K_SPRINGS_ADJ,
+    K_FFT_XY_INV,
     K_NUM
 };
 

@@ -197,7 +197,7 @@ def test_fluid_solve_large_shear_mode(torch_cuda, prec, L):
     assert err < tol and err_rest < tol
 
 
-def _step_case(torch, w, prec, nsteps, v0=None, check_factor=1.0, **kw):
+def _step_case(torch, w, prec, nsteps, v0=None, check_factor=1.0, ref=None, **kw):
     from paper_1407_5600_amd import Springs
     g = grid(w.L, prec, w.M, rho=w.rho, eta=w.eta, dt=w.dt, **kw)
     sp = Springs(w.nb, w.pa, w.pb, w.r0, w.k)
@@ -213,7 +213,7 @@ def _step_case(torch, w, prec, nsteps, v0=None, check_factor=1.0, **kw):
     prm = oracle.params(w.L, rho=w.rho, eta=w.eta, dt=w.dt,
                         steady=kw.get("mode") == "steady",
                         zero_mean=kw.get("zero_mean", False))
-    r = oracle.step(prm, w.springs(), w.q, vstart, w.Fext, nsteps)
+    r = ref if ref is not None else oracle.step(prm, w.springs(), w.q, vstart, w.Fext, nsteps)
     name = f"step {w.name} {prec} n={nsteps}"
     check(name + " u", u.cpu().numpy(), r["u"], prec, check_factor)
     check(name + " U0", U0.cpu().numpy(), r["U0"], prec, check_factor)
@@ -241,6 +241,8 @@ def _step_case(torch, w, prec, nsteps, v0=None, check_factor=1.0, **kw):
     check(name + " sumF", d[3:6], r["diag"][3:6], prec, check_factor,
           floor=np.linalg.norm(Fmag))
     assert d[6] < (1e-10 if prec == "fp64" else 1e-3) * max(1.0, np.abs(r["v"]).max())
+    g.last = {"u": u.cpu().numpy(), "U0": U0.cpu().numpy(), "v": v.double().cpu().numpy(),
+              "q": qg}
     return g, r
 
 
@@ -300,6 +302,33 @@ def test_step_dense_full_size(torch_cuda, prec):
     say("step dense 128^3", prec)
     w = inputs.cached("dense")
     _step_case(torch, w, prec, 1)
+
+
+def test_step_large_full_size(torch_cuda):
+    """The 256^3, phi = 0.4 suspension (391,139 particles, 5,084,807 blobs):
+    one step in float64 and one in mixed precision, in the launch
+    configuration the benchmark times, each against the same oracle step
+    (every output); the mixed step's error against the float64 step is
+    printed."""
+    torch = torch_cuda
+    w = inputs.cached("large")
+    L = w.L
+    say(f"step large {L}^3: oracle step of {w.M} blobs (about a minute on one core)")
+    prm = oracle.params(L, rho=w.rho, eta=w.eta, dt=w.dt)
+    ref = oracle.step(prm, w.springs(), w.q, np.zeros((3, L, L, L)), w.Fext, 1)
+    say("step large: oracle done")
+    last = {}
+    for prec in ("fp64", "mixed"):
+        say(f"step large {L}^3 {prec}")
+        g, _ = _step_case(torch, w, prec, 1, ref=ref)
+        last[prec] = g.last
+        del g
+        torch.cuda.empty_cache()
+    for k in ("u", "U0", "v"):
+        say(f"step large: mixed vs float64 {k}: rel err {rel(last['mixed'][k], last['fp64'][k]):.3e}")
+    dq = {p: last[p]["q"] - w.q for p in last}
+    say(f"step large: mixed vs float64 dq: rel err {rel(dq['mixed'], dq['fp64']):.3e}")
+    assert rel(last["mixed"]["U0"], last["fp64"]["U0"]) < TOL["mixed"]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
