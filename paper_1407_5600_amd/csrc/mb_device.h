@@ -39,6 +39,20 @@ __device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) {
     return INV ? cplx<T>{-a.y, a.x} : cplx<T>{a.y, -a.x};
 }
 
+// 1/sqrt(x) for a normal float64 x > 0: the hardware estimate refined by
+// two Newton steps y <- y + y (1/2 - x y^2 / 2) for the root of 1/y^2 - x,
+// each of which squares the relative error (an estimate good to 2^-14
+// ends below the float64 rounding).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double r = fma(-(x * y), 0.5 * y, 0.5);
+        y = fma(y, r, y);
+    }
+    return y;
+}
+
 // Weights of the 3-point kernel at the nodes i0-1, i0, i0+1 of a point at
 // offset t in [-1/2, 1/2] from node i0 (t = x/h - i0).  With s = sqrt(1-3t^2):
 // Phi(t) = (1+s)/3 and Phi(1 -+ t) = (2 +- 3t - s)/6.

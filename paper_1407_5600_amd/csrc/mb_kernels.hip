@@ -42,15 +42,17 @@ struct Geom {
 // Cell, rounding bits and kernel offsets of a position (float64).  For the
 // node set of velocity component a along axis b the node coordinate is
 // x = q_b/h - (1/2) delta_ab; the nearest node is i0 = floor(x + 1/2) and
-// t = x - i0 in [-1/2, 1/2).
+// t = x - i0 in [-1/2, 1/2).  q_b/h is formed as q_b (1/h) (exact for h a
+// power of two, else within an ulp; at a tie of the rounding either node
+// set gives the same sums, the kernel vanishing at 3/2).
 __device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
-                                          int64_t i, double h, int L) {
+                                          int64_t i, double inv_h, int L) {
     Geom g;
     const double Ld = (double)L;
     const double invL = 1.0 / Ld;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        const double x = q[3 * i + b] / h;
+        const double x = q[3 * i + b] * inv_h;
         const double fl = floor(x);
         const double s = x - fl;  // [0, 1)
         // fl mod L without integer division: exact for |fl| < 2^53, the
@@ -118,7 +120,7 @@ constexpr int TILE_WIN = 64;
 
 __global__ void __launch_bounds__(BLK)
 k_tile_count(const double* __restrict__ q, const int* __restrict__ order,
-             int64_t M, int64_t mbox, double h, int L, Tiles tl, int* __restrict__ count,
+             int64_t M, int64_t mbox, double inv_h, int L, Tiles tl, int* __restrict__ count,
              int* __restrict__ tile_of, int* __restrict__ rank) {
     __shared__ int lcount[TILE_WIN];
     __shared__ int lbase[TILE_WIN];
@@ -129,7 +131,7 @@ k_tile_count(const double* __restrict__ q, const int* __restrict__ order,
     int t = 0;
     if (j < M) {
         i = order ? order[j] : j;
-        const Geom g = blob_geom(q, i, h, L);
+        const Geom g = blob_geom(q, i, inv_h, L);
         t = (int)(i / mbox) * tl.n + tile_linear(g.c, tl);  // box i / mbox
     }
     if (threadIdx.x == 0) t0s = t;  // block 0's first blob exists (M > 0)
@@ -225,13 +227,13 @@ __device__ __forceinline__ void write_record(Rec<T>* __restrict__ rec,
 template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
-              int64_t M, double h, int L, double inv_vol,
+              int64_t M, double inv_h, int L, double inv_vol,
               const int* __restrict__ offs, const int* __restrict__ tile_of,
               const int* __restrict__ rank, Rec<T>* __restrict__ rec,
               int* __restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (i >= M) return;
-    const Geom g = blob_geom(q, i, h, L);
+    const Geom g = blob_geom(q, i, inv_h, L);
     double f[3] = {0.0, 0.0, 0.0};
     if (F) {
         f[0] = F[3 * i];
@@ -328,8 +330,9 @@ __device__ __forceinline__ void springs_forces(const SpringsDev& sp, const Sprin
         const int o = code & 0xff;
         const double* qo = qp + 3 * o;
         const double dx = qo[0] - qx, dy = qo[1] - qy, dz = qo[2] - qz;
-        const double len = sqrt(dx * dx + dy * dy + dz * dz);
-        const double s = sp.k * (len - B.r0s[code >> 8]) / len;
+        // k (|d| - r0) / |d| = k - k r0 / |d|
+        const double inv_len = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+        const double s = fma(-(sp.k * B.r0s[code >> 8]), inv_len, sp.k);
         fx += s * dx;
         fy += s * dy;
         fz += s * dz;
@@ -348,7 +351,7 @@ template <typename T>
 __global__ void __launch_bounds__(BLK)
 k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
                   const double* __restrict__ Fext, const double* __restrict__ Gblob,
-                  int64_t P, double h, int L,
+                  int64_t P, double inv_h, int L,
                   double inv_vol, const int* __restrict__ offs,
                   const int* __restrict__ tile_of, const int* __restrict__ rank,
                   Rec<T>* __restrict__ rec, int* __restrict__ perm,
@@ -371,7 +374,7 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
     int64_t i;
     springs_forces(sp, B, fe, F, &i);
     if (i >= 0) {
-        const Geom g = blob_geom(B.qs, threadIdx.x, h, L);
+        const Geom g = blob_geom(B.qs, threadIdx.x, inv_h, L);
         write_record<T>(rec, perm, (int64_t)off + rk, i, g, F, inv_vol);
     }
     double tot[3] = {F[0], F[1], F[2]};
@@ -757,9 +760,16 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     // the thread's first record and its blob, loaded once
     Rec<T> r0{};
     int64_t i0 = -1;
+    double q0[3] = {0.0, 0.0, 0.0};  // its position, fetched before the staging
     if (pos0 >= 0) {
         r0 = rec[pos0];
         i0 = perm[pos0];
+        // blob i0 belongs to this record only: no other thread updates it
+        if (q) {
+            q0[0] = q[3 * i0];
+            q0[1] = q[3 * i0 + 1];
+            q0[2] = q[3 * i0 + 2];
+        }
     }
     __syncthreads();  // rowoff
     double u0[3] = {0.0, 0.0, 0.0};  // velocity of the first record
@@ -862,21 +872,36 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
             u_out[3 * i + 2] = u0[2];
         }
         if (q) {
-            q[3 * i] += dt * u0[0];
-            q[3 * i + 1] += dt * u0[1];
-            q[3 * i + 2] += dt * u0[2];
+            q[3 * i] = q0[0] + dt * u0[0];
+            q[3 * i + 1] = q0[1] + dt * u0[1];
+            q[3 * i + 2] = q0[2] + dt * u0[2];
         }
     }
     if (part) {
+        // the three sums and the max over the block, combined by thread 0
         double dmax = 0.0;
 #pragma unroll
         for (int j = 0; j < CPT; ++j) dmax = fmax(dmax, fabs(dv[j]) * inv_h);
-        for (int a = 0; a < 3; ++a) {
-            const double s = block_reduce<false>(sv[a], red);
-            if (threadIdx.x == 0) part[4 * tile + a] = s;
+        double w4[4] = {wave_sum(sv[0]), wave_sum(sv[1]), wave_sum(sv[2]), wave_max(dmax)};
+        constexpr int NW = BLK / WAVE;
+        static_assert(4 * NW <= 16, "reduction scratch");
+        const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[4 * wid + c] = w4[c];
         }
-        const double m = block_reduce<true>(dmax, red);
-        if (threadIdx.x == 0) part[4 * tile + 3] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t4[4] = {red[0], red[1], red[2], red[3]};
+            for (int w = 1; w < NW; ++w) {
+                t4[0] += red[4 * w];
+                t4[1] += red[4 * w + 1];
+                t4[2] += red[4 * w + 2];
+                t4[3] = fmax(t4[3], red[4 * w + 3]);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) part[4 * tile + c] = t4[c];
+        }
     }
 }
 
@@ -1029,7 +1054,7 @@ hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
         // the previous sorted order, when it is a permutation of these blobs
         const int* order = g->perm_m == M ? g->d_perm : nullptr;
         MB_LAUNCH(g, K_BIN_COUNT, s, k_tile_count, blocks_for(M), BLK, 0, q, order, M,
-                  M / g->tiles.nbox, g->d.h, g->L, g->tiles, g->d_count, g->d_tile,
+                  M / g->tiles.nbox, 1.0 / g->d.h, g->L, g->tiles, g->d_count, g->d_tile,
                   g->d_rank);
     }
     if (g->nscan > 1)
@@ -1047,7 +1072,7 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
     const double h = g->d.h;
     const double sc = fscale > 0.0 ? fscale : 1.0 / (h * h * h);
     MB_LAUNCH(g, K_BIN_SCATTER, s, k_bin_scatter<T>, blocks_for(M), BLK, 0, q, F,
-              M, h, g->L, sc, g->d_offs, g->d_tile, g->d_rank,
+              M, 1.0 / h, g->L, sc, g->d_offs, g->d_tile, g->d_rank,
               (Rec<T>*)g->d_rec, g->d_perm);
     g->perm_m = M;
     return hipGetLastError();
@@ -1061,7 +1086,7 @@ hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
     if (M == 0) return hipSuccess;
     const double h = g->d.h;
     MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, springs_blocks(sp, P), BLK,
-              springs_lds(sp), sp, q, Fext, Gblob, P, h, g->L, 1.0 / (h * h * h), g->d_offs,
+              springs_lds(sp), sp, q, Fext, Gblob, P, 1.0 / h, g->L, 1.0 / (h * h * h), g->d_offs,
               g->d_tile, g->d_rank, (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part);
     g->perm_m = M;
     return hipGetLastError();
