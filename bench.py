@@ -101,8 +101,10 @@ def measured_traffic(kernel):
 
 
 def run_steps(torch, g, sp, q, v, Fe, n):
-    for _ in range(n):
-        g.step(sp, q, v, Fe, 1)
+    # one call of n steps (steps after a call's first take their binning
+    # from the previous step's interpolation)
+    if n > 0:
+        g.step(sp, q, v, Fe, n)
 
 
 def bench_precision(torch, w, prec, steps, warmup, live_kernel=None):

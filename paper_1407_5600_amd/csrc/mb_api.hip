@@ -472,12 +472,13 @@ extern "C++" {
 template <typename T>
 static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t M,
                             double* q, T* v, const double* Fext, const double* Gblob,
-                            const T* ffluid, double* u_dst, hipStream_t s) {
+                            const T* ffluid, double* u_dst, hipStream_t s,
+                            bool binned = false, bool bin_next = false) {
     T* ff = (T*)g->d_ffield;
     // forces at positions x, spread into the boxes (and folded with the
-    // fluid force when there is one)
-    auto forces = [&](const double* x) {
-        hipError_t e = bin_blobs<T>(g, M, x, s);
+    // fluid force when there is one); binned: the counts of q are in place
+    auto forces = [&](const double* x, bool counted) {
+        hipError_t e = bin_blobs<T>(g, M, x, s, counted);
         if (e == hipSuccess) e = scatter_springs<T>(g, sd, P, x, Fext, s, Gblob);
         if (e == hipSuccess) e = spread_boxes<T>(g, s);
         if (e == hipSuccess && ffluid) e = fold_boxes<T>(g, ff, s, ffluid);
@@ -486,9 +487,9 @@ static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t
     auto solve = [&]() { return fluid_solve<T>(g, v, ff, v, s, !ffluid); };
     hipError_t e;
     if (g->scheme == MB_SCHEME_EULER) {
-        e = forces(q);
+        e = forces(q, binned);
         if (e == hipSuccess) e = solve();
-        if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 1, s);
+        if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 1, s, 1.0, bin_next);
         return e;
     }
     // midpoint predictor-corrector: q* in d_mid, the second half of the
@@ -498,10 +499,10 @@ static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t
     e = blob_axpy(3 * M, nullptr, 1.0, q, qs, s);  // q* = q^n
     if (g->d.mode == MB_STEADY_STOKES) {
         // q* += (dt/2) J(q^n) v(q^n);  q += dt J(q*) v(q*)
-        if (e == hipSuccess) e = forces(q);
+        if (e == hipSuccess) e = forces(q, false);
         if (e == hipSuccess) e = solve();
         if (e == hipSuccess) e = interpolate<T>(g, M, v, nullptr, qs, 0, s, 0.5);
-        if (e == hipSuccess) e = forces(qs);
+        if (e == hipSuccess) e = forces(qs, false);
         if (e == hipSuccess) e = solve();
         if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 1, s);
         return e;
@@ -511,7 +512,7 @@ static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t
     if (e == hipSuccess) e = scatter_records<T>(g, M, q, nullptr, s);
     if (e == hipSuccess) e = interpolate<T>(g, M, v, nullptr, qs, 0, s, 0.5);
     // forces at q*; q += (dt/2) J(q*) v^n; solve; q += (dt/2) J(q*) v^{n+1}
-    if (e == hipSuccess) e = forces(qs);
+    if (e == hipSuccess) e = forces(qs, false);
     if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 0, s, 0.5);
     if (e == hipSuccess) e = solve();
     if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst ? u2 : nullptr, q, 1, s, 0.5);
@@ -554,16 +555,24 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
         e = hipMemsetAsync(g->d_force_part, 0, 3 * sizeof(double), s);
         if (e != hipSuccess) return from_hip(e);
     }
+    // first-order steps after the first of the call take their binning from
+    // the interpolation of the step before (the positions it wrote); the
+    // last step leaves the counts at zero
+    const bool carry = g->scheme == MB_SCHEME_EULER && M > 0;
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
         const bool last = n == nsteps - 1;
+        const bool binned = carry && n > 0, bin_next = carry && !last;
         double* u_dst = nullptr;
         if (last) u_dst = u_out ? u_out : (U0_out ? g->d_u : nullptr);
         if (g->fsz == 4)
             e = step_once<float>(g, sd, P, M, q, (float*)v, Fext, Gblob, (const float*)ffluid,
-                                 u_dst, s);
+                                 u_dst, s, binned, bin_next);
         else
             e = step_once<double>(g, sd, P, M, q, (double*)v, Fext, Gblob,
-                                  (const double*)ffluid, u_dst, s);
+                                  (const double*)ffluid, u_dst, s, binned, bin_next);
+        if (!last && e != hipSuccess && bin_next)
+            (void)hipMemsetAsync(g->d_count, 0,
+                                 sizeof(int) * (size_t)g->tiles.n * g->tiles.nbox, s);
         if (last && e == hipSuccess && U0_out)
             e = particle_means(g, P, sp->nb, u_dst, U0_out, s);
         if (last && e == hipSuccess && diag_out)

@@ -148,8 +148,12 @@ int fft_x_blocks(int L, int precision);
 
 // Launchers (templated on the field scalar type, float or double).  Each
 // returns hipSuccess or the launch error.
+// Tile, rank and counting sort of the blobs at q; with counted the counts,
+// tiles and ranks are already in place (the previous step's interpolation
+// binned these positions) and only the scan runs.
 template <typename T>
-hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s);
+hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s,
+                     bool counted = false);
 // Records of the binned blobs with forces F scaled by fscale (h^-3 when
 // fscale <= 0: a force density).
 template <typename T>
@@ -186,9 +190,13 @@ hipError_t fluid_solve(mb_grid* g, const T* v_in, const T* f, T* v_out,
                        hipStream_t s, bool boxed = false);
 // Elements of the box array: 3 components x tiles x (tx+3)(ty+3)(tz+3).
 size_t box_elems(const Tiles& t);
+// Interpolation of v at the binned blobs (u_out, q_update += dt u, both
+// nullable; diag: per-tile partial sums); bin_next (with q_update): also
+// bin the moved blobs into the counts of the next binning.
 template <typename T>
 hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
-                       double* q_update, int diag, hipStream_t s, double uscale = 1.0);
+                       double* q_update, int diag, hipStream_t s, double uscale = 1.0,
+                       bool bin_next = false);
 // gout += wscale sum_a W_a grad_q (J v)_a per blob, on the binned records.
 template <typename T>
 hipError_t interpolate_grad(mb_grid* g, const T* v, const double* W, double wscale,

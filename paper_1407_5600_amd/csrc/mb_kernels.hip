@@ -717,6 +717,14 @@ k_fold(const T* __restrict__ E, int L, Tiles tl, const T* __restrict__ add,
     f[i] = add ? val + add[i] : val;
 }
 
+// Binning of the moved blobs for the next step, done by the interpolation
+// that moves them (count: per-tile counts, zero before; null: none).
+struct BinNext {
+    int* count;
+    int* tile_of;
+    int* rank;
+};
+
 // Interpolation: one block per tile.  The velocity on nodes [lo-1, hi+2]
 // is staged in LDS (rows located through a table of wrapped row offsets),
 // all three components at once for float32 fields and one at a time for
@@ -725,13 +733,17 @@ k_fold(const T* __restrict__ E, int L, Tiles tl, const T* __restrict__ add,
 // once per blob for each thread's first record, per component for the rest
 // (tiles with more records than threads), scaled by uscale.  With part the
 // block also writes its float64 sum of each component and the max |Dv| over
-// its cells.
+// its cells.  With bn.count the block also bins the moved blobs as
+// k_tile_count would bin the new positions: each thread's first record
+// through LDS counts for the 27 tiles around this one (a blob moves less
+// than a tile per step), the rest, and any farther move, with a global
+// atomic each.
 template <typename T, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
 k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
          const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
          double* __restrict__ u_out, double uscale, double* __restrict__ q, double dt,
-         double inv_h, double* __restrict__ part) {
+         double inv_h, double* __restrict__ part, BinNext bn) {
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
     constexpr int EV = EX * EY * EZ;
     constexpr int TV = TX * TY * TZ;
@@ -742,9 +754,12 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     __shared__ T vt[NCS * EV];
     __shared__ int rowoff[EY * EZ];
     __shared__ double red[16];
+    __shared__ int lcount[27];
+    __shared__ int lbase[27];
     const TileBox tb = tile_box(tl, L);
     const int tile = tb.gt;
     const int N = L * L * L;  // 3 L^3 < 2^31 for L <= 512
+    if (bn.count && threadIdx.x < 27) lcount[threadIdx.x] = 0;
     v += (size_t)tb.box * 3 * N;
     for (int r = threadIdx.x; r < EY * EZ; r += BLK) {
         const int ey = r % EY, ez = r / EY;
@@ -864,6 +879,7 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
             }
         }
     }
+    double qn[3] = {0.0, 0.0, 0.0};  // the first record's new position
     if (pos0 >= 0) {
         const int64_t i = i0;
         if (u_out) {
@@ -872,9 +888,66 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
             u_out[3 * i + 2] = u0[2];
         }
         if (q) {
-            q[3 * i] = q0[0] + dt * u0[0];
-            q[3 * i + 1] = q0[1] + dt * u0[1];
-            q[3 * i + 2] = q0[2] + dt * u0[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                qn[c] = q0[c] + dt * u0[c];
+                q[3 * i + c] = qn[c];
+            }
+        }
+    }
+    if (bn.count) {
+        // tile coordinates of this tile
+        const int ot[3] = {tb.lo[0] / tl.tx, tb.lo[1] / tl.ty, tb.lo[2] / tl.tz};
+        const int nt[3] = {tl.ntx, tl.nty, tl.ntz};
+        const int sh[3] = {__ffs(tl.tx) - 1, __ffs(tl.ty) - 1, __ffs(tl.tz) - 1};
+        int slot = -1, rk = 0, tnew = 0;
+        if (pos0 >= 0) {
+            const Geom gn = blob_geom(qn, 0, inv_h, L);
+            tnew = tb.box * tl.n + tile_linear(gn.c, tl);
+            slot = 0;
+#pragma unroll
+            for (int b = 2; b >= 0; --b) {
+                int d = (gn.c[b] >> sh[b]) - ot[b];
+                if (d == nt[b] - 1) d = -1;
+                if (d == 1 - nt[b]) d = 1;
+                if (slot >= 0 && d >= -1 && d <= 1) slot = slot * 3 + d + 1;
+                else slot = -1;
+            }
+            if (slot >= 0) rk = atomicAdd(&lcount[slot], 1);
+            else rk = atomicAdd(&bn.count[tnew], 1);
+        }
+        // records beyond each thread's first: positions re-read (written by
+        // this thread above), one global atomic each
+        for (int k = threadIdx.x + BLK; k < total; k += BLK) {
+            const int64_t i = perm[first + k];
+            const Geom gk = blob_geom(q, i, inv_h, L);
+            const int t = tb.box * tl.n + tile_linear(gk.c, tl);
+            bn.tile_of[i] = t;
+            bn.rank[i] = atomicAdd(&bn.count[t], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x < 27) {
+            const int c = lcount[threadIdx.x];
+            int base = 0;
+            if (c > 0) {
+                const int d[3] = {(int)threadIdx.x % 3 - 1, ((int)threadIdx.x / 3) % 3 - 1,
+                                  (int)threadIdx.x / 9 - 1};
+                int tc[3];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    tc[b] = ot[b] + d[b];
+                    if (tc[b] < 0) tc[b] += nt[b];
+                    if (tc[b] >= nt[b]) tc[b] -= nt[b];
+                }
+                const int t = tb.box * tl.n + (tc[2] * tl.nty + tc[1]) * tl.ntx + tc[0];
+                base = atomicAdd(&bn.count[t], c);
+            }
+            lbase[threadIdx.x] = base;
+        }
+        __syncthreads();
+        if (pos0 >= 0) {
+            bn.tile_of[i0] = tnew;
+            bn.rank[i0] = slot >= 0 ? lbase[slot] + rk : rk;
         }
     }
     if (part) {
@@ -1048,9 +1121,9 @@ static inline unsigned blocks_for(int64_t n) {
 }
 
 template <typename T>
-hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s) {
+hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s, bool counted) {
     const int nt = g->tiles.n * g->tiles.nbox;
-    if (M > 0) {
+    if (M > 0 && !counted) {
         // the previous sorted order, when it is a permutation of these blobs
         const int* order = g->perm_m == M ? g->d_perm : nullptr;
         MB_LAUNCH(g, K_BIN_COUNT, s, k_tile_count, blocks_for(M), BLK, 0, q, order, M,
@@ -1193,15 +1266,18 @@ hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s, const T* add) {
 
 template <typename T>
 hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
-                       double* q_update, int diag, hipStream_t s, double uscale) {
+                       double* q_update, int diag, hipStream_t s, double uscale,
+                       bool bin_next) {
     (void)M;
     double* part = diag ? g->d_tile_part : nullptr;
     const int kid = q_update ? K_INTERP_STEP : K_INTERP;
+    BinNext bn{nullptr, nullptr, nullptr};
+    if (bin_next && q_update) bn = BinNext{g->d_count, g->d_tile, g->d_rank};
     const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
         MB_LAUNCH(g, kid, s, (k_interp<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
                   g->tiles.n * g->tiles.nbox, BLK, 0, (const Rec<T>*)g->d_rec, g->d_perm,
                   g->d_offs, g->L, g->tiles, v, u_out, uscale, q_update, g->d.dt,
-                  1.0 / g->d.h, part);
+                  1.0 / g->d.h, part, bn);
     });
     return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -1235,8 +1311,8 @@ hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,
 }
 
 // Explicit instantiations.
-template hipError_t bin_blobs<float>(mb_grid*, int64_t, const double*, hipStream_t);
-template hipError_t bin_blobs<double>(mb_grid*, int64_t, const double*, hipStream_t);
+template hipError_t bin_blobs<float>(mb_grid*, int64_t, const double*, hipStream_t, bool);
+template hipError_t bin_blobs<double>(mb_grid*, int64_t, const double*, hipStream_t, bool);
 template hipError_t scatter_records<float>(mb_grid*, int64_t, const double*, const double*, hipStream_t, double);
 template hipError_t scatter_records<double>(mb_grid*, int64_t, const double*, const double*, hipStream_t, double);
 template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*);
@@ -1245,8 +1321,8 @@ template hipError_t spread_boxes<float>(mb_grid*, hipStream_t);
 template hipError_t spread_boxes<double>(mb_grid*, hipStream_t);
 template hipError_t fold_boxes<float>(mb_grid*, float*, hipStream_t, const float*);
 template hipError_t fold_boxes<double>(mb_grid*, double*, hipStream_t, const double*);
-template hipError_t interpolate<float>(mb_grid*, int64_t, const float*, double*, double*, int, hipStream_t, double);
-template hipError_t interpolate<double>(mb_grid*, int64_t, const double*, double*, double*, int, hipStream_t, double);
+template hipError_t interpolate<float>(mb_grid*, int64_t, const float*, double*, double*, int, hipStream_t, double, bool);
+template hipError_t interpolate<double>(mb_grid*, int64_t, const double*, double*, double*, int, hipStream_t, double, bool);
 template hipError_t interpolate_grad<float>(mb_grid*, const float*, const double*, double, double*, hipStream_t);
 template hipError_t interpolate_grad<double>(mb_grid*, const double*, const double*, double, double*, hipStream_t);
 

@@ -368,3 +368,56 @@ def test_spread_crowded_tile(torch_cuda, prec, M):
     torch.cuda.synchronize()
     ref = oracle.spread(oracle.params(L), q, F)
     check(f"spread crowded {prec} M={M}", f.double().cpu().numpy(), ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["suspension", "steady", "batch", "tile8", "fast"])
+def test_step_call_binning_carry_is_exact(torch_cuda, prec, case):
+    """Within one call of several first-order steps, each step after the
+    first takes its binning from the interpolation that moved the blobs.
+    Spreading sums in fixed point and the rest works per blob, per cell or
+    per tile, so the result equals that of one call per step bit for bit
+    (suspension, steady Stokes, a batch of boxes, small tiles; "fast": blobs
+    that move more than a tile per step, which take the global-atomic path).
+    The last step leaves the counts at zero: a following call bins afresh."""
+    from paper_1407_5600_amd import Springs
+    torch = torch_cuda
+    say("binning carry", prec, case)
+    nbox, kw = 1, {}
+    if case == "batch":
+        nbox = 3
+        ws = [inputs.random_suspension(40 + b, 32, 40) for b in range(nbox)]
+        w = ws[0]
+        q0 = np.concatenate([x.q for x in ws])
+        Fe = np.concatenate([x.Fext for x in ws])
+    else:
+        w = inputs.random_suspension(31, 48, 150)
+        q0, Fe = w.q, w.Fext
+        if case == "steady":
+            kw = {"mode": "steady", "zero_mean": True}
+
+    M = q0.shape[0]
+    sp = Springs(w.nb, w.pa, w.pb, w.r0, w.k)
+    out = []
+    for calls in ([5], [1, 1, 1, 1, 1], [2, 3]):
+        g = grid(w.L, prec, M, rho=w.rho, eta=w.eta, dt=w.dt, nbox=nbox, **kw)
+        if case == "tile8":
+            g.set_tiles(8, 8, 8)
+        q = dev(torch, q0)
+        v = g.field()
+        if case == "fast":
+            v[0] += 2000.0  # a uniform flow carries the blobs 20 cells per step
+        F = dev(torch, Fe)
+        diag = torch.zeros(7, dtype=torch.float64, device="cuda")
+        U0 = torch.zeros((M // w.nb, 3), dtype=torch.float64, device="cuda")
+        for n in calls:
+            g.step(sp, q, v, F, n, None, U0, diag)
+        torch.cuda.synchronize()
+        out.append([x.cpu().numpy() for x in (q, v, U0, diag)])
+        if calls == [5] and case == "fast":
+            moved = np.abs(out[0][0] - q0).max()
+            say(f"binning carry fast: max move {moved:.2f} cells over 5 steps")
+            assert moved > 5 * 16, "the fast case must move blobs beyond a tile per step"
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            assert np.array_equal(a, b)
