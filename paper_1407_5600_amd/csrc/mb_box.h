@@ -98,6 +98,45 @@ __device__ __forceinline__ T box_sum(const T* __restrict__ Ea, const AxisSrc& sx
 #undef MB_ROW
 }
 
+// The entries of component array Ea holding a node, loaded without
+// arithmetic: e[s][0] (first x source) and e[s][1] (second x source, lane
+// masked) for the (z, y) source pairs s = 0 (z0, y0), 1 (z0, y1), 2 (z1, y0),
+// 3 (z1, y1); pairs absent from the node are not loaded and stay zero.  The
+// y and z counts are uniform over the wave when the lanes share y and z, so
+// the branches do not diverge, and since nothing is added inside them the
+// loads of several nodes stay in flight together; box_entries_sum then adds
+// them in the order of box_sum.
+template <typename T>
+__device__ __forceinline__ void box_entries(const T* __restrict__ Ea, const AxisSrc& sx,
+                                            const AxisSrc& sy, const AxisSrc& sz,
+                                            T e[4][2]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k][0] = e[k][1] = T(0);
+    const int o0 = sz.off[0] + sy.off[0];
+    e[0][0] = Ea[o0 + sx.off[0]];
+    if (sx.n > 1) e[0][1] = Ea[o0 + sx.off[1]];
+    if (sy.n > 1) {
+        const int o1 = sz.off[0] + sy.off[1];
+        e[1][0] = Ea[o1 + sx.off[0]];
+        if (sx.n > 1) e[1][1] = Ea[o1 + sx.off[1]];
+    }
+    if (sz.n > 1) {
+        const int o2 = sz.off[1] + sy.off[0];
+        e[2][0] = Ea[o2 + sx.off[0]];
+        if (sx.n > 1) e[2][1] = Ea[o2 + sx.off[1]];
+        if (sy.n > 1) {
+            const int o3 = sz.off[1] + sy.off[1];
+            e[3][0] = Ea[o3 + sx.off[0]];
+            if (sx.n > 1) e[3][1] = Ea[o3 + sx.off[1]];
+        }
+    }
+}
+template <typename T>
+__device__ __forceinline__ T box_entries_sum(const T e[4][2]) {
+    return ((e[0][0] + e[0][1]) + (e[1][0] + e[1][1])) +
+           ((e[2][0] + e[2][1]) + (e[3][0] + e[3][1]));
+}
+
 // Node (x, y, z) of component a.
 template <typename T>
 __device__ __forceinline__ T box_sum(const T* __restrict__ E, const Tiles& tl,

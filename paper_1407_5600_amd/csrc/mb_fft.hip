@@ -276,55 +276,70 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
     } else {
         f += (size_t)box * 3 * L * L * L;
     }
+    // KG iterations (2 KG nodes) per round: all loads of a round, the box
+    // entries included (box_entries: loads only, in uniform branches), are
+    // issued before its arithmetic
+    constexpr int KG = sizeof(T) == 4 ? 2 : 1;  // registers
+    static_assert(EPT % KG == 0, "rounds of the x pass");
+    // a wave's lanes share y when L is a multiple of the wave
+    constexpr bool UNI = L % WAVE == 0 && NTHR % L == 0;
 #pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        const int e = tid + kk * NTHR;
-        const int line = e / L;
-        const int x = e - line * L;
-        const int xm = x == 0 ? L - 1 : x - 1, xp = x == L - 1 ? 0 : x + 1;
-        // the loads of both rows are issued before any arithmetic
-        T vc[2], vn[2][6], fv[2];
+    for (int k0 = 0; k0 < EPT; k0 += KG) {
+        T vc[KG][2], vn[KG][2][6], fv[KG][2];
+        T eb[KG][2][4][2];
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            const int y = y0 + 2 * line + hh;
-            const int row = cbase + (z * L + y) * L;
-            if (!BOX) fv[hh] = f[row + x];
-            if (!STEADY) {
-                const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-                vc[hh] = v[row + x];
-                vn[hh][0] = v[row + xm];
-                vn[hh][1] = v[row + xp];
-                vn[hh][2] = v[cbase + (z * L + ym) * L + x];
-                vn[hh][3] = v[cbase + (z * L + yp) * L + x];
-                vn[hh][4] = v[cbase + (zm * L + y) * L + x];
-                vn[hh][5] = v[cbase + (zp * L + y) * L + x];
-            }
-        }
-        if constexpr (BOX) {
-            // a wave's lanes share y when L is a multiple of the wave
-            constexpr bool UNI = L % WAVE == 0 && NTHR % L == 0;
-            const AxisSrc bx = box_src_x(tl, x);
+        for (int g = 0; g < KG; ++g) {
+            const int e = tid + (k0 + g) * NTHR;
+            const int line = e / L;
+            const int x = e - line * L;
+            const int xm = x == 0 ? L - 1 : x - 1, xp = x == L - 1 ? 0 : x + 1;
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 const int y = y0 + 2 * line + hh;
-                const int yu = UNI ? __builtin_amdgcn_readfirstlane(y) : y;
-                fv[hh] = box_sum<UNI>(Ec, bx, box_src_y(tl, yu), bz);
+                const int row = cbase + (z * L + y) * L;
+                if (!BOX) fv[g][hh] = f[row + x];
+                if (!STEADY) {
+                    const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+                    vc[g][hh] = v[row + x];
+                    vn[g][hh][0] = v[row + xm];
+                    vn[g][hh][1] = v[row + xp];
+                    vn[g][hh][2] = v[cbase + (z * L + ym) * L + x];
+                    vn[g][hh][3] = v[cbase + (z * L + yp) * L + x];
+                    vn[g][hh][4] = v[cbase + (zm * L + y) * L + x];
+                    vn[g][hh][5] = v[cbase + (zp * L + y) * L + x];
+                }
             }
-        }
-        T val[2];
+            if constexpr (BOX) {
+                const AxisSrc bx = box_src_x(tl, x);
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            sf += (double)fv[hh];
-            if (STEADY) {
-                val[hh] = fv[hh];
-            } else {
-                sv += (double)vc[hh];
-                const T lap = (vn[hh][0] + vn[hh][1]) + (vn[hh][2] + vn[hh][3]) +
-                              (vn[hh][4] + vn[hh][5]) - T(6) * vc[hh];
-                val[hh] = a * vc[hh] + b * lap + fv[hh];
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int y = y0 + 2 * line + hh;
+                    const int yu = UNI ? __builtin_amdgcn_readfirstlane(y) : y;
+                    box_entries(Ec, bx, box_src_y(tl, yu), bz, eb[g][hh]);
+                }
             }
         }
-        buf[line * LS + lpad(x)] = cplx<T>{val[0], val[1]};
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+            const int e = tid + (k0 + g) * NTHR;
+            const int line = e / L;
+            const int x = e - line * L;
+            T val[2];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                if (BOX) fv[g][hh] = box_entries_sum(eb[g][hh]);
+                sf += (double)fv[g][hh];
+                if (STEADY) {
+                    val[hh] = fv[g][hh];
+                } else {
+                    sv += (double)vc[g][hh];
+                    const T lap = (vn[g][hh][0] + vn[g][hh][1]) + (vn[g][hh][2] + vn[g][hh][3]) +
+                                  (vn[g][hh][4] + vn[g][hh][5]) - T(6) * vc[g][hh];
+                    val[hh] = a * vc[g][hh] + b * lap + fv[g][hh];
+                }
+            }
+            buf[line * LS + lpad(x)] = cplx<T>{val[0], val[1]};
+        }
     }
     __syncthreads();
     line_fft<T, L, false, NL, LS, NTHR>(buf, tws, tid);
