@@ -47,7 +47,8 @@ def algorithmic_bytes(L, M, P, prec, steady=False):
     """Bytes each kernel of one step must move at minimum (one read or write
     of every array it consumes or produces), per launch."""
     s = 4 if prec == "mixed" else 8
-    rec = 48 if prec == "mixed" else 80
+    recg = 16 if prec == "mixed" else 32      # geometry record (fractions, cell)
+    rec = recg + 3 * s                        # + force record
     N = L ** 3
     field = 3 * N * s
     spec = 3 * L * L * (L // 2 + 1) * 2 * s
@@ -64,7 +65,7 @@ def algorithmic_bytes(L, M, P, prec, steady=False):
         "fft_z_spectral": 2 * spec,
         "fft_y_inv": 2 * spec,
         "fft_x_inv": spec + field,
-        "interp_step": field + rec * M + 4 * M + 48 * M,
+        "interp_step": field + recg * M + 4 * M + 48 * M,
     }
 
 

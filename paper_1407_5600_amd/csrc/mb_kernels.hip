@@ -8,6 +8,7 @@
 // interpolated tile by tile from an LDS copy of the field, moving the blobs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -17,26 +18,32 @@
 
 namespace mb {
 
-// Sorted-blob record: kernel offsets for the cell-centred (tu) and the
-// component's own, half-cell shifted (ts) node sets, the force scaled by
-// h^-3, and the packed cell: bits 0-8 x, 9-17 y, 18-26 z, 27-29 the
-// "rounds up" bit per axis (node i0 = c + bit for the cell-centred set).
+// Sorted-blob records, in two arrays.  The geometry record holds the
+// position's fraction of its cell per axis, s = x/h - floor(x/h) in [0, 1),
+// and the packed cell: bits 0-8 x, 9-17 y, 18-26 z, 27-29 the "rounds up"
+// bit per axis (s >= 1/2).  The kernel offset of the cell-centred node set
+// is t = s - bit (nearest node c + bit), that of the component's own,
+// half-cell shifted set t = s - 1/2 (nearest node c); rec_t forms them.
+// The force record (F h^-3 per component, [pos][3]) is a separate array:
+// the interpolation reads only the geometry.
 template <typename T>
-struct __align__(16) Rec {
-    T tu[3];
-    T ts[3];
-    T F[3];
+struct __align__(16) RecG {
+    T s[3];
     uint32_t cell;
-    uint32_t pad;
 };
+
+// Kernel offset of a record for velocity component a along axis b.
+template <typename T>
+__device__ __forceinline__ T rec_t(const RecG<T>& r, int a, int b) {
+    return a == b ? r.s[b] - T(0.5) : r.s[b] - T((r.cell >> (27 + b)) & 1u);
+}
 
 constexpr int BLK = 256;
 
 struct Geom {
     int c[3];
     int up[3];
-    double tu[3];
-    double ts[3];
+    double s[3];
 };
 
 // Cell, rounding bits and kernel offsets of a position (float64).  For the
@@ -62,8 +69,7 @@ __device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
         if (c >= Ld) c -= Ld;
         g.c[b] = (int)c;
         g.up[b] = s >= 0.5 ? 1 : 0;
-        g.tu[b] = s - (double)g.up[b];
-        g.ts[b] = s - 0.5;
+        g.s[b] = s;
     }
     return g;
 }
@@ -204,22 +210,22 @@ k_scan_apply(int* __restrict__ count, int64_t n, const int* __restrict__ bsum,
     if (base + SCAN_TILE >= n && threadIdx.x == 0) offs[n] = off + total;
 }
 
-// Writes the record of blob i at sorted position pos.
+// Writes the records of blob i at sorted position pos (recf may be null:
+// no forces).
 template <typename T>
-__device__ __forceinline__ void write_record(Rec<T>* __restrict__ rec,
+__device__ __forceinline__ void write_record(RecG<T>* __restrict__ rec, T* __restrict__ recf,
                                              int* __restrict__ perm, int64_t pos,
                                              int64_t i, const Geom& g,
                                              const double F[3], double inv_vol) {
-    Rec<T> r;
+    RecG<T> r;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        r.tu[b] = (T)g.tu[b];
-        r.ts[b] = (T)g.ts[b];
-        r.F[b] = (T)(F[b] * inv_vol);
-    }
+    for (int b = 0; b < 3; ++b) r.s[b] = (T)g.s[b];
     r.cell = cell_pack(g);
-    r.pad = 0;
     rec[pos] = r;
+    if (recf) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) recf[3 * pos + b] = (T)(F[b] * inv_vol);
+    }
     perm[pos] = (int)i;
 }
 
@@ -229,8 +235,8 @@ __global__ void __launch_bounds__(BLK)
 k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
               int64_t M, double inv_h, int L, double inv_vol,
               const int* __restrict__ offs, const int* __restrict__ tile_of,
-              const int* __restrict__ rank, Rec<T>* __restrict__ rec,
-              int* __restrict__ perm) {
+              const int* __restrict__ rank, RecG<T>* __restrict__ rec,
+              T* __restrict__ recf, int* __restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (i >= M) return;
     const Geom g = blob_geom(q, i, inv_h, L);
@@ -241,7 +247,7 @@ k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
         f[2] = F[3 * i + 2];
     }
     const int64_t pos = (int64_t)offs[tile_of[i]] + rank[i];
-    write_record<T>(rec, perm, pos, i, g, f, inv_vol);
+    write_record<T>(rec, F ? recf : nullptr, perm, pos, i, g, f, inv_vol);
 }
 
 // Spring forces of the sp.ppb particles of a block (float64), in two
@@ -354,7 +360,7 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
                   int64_t P, double inv_h, int L,
                   double inv_vol, const int* __restrict__ offs,
                   const int* __restrict__ tile_of, const int* __restrict__ rank,
-                  Rec<T>* __restrict__ rec, int* __restrict__ perm,
+                  RecG<T>* __restrict__ rec, T* __restrict__ recf, int* __restrict__ perm,
                   double* __restrict__ fpart) {
     extern __shared__ double smem[];
     __shared__ double red[16 * 3];
@@ -375,7 +381,7 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
     springs_forces(sp, B, fe, F, &i);
     if (i >= 0) {
         const Geom g = blob_geom(B.qs, threadIdx.x, inv_h, L);
-        write_record<T>(rec, perm, (int64_t)off + rk, i, g, F, inv_vol);
+        write_record<T>(rec, recf, perm, (int64_t)off + rk, i, g, F, inv_vol);
     }
     double tot[3] = {F[0], F[1], F[2]};
     block_reduce3(tot, red);
@@ -587,8 +593,8 @@ __device__ __forceinline__ int fixed_exponent(double fmax, int n, double lim_sum
 //    when n <= 2^20, else float64 LDS atomics.
 template <typename T, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
-k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
-         Tiles tl, T* __restrict__ E) {
+k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
+         const int* __restrict__ offs, int L, Tiles tl, T* __restrict__ E) {
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
     constexpr int EV = EX * EY * EZ;
     constexpr bool F32 = std::is_same<T, float>::value;
@@ -601,16 +607,20 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
     for (int i = threadIdx.x; i < EV; i += BLK) acc[i] = 0ull;
     const int first = offs[tb.gt];
     const int total = offs[tb.gt + 1] - first;
-    const Rec<T>* trec = rec + first;
+    const RecG<T>* trec = rec + first;
+    const T* tF = recf + 3 * (size_t)first;
     // this thread's first record is kept in registers for all components
-    Rec<T> r0{};
-    if ((int)threadIdx.x < total) r0 = trec[threadIdx.x];
+    RecG<T> r0{};
+    T F0[3] = {T(0), T(0), T(0)};
+    if ((int)threadIdx.x < total) {
+        r0 = trec[threadIdx.x];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) F0[b] = tF[3 * threadIdx.x + b];
+    }
     double fm = 0.0;
     for (int k = threadIdx.x; k < total; k += BLK) {
-        Rec<T> r = r0;
-        if (k >= BLK) r = trec[k];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) fm = fmax(fm, fabs((double)r.F[b]));
+        for (int b = 0; b < 3; ++b) fm = fmax(fm, fabs((double)(k < BLK ? F0[b] : tF[3 * k + b])));
     }
     const double fmx = block_reduce<true>(fm, red);
     // mode 0: the fast fixed-point form (u32 for float, u64 for double)
@@ -625,19 +635,23 @@ k_spread(const Rec<T>* __restrict__ rec, const int* __restrict__ offs, int L,
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         for (int k = threadIdx.x; k < total; k += BLK) {
-            Rec<T> r = r0;
-            if (k >= BLK) r = trec[k];
+            RecG<T> r = r0;
+            T Fr = F0[a];
+            if (k >= BLK) {
+                r = trec[k];
+                Fr = tF[3 * k + a];
+            }
             T w[3][3];
             int e0[3];  // box index of node i0 - 1
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                kernel_weights<T>(a == b ? r.ts[b] : r.tu[b], w[b]);
+                kernel_weights<T>(rec_t(r, a, b), w[b]);
                 const int c = (int)((r.cell >> (9 * b)) & 511u) - tb.lo[b];  // [0, T)
                 const int up = (int)((r.cell >> (27 + b)) & 1u);
                 e0[b] = a == b ? c : c + up;
             }
             const int base = (e0[2] * EY + e0[1]) * EX + e0[0];
-            const T Fa = ldexp(r.F[a], e);
+            const T Fa = ldexp(Fr, e);
             // the 27 node offsets from base are compile-time constants
 #define MB_SPREAD_27(ADD)                                                    \
     _Pragma("unroll") for (int oz = 0; oz < 3; ++oz) {                       \
@@ -740,7 +754,7 @@ struct BinNext {
 // atomic each.
 template <typename T, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
-k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
+k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
          const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
          double* __restrict__ u_out, double uscale, double* __restrict__ q, double dt,
          double inv_h, double* __restrict__ part, BinNext bn) {
@@ -773,7 +787,7 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     const int gx = wrapL(tb.lo[0] - 1 + sx, L);
     const int pos0 = (int)threadIdx.x < total ? first + (int)threadIdx.x : -1;
     // the thread's first record and its blob, loaded once
-    Rec<T> r0{};
+    RecG<T> r0{};
     int64_t i0 = -1;
     double q0[3] = {0.0, 0.0, 0.0};  // its position, fetched before the staging
     if (pos0 >= 0) {
@@ -818,7 +832,7 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
         __syncthreads();
         for (int k = threadIdx.x; k < total; k += BLK) {
             const int pos = first + k;
-            Rec<T> r = r0;
+            RecG<T> r = r0;
             if (k >= BLK) r = rec[pos];
             double ua[NCS];
 #pragma unroll
@@ -828,7 +842,7 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
                 int e0[3];  // extended-tile index of node i0 - 1
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    kernel_weights<T>(a == b ? r.ts[b] : r.tu[b], w[b]);
+                    kernel_weights<T>(rec_t(r, a, b), w[b]);
                     const int cc = (int)((r.cell >> (9 * b)) & 511u) - tb.lo[b];  // [0, T)
                     const int up = (int)((r.cell >> (27 + b)) & 1u);
                     e0[b] = a == b ? cc : cc + up;
@@ -987,7 +1001,7 @@ k_interp(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
 // atomics.
 template <typename T, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(BLK)
-k_interp_grad(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
+k_interp_grad(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
               const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
               const double* __restrict__ W, double wscale, double inv_h,
               double* __restrict__ gout) {
@@ -1014,7 +1028,7 @@ k_interp_grad(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
     for (int k0 = 0; k0 < total; k0 += BLK) {
         const int k = k0 + threadIdx.x;
         const bool has = k < total;
-        Rec<T> r{};
+        RecG<T> r{};
         int64_t i = 0;
         double wgt[3] = {0.0, 0.0, 0.0};
         if (has) {
@@ -1047,7 +1061,7 @@ k_interp_grad(const Rec<T>* __restrict__ rec, const int* __restrict__ perm,
             int e0[3];
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                kernel_weights_deriv<T>(a == b ? r.ts[b] : r.tu[b], w[b], dw[b]);
+                kernel_weights_deriv<T>(rec_t(r, a, b), w[b], dw[b]);
                 const int cc = (int)((r.cell >> (9 * b)) & 511u) - tb.lo[b];
                 const int up = (int)((r.cell >> (27 + b)) & 1u);
                 e0[b] = a == b ? cc : cc + up;
@@ -1120,6 +1134,17 @@ static inline unsigned blocks_for(int64_t n) {
     return (unsigned)((n + BLK - 1) / BLK);
 }
 
+// The two record arrays in the grid's record scratch: geometry, then forces.
+template <typename T>
+static RecG<T>* rec_geo(mb_grid* g) {
+    return (RecG<T>*)g->d_rec;
+}
+template <typename T>
+static T* rec_force(mb_grid* g) {
+    const size_t cap = (size_t)std::max<int64_t>(g->d.max_blobs, 1);
+    return (T*)((char*)g->d_rec + cap * sizeof(RecG<T>));
+}
+
 template <typename T>
 hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s, bool counted) {
     const int nt = g->tiles.n * g->tiles.nbox;
@@ -1146,7 +1171,7 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
     const double sc = fscale > 0.0 ? fscale : 1.0 / (h * h * h);
     MB_LAUNCH(g, K_BIN_SCATTER, s, k_bin_scatter<T>, blocks_for(M), BLK, 0, q, F,
               M, 1.0 / h, g->L, sc, g->d_offs, g->d_tile, g->d_rank,
-              (Rec<T>*)g->d_rec, g->d_perm);
+              rec_geo<T>(g), rec_force<T>(g), g->d_perm);
     g->perm_m = M;
     return hipGetLastError();
 }
@@ -1160,7 +1185,8 @@ hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
     const double h = g->d.h;
     MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, springs_blocks(sp, P), BLK,
               springs_lds(sp), sp, q, Fext, Gblob, P, 1.0 / h, g->L, 1.0 / (h * h * h), g->d_offs,
-              g->d_tile, g->d_rank, (Rec<T>*)g->d_rec, g->d_perm, g->d_force_part);
+              g->d_tile, g->d_rank, rec_geo<T>(g), rec_force<T>(g), g->d_perm,
+              g->d_force_part);
     g->perm_m = M;
     return hipGetLastError();
 }
@@ -1251,8 +1277,8 @@ template <typename T>
 hipError_t spread_boxes(mb_grid* g, hipStream_t s) {
     const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
         MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
-                  g->tiles.n * g->tiles.nbox, BLK, 0, (const Rec<T>*)g->d_rec, g->d_offs,
-                  g->L, g->tiles, (T*)g->d_box);
+                  g->tiles.n * g->tiles.nbox, BLK, 0, rec_geo<T>(g), rec_force<T>(g),
+                  g->d_offs, g->L, g->tiles, (T*)g->d_box);
     });
     return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -1275,7 +1301,7 @@ hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
     if (bin_next && q_update) bn = BinNext{g->d_count, g->d_tile, g->d_rank};
     const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
         MB_LAUNCH(g, kid, s, (k_interp<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
-                  g->tiles.n * g->tiles.nbox, BLK, 0, (const Rec<T>*)g->d_rec, g->d_perm,
+                  g->tiles.n * g->tiles.nbox, BLK, 0, rec_geo<T>(g), g->d_perm,
                   g->d_offs, g->L, g->tiles, v, u_out, uscale, q_update, g->d.dt,
                   1.0 / g->d.h, part, bn);
     });
@@ -1287,7 +1313,7 @@ hipError_t interpolate_grad(mb_grid* g, const T* v, const double* W, double wsca
                             double* gout, hipStream_t s) {
     const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
         MB_LAUNCH(g, K_INTERP_GRAD, s, (k_interp_grad<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
-                  g->tiles.n * g->tiles.nbox, BLK, 0, (const Rec<T>*)g->d_rec, g->d_perm,
+                  g->tiles.n * g->tiles.nbox, BLK, 0, rec_geo<T>(g), g->d_perm,
                   g->d_offs, g->L, g->tiles, v, W, wscale, 1.0 / g->d.h, gout);
     });
     return ok ? hipGetLastError() : hipErrorInvalidValue;
@@ -1331,7 +1357,8 @@ size_t box_elems(const Tiles& t) {
 }
 
 size_t record_size(int precision) {
-    return precision == MB_MIXED ? sizeof(Rec<float>) : sizeof(Rec<double>);
+    return precision == MB_MIXED ? sizeof(RecG<float>) + 3 * sizeof(float)
+                                 : sizeof(RecG<double>) + 3 * sizeof(double);
 }
 
 }  // namespace mb
