@@ -915,29 +915,36 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
         const int nt[3] = {tl.ntx, tl.nty, tl.ntz};
         const int sh[3] = {__ffs(tl.tx) - 1, __ffs(tl.ty) - 1, __ffs(tl.tz) - 1};
         int slot = -1, rk = 0, tnew = 0;
+        auto slot_of = [&](const int c[3]) {
+            int sl = 0;
+#pragma unroll
+            for (int b = 2; b >= 0; --b) {
+                int d = (c[b] >> sh[b]) - ot[b];
+                if (d == nt[b] - 1) d = -1;
+                if (d == 1 - nt[b]) d = 1;
+                if (sl >= 0 && d >= -1 && d <= 1) sl = sl * 3 + d + 1;
+                else sl = -1;
+            }
+            return sl;
+        };
         if (pos0 >= 0) {
             const Geom gn = blob_geom(qn, 0, inv_h, L);
             tnew = tb.box * tl.n + tile_linear(gn.c, tl);
-            slot = 0;
-#pragma unroll
-            for (int b = 2; b >= 0; --b) {
-                int d = (gn.c[b] >> sh[b]) - ot[b];
-                if (d == nt[b] - 1) d = -1;
-                if (d == 1 - nt[b]) d = 1;
-                if (slot >= 0 && d >= -1 && d <= 1) slot = slot * 3 + d + 1;
-                else slot = -1;
-            }
+            slot = slot_of(gn.c);
             if (slot >= 0) rk = atomicAdd(&lcount[slot], 1);
             else rk = atomicAdd(&bn.count[tnew], 1);
         }
-        // records beyond each thread's first: positions re-read (written by
-        // this thread above), one global atomic each
+        // records beyond each thread's first (positions re-read: written by
+        // this thread above): counted through the same LDS slots, their
+        // rank within the slot stored and completed below (a global atomic
+        // each only for a move beyond the neighbour tiles)
         for (int k = threadIdx.x + BLK; k < total; k += BLK) {
             const int64_t i = perm[first + k];
             const Geom gk = blob_geom(q, i, inv_h, L);
             const int t = tb.box * tl.n + tile_linear(gk.c, tl);
+            const int sl = slot_of(gk.c);
             bn.tile_of[i] = t;
-            bn.rank[i] = atomicAdd(&bn.count[t], 1);
+            bn.rank[i] = sl >= 0 ? atomicAdd(&lcount[sl], 1) : atomicAdd(&bn.count[t], 1);
         }
         __syncthreads();
         if (threadIdx.x < 27) {
@@ -962,6 +969,25 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
         if (pos0 >= 0) {
             bn.tile_of[i0] = tnew;
             bn.rank[i0] = slot >= 0 ? lbase[slot] + rk : rk;
+        }
+        for (int k = threadIdx.x + BLK; k < total; k += BLK) {
+            const int64_t i = perm[first + k];
+            int tc[3];  // the tile written above, back to its slot
+            int t = bn.tile_of[i] - tb.box * tl.n;
+            tc[0] = t % tl.ntx;
+            t /= tl.ntx;
+            tc[1] = t % tl.nty;
+            tc[2] = t / tl.nty;
+            int sl = 0;
+#pragma unroll
+            for (int b = 2; b >= 0; --b) {
+                int d = tc[b] - ot[b];
+                if (d == nt[b] - 1) d = -1;
+                if (d == 1 - nt[b]) d = 1;
+                if (sl >= 0 && d >= -1 && d <= 1) sl = sl * 3 + d + 1;
+                else sl = -1;
+            }
+            if (sl >= 0) bn.rank[i] += lbase[sl];
         }
     }
     if (part) {

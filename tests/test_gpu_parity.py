@@ -371,15 +371,18 @@ def test_spread_crowded_tile(torch_cuda, prec, M):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("case", ["suspension", "steady", "batch", "tile8", "fast"])
+@pytest.mark.parametrize("case", ["suspension", "steady", "batch", "tile8", "fast", "crowded",
+                                  "crowded_fast"])
 def test_step_call_binning_carry_is_exact(torch_cuda, prec, case):
     """Within one call of several first-order steps, each step after the
     first takes its binning from the interpolation that moved the blobs.
     Spreading sums in fixed point and the rest works per blob, per cell or
     per tile, so the result equals that of one call per step bit for bit
     (suspension, steady Stokes, a batch of boxes, small tiles; "fast": blobs
-    that move more than a tile per step, which take the global-atomic path).
-    The last step leaves the counts at zero: a following call bins afresh."""
+    that move more than a tile per step, which take the global-atomic path;
+    "crowded": several hundred blobs per tile, more than the block's
+    threads, whose extra records are counted in a second pass).  The last
+    step leaves the counts at zero: a following call bins afresh."""
     from paper_1407_5600_amd import Springs
     torch = torch_cuda
     say("binning carry", prec, case)
@@ -390,6 +393,17 @@ def test_step_call_binning_carry_is_exact(torch_cuda, prec, case):
         w = ws[0]
         q0 = np.concatenate([x.q for x in ws])
         Fe = np.concatenate([x.Fext for x in ws])
+    elif case.startswith("crowded"):
+        # 400 overlapping particles in [4, 12)^3 of a 64^3 box: ~1,300 blobs
+        # in each of the 4 tiles (16x8x8) they cover; with the flow (1.25
+        # tiles per step along x) some move beyond the neighbour tiles
+        w = inputs.random_suspension(33, 64, 1)
+        rng = np.random.default_rng(34)
+        P = 400
+        tmpl = w.q - w.q.mean(axis=0)
+        cent = rng.uniform(4.0, 12.0, size=(P, 1, 3))
+        q0 = (cent + tmpl[None, :, :]).reshape(-1, 3)
+        Fe = rng.standard_normal((P, 3))
     else:
         w = inputs.random_suspension(31, 48, 150)
         q0, Fe = w.q, w.Fext
@@ -405,7 +419,7 @@ def test_step_call_binning_carry_is_exact(torch_cuda, prec, case):
             g.set_tiles(8, 8, 8)
         q = dev(torch, q0)
         v = g.field()
-        if case == "fast":
+        if case.endswith("fast"):
             v[0] += 2000.0  # a uniform flow carries the blobs 20 cells per step
         F = dev(torch, Fe)
         diag = torch.zeros(7, dtype=torch.float64, device="cuda")
@@ -414,7 +428,7 @@ def test_step_call_binning_carry_is_exact(torch_cuda, prec, case):
             g.step(sp, q, v, F, n, None, U0, diag)
         torch.cuda.synchronize()
         out.append([x.cpu().numpy() for x in (q, v, U0, diag)])
-        if calls == [5] and case == "fast":
+        if calls == [5] and case.endswith("fast"):
             moved = np.abs(out[0][0] - q0).max()
             say(f"binning carry fast: max move {moved:.2f} cells over 5 steps")
             assert moved > 5 * 16, "the fast case must move blobs beyond a tile per step"
