@@ -93,6 +93,29 @@ Tiles make_tiles(int L, int nbox, int tx, int ty, int tz) {
     return t;
 }
 
+// Box tiles of the spreading for binning tiles t: each extent below 16 is
+// doubled once (z, then y, then x) when the doubled extent divides L and the
+// box of (sx+3)(sy+3)(sz+3) nodes stays within 7,400 (58 KB of 64-bit LDS
+// accumulators, two blocks per CU); the binning tiles are kept when no
+// spreading kernel exists for the result.  Larger box tiles carry less halo
+// per node.
+Tiles make_box_tiles(int L, const Tiles& t) {
+    int sx = t.tx, sy = t.ty, sz = t.tz;
+    int* ext[3] = {&sz, &sy, &sx};
+    for (int* e : ext) {
+        const int old = *e;
+        if (old >= 16 || L % (2 * old) != 0) continue;
+        *e = 2 * old;
+        if ((sx + 3) * (sy + 3) * (sz + 3) > 7400) *e = old;
+    }
+    if (!box_shape_supported(sx, sy, sz, t.tx, t.ty, t.tz)) {
+        sx = t.tx;
+        sy = t.ty;
+        sz = t.tz;
+    }
+    return make_tiles(L, t.nbox, sx, sy, sz);
+}
+
 // (Re)allocates the scratch indexed by tile for g->tiles: counts (zeroed),
 // offsets, scan block sums, diagnostics partials (zeroed) and the spread
 // boxes.  The caller has synchronised any work using the old buffers.
@@ -110,7 +133,7 @@ hipError_t alloc_tile_buffers(mb_grid* g) {
     if (e == hipSuccess) e = hipMalloc((void**)&g->d_bsum, (size_t)g->nscan * sizeof(int));
     if (e == hipSuccess)
         e = hipMalloc((void**)&g->d_tile_part, (size_t)ntiles * 4 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&g->d_box, box_elems(g->tiles) * g->fsz);
+    if (e == hipSuccess) e = hipMalloc(&g->d_box, box_elems(g->btiles) * g->fsz);
     if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)ntiles * sizeof(int));
     if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)ntiles * 4 * sizeof(double));
     return e;
@@ -246,6 +269,7 @@ mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox, mb_grid**
     // and mb_grid_autotune choose others)
     const Tiles t = make_tiles(L, nbox, (L % 16 == 0) ? 16 : 8, 8, 8);
     g->tiles = t;
+    g->btiles = make_box_tiles(L, t);
     g->rec_size = record_size(d.precision);
     // springs blocks hold at least one particle of at least one blob
     g->force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
@@ -822,6 +846,7 @@ static mb_status set_tiles(mb_grid* g, int tx, int ty, int tz) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return from_hip(e);
     g->tiles = make_tiles(g->L, g->tiles.nbox, tx, ty, tz);
+    g->btiles = make_box_tiles(g->L, g->tiles);
     e = alloc_tile_buffers(g);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : from_hip(e);
     return MB_OK;

@@ -664,7 +664,7 @@ hipError_t solve_sized(mb_grid* g, const T* v_in, const T* f, bool boxed, T* v_o
     const int nbox = g->tiles.nbox;
 #define MB_XF(BX, ST)                                                                     \
     MB_LAUNCH(g, K_FFT_X_FWD, s, (k_x_fwd<T, L, BX, ST>), G::NBX * nbox, G::TX, 0, v_in, fin, \
-              g->tiles, tw, a, b, A, g->d_psum)
+              g->btiles, tw, a, b, A, g->d_psum)
     if (boxed) {
         if (steady) MB_XF(true, true);
         else MB_XF(true, false);

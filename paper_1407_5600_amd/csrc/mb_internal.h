@@ -65,6 +65,9 @@ struct Tiles {
 #define MB_TILE_SHAPES(X) X(16, 8, 8) X(8, 8, 8) X(32, 8, 8) X(16, 16, 8) X(16, 8, 16) X(8, 16, 16)
 
 bool tile_shape_supported(int tx, int ty, int tz);
+// A spreading kernel exists for box tiles of sx x sy x sz cells made of
+// binning tiles of tx x ty x tz.
+bool box_shape_supported(int sx, int sy, int sz, int tx, int ty, int tz);
 
 struct TimerPair {
     hipEvent_t a, b;
@@ -110,7 +113,8 @@ struct mb_grid {
     int64_t perm_m;     // d_perm is a permutation of [0, perm_m) (-1: none)
     void* d_rec;        // [max_blobs] records
     size_t rec_size;
-    mb::Tiles tiles;
+    mb::Tiles tiles;       // binning, spreading and interpolation tiles
+    mb::Tiles btiles;      // spread box tiles: whole numbers of tiles per axis
     void* d_box;           // [3][tiles][box nodes] spread boxes of the step
     double* d_u;           // [max_blobs][3] blob velocities of the last step
     double* d_adj;         // reverse-step scratch (allocated on first use)

@@ -570,14 +570,17 @@ __device__ __forceinline__ int fixed_exponent(double fmax, int n, double lim_sum
     return e_sum < e_one ? e_sum : e_one;
 }
 
-// Spreading: one block per tile, one velocity component at a time.  The
-// tile's own records (those of its cells) add all 27 of their contributions
-// to an LDS box of the nodes they can reach, [lo-1, lo+T+1] per axis: the
-// same box the interpolation stages, so no record is read by more than one
-// block and no contribution is masked.  The box is written to the tile's
-// slot of the box array E[a][tile][box node]; a node of the field is the sum
-// of the entries of the (at most 8) boxes holding it (box_sum), formed by
-// the fold kernel or by the first FFT pass as it reads the force.
+// Spreading: one block per box tile (FX x FY x FZ binning tiles, btl), one
+// velocity component at a time.  The box tile's own records (those of its
+// cells) add all 27 of their contributions to an LDS box of the nodes they
+// can reach, [lo-1, lo+T+1] per axis, so no record is read by more than one
+// block and no contribution is masked.  The box is written to the box
+// tile's slot of the box array E[a][box tile][box node]; a node of the
+// field is the sum of the entries of the (at most 8) boxes holding it
+// (box_sum), formed by the fold kernel or by the first FFT pass as it reads
+// the force.  Box tiles larger than the binning tiles (16^3 against 16x8x8)
+// carry less halo: 1.67 against 2.25 box entries per node, each written
+// here and read by the x pass.
 //
 // Accumulation is in fixed point with integer LDS atomics, which are much
 // faster on gfx950 than the floating ones (float32 ones by more than an
@@ -591,10 +594,21 @@ __device__ __forceinline__ int fixed_exponent(double fmax, int n, double lim_sum
 //  - float64: 64-bit sums of float64 contributions rounded to int64 (a
 //    quantum of at most 2^-50 fmax for n < 27000, coarsening slowly above)
 //    when n <= 2^20, else float64 LDS atomics.
-template <typename T, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(BLK)
+// Threads of a spreading block covering f binning tiles: up to 1024 for
+// float32 fields, 512 for float64 ones (whose ~80 registers per thread
+// would otherwise leave room for one block per CU, not two).
+template <typename T>
+constexpr int spread_threads(int f) {
+    const int cap = sizeof(T) == 4 ? 1024 : 512;
+    return f * BLK < cap ? f * BLK : cap;
+}
+
+template <typename T, int TX, int TY, int TZ, int FX, int FY, int FZ>
+__global__ void __launch_bounds__(spread_threads<T>(FX * FY * FZ))
 k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
-         const int* __restrict__ offs, int L, Tiles tl, T* __restrict__ E) {
+         const int* __restrict__ offs, int L, Tiles btl, Tiles tl, T* __restrict__ E) {
+    constexpr int NT = spread_threads<T>(FX * FY * FZ);
+    constexpr int NR = FX * FY * FZ;  // binning tiles of this box tile
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
     constexpr int EV = EX * EY * EZ;
     constexpr bool F32 = std::is_same<T, float>::value;
@@ -602,25 +616,47 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
     __shared__ double red[16];
     unsigned int* acc32 = reinterpret_cast<unsigned int*>(acc);
     double* accd = reinterpret_cast<double*>(acc);
-    const TileBox tb = tile_box(tl, L);
+    const TileBox tb = tile_box(btl, L);
     const int tile = tb.tile;
-    for (int i = threadIdx.x; i < EV; i += BLK) acc[i] = 0ull;
-    const int first = offs[tb.gt];
-    const int total = offs[tb.gt + 1] - first;
-    const RecG<T>* trec = rec + first;
-    const T* tF = recf + 3 * (size_t)first;
+    for (int i = threadIdx.x; i < EV; i += NT) acc[i] = 0ull;
+    // the record ranges of the binning tiles making up this box tile,
+    // concatenated: record k < total lies in range r with
+    // start[r] <= k < start[r + 1]
+    int rfirst[NR], start[NR + 1];
+    {
+        const int bx0 = tb.lo[0] / tl.tx, by0 = tb.lo[1] / tl.ty, bz0 = tb.lo[2] / tl.tz;
+        start[0] = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int dx = r % FX, dy = (r / FX) % FY, dz = r / (FX * FY);
+            const int g = tb.box * tl.n + ((bz0 + dz) * tl.nty + by0 + dy) * tl.ntx + bx0 + dx;
+            rfirst[r] = offs[g];
+            start[r + 1] = start[r] + (offs[g + 1] - rfirst[r]);
+        }
+    }
+    const int total = start[NR];
+    auto rpos = [&](int k) {  // sorted position of concatenated record k
+        int p = rfirst[0] + k;
+#pragma unroll
+        for (int r = 1; r < NR; ++r)
+            if (k >= start[r]) p = rfirst[r] + (k - start[r]);
+        return p;
+    };
     // this thread's first record is kept in registers for all components
     RecG<T> r0{};
     T F0[3] = {T(0), T(0), T(0)};
     if ((int)threadIdx.x < total) {
-        r0 = trec[threadIdx.x];
+        const int p = rpos(threadIdx.x);
+        r0 = rec[p];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) F0[b] = tF[3 * threadIdx.x + b];
+        for (int b = 0; b < 3; ++b) F0[b] = recf[3 * (size_t)p + b];
     }
     double fm = 0.0;
-    for (int k = threadIdx.x; k < total; k += BLK) {
+    for (int k = threadIdx.x; k < total; k += NT) {
+        const size_t p = k < NT ? 0 : (size_t)rpos(k);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) fm = fmax(fm, fabs((double)(k < BLK ? F0[b] : tF[3 * k + b])));
+        for (int b = 0; b < 3; ++b)
+            fm = fmax(fm, fabs((double)(k < NT ? F0[b] : recf[3 * p + b])));
     }
     const double fmx = block_reduce<true>(fm, red);
     // mode 0: the fast fixed-point form (u32 for float, u64 for double)
@@ -634,12 +670,13 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        for (int k = threadIdx.x; k < total; k += BLK) {
+        for (int k = threadIdx.x; k < total; k += NT) {
             RecG<T> r = r0;
             T Fr = F0[a];
-            if (k >= BLK) {
-                r = trec[k];
-                Fr = tF[3 * k + a];
+            if (k >= NT) {
+                const size_t p = (size_t)rpos(k);
+                r = rec[p];
+                Fr = recf[3 * p + a];
             }
             T w[3][3];
             int e0[3];  // box index of node i0 - 1
@@ -692,8 +729,8 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
         }
         __syncthreads();
         // write the box and clear it for the next component
-        T* Ea = E + ((size_t)(tb.box * 3 + a) * tl.n + tile) * EV;
-        for (int i = threadIdx.x; i < EV; i += BLK) {
+        T* Ea = E + ((size_t)(tb.box * 3 + a) * btl.n + tile) * EV;
+        for (int i = threadIdx.x; i < EV; i += NT) {
             T val;
             if (F32 && mode == 0) {
                 val = ldexpf((float)(int)acc32[i], -e);
@@ -1299,20 +1336,44 @@ bool tile_shape_supported(int tx, int ty, int tz) {
     return false;
 }
 
+// Box tiles with instantiated spreading kernels: (box tile extents, binning
+// tiles per box tile along x, y, z).  box_tiles picks them.
+#define MB_BOX_SHAPES(X)                                                     \
+    X(16, 16, 16, 1, 2, 2) X(16, 16, 16, 2, 2, 2) X(16, 16, 16, 1, 1, 2)     \
+    X(16, 16, 16, 1, 2, 1) X(16, 16, 16, 2, 1, 1) X(32, 8, 16, 1, 1, 2)      \
+    X(8, 8, 8, 1, 1, 1) X(16, 8, 8, 1, 1, 1) X(32, 8, 8, 1, 1, 1)            \
+    X(16, 16, 8, 1, 1, 1) X(16, 8, 16, 1, 1, 1) X(8, 16, 16, 1, 1, 1)
+
 template <typename T>
 hipError_t spread_boxes(mb_grid* g, hipStream_t s) {
-    const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
-        MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
-                  g->tiles.n * g->tiles.nbox, BLK, 0, rec_geo<T>(g), rec_force<T>(g),
-                  g->d_offs, g->L, g->tiles, (T*)g->d_box);
-    });
+    const Tiles& t = g->tiles;
+    const Tiles& b = g->btiles;
+    bool ok = false;
+#define MB_BOX(SX, SY, SZ, FX, FY, FZ)                                                   \
+    if (!ok && b.tx == SX && b.ty == SY && b.tz == SZ && SX == FX * t.tx &&              \
+        SY == FY * t.ty && SZ == FZ * t.tz) {                                            \
+        MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, SX, SY, SZ, FX, FY, FZ>), b.n * b.nbox,   \
+                  spread_threads<T>(FX * FY * FZ), 0, rec_geo<T>(g), rec_force<T>(g),    \
+                  g->d_offs, g->L, b, t, (T*)g->d_box);                                  \
+        ok = true;                                                                       \
+    }
+    MB_BOX_SHAPES(MB_BOX)
+#undef MB_BOX
     return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+bool box_shape_supported(int sx, int sy, int sz, int tx, int ty, int tz) {
+#define MB_BOX(SX, SY, SZ, FX, FY, FZ) \
+    if (sx == SX && sy == SY && sz == SZ && SX == FX * tx && SY == FY * ty && SZ == FZ * tz) return true;
+    MB_BOX_SHAPES(MB_BOX)
+#undef MB_BOX
+    return false;
 }
 
 template <typename T>
 hipError_t fold_boxes(mb_grid* g, T* f, hipStream_t s, const T* add) {
     MB_LAUNCH(g, K_FOLD, s, k_fold<T>, blocks_for(3 * g->N * g->tiles.nbox), BLK, 0,
-              (const T*)g->d_box, g->L, g->tiles, add, f);
+              (const T*)g->d_box, g->L, g->btiles, add, f);
     return hipGetLastError();
 }
 
