@@ -51,7 +51,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with "
-                "`python paper_1407_5600_amd/build.py` (or __graft_entry__.build())")
+                "`python paper_1407_5600_amd/build.py`")
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         sig = {

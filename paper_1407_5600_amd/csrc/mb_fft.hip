@@ -359,9 +359,21 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
         }
         out[kx * L + rl] = o;
     }
-    const double ts = block_reduce<false>(sv, red);
-    const double tf = block_reduce<false>(sf, red);
+    // the block's sums of v and f (one barrier; red holds 16 doubles, at
+    // most 8 waves of two partials each)
+    static_assert(2 * ((NTHR + WAVE - 1) / WAVE) <= 16, "reduction scratch");
+    const double wsv = wave_sum(sv), wsf = wave_sum(sf);
+    if (tid % WAVE == 0) {
+        red[2 * (tid / WAVE)] = wsv;
+        red[2 * (tid / WAVE) + 1] = wsf;
+    }
+    __syncthreads();
     if (tid == 0) {
+        double ts = 0.0, tf = 0.0;
+        for (int w = 0; w < (NTHR + WAVE - 1) / WAVE; ++w) {
+            ts += red[2 * w];
+            tf += red[2 * w + 1];
+        }
         const size_t pb = (size_t)box * G::NBX + lb;  // component-major order
         psum[2 * pb] = ts;
         psum[2 * pb + 1] = tf;

@@ -182,9 +182,12 @@ k_scan_apply(int* __restrict__ count, int64_t n, const int* __restrict__ bsum,
     __shared__ int scratch[16];
     __shared__ double red[16];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    int before = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += BLK) before += bsum[b];
-    const int off = (int)block_reduce<false>((double)before, red);
+    int off = 0;  // the counts of the blocks before this one
+    if (gridDim.x > 1) {
+        int before = 0;
+        for (int b = threadIdx.x; b < (int)blockIdx.x; b += BLK) before += bsum[b];
+        off = (int)block_reduce<false>((double)before, red);
+    }
     {
         int c[SCAN_ITEMS];  // all loads before the LDS stores
 #pragma unroll
@@ -330,9 +333,8 @@ __device__ __forceinline__ void springs_forces(const SpringsDev& sp, const Sprin
     const double qx = qp[3 * b], qy = qp[3 * b + 1], qz = qp[3 * b + 2];
     double fx = fe[0], fy = fe[1], fz = fe[2];
     const int* inc = B.adj + nb + 1;
-    const int e1 = B.adj[b + 1];
-    for (int x = B.adj[b]; x < e1; ++x) {
-        const int code = inc[x];
+    const int e0 = B.adj[b], e1 = B.adj[b + 1];
+    auto pair = [&](int code) {
         const int o = code & 0xff;
         const double* qo = qp + 3 * o;
         const double dx = qo[0] - qx, dy = qo[1] - qy, dz = qo[2] - qz;
@@ -342,6 +344,19 @@ __device__ __forceinline__ void springs_forces(const SpringsDev& sp, const Sprin
         fx += s * dx;
         fy += s * dy;
         fz += s * dz;
+    };
+    constexpr int DMAX = 16;  // incident pairs held in registers
+    if (e1 - e0 <= DMAX) {
+        // all incidence codes read at once, then the pairs four at a time
+        // (their position reads independent of one another)
+        int codes[DMAX];
+#pragma unroll
+        for (int x = 0; x < DMAX; ++x) codes[x] = e0 + x < e1 ? inc[e0 + x] : -1;
+#pragma unroll 4
+        for (int x = 0; x < DMAX; ++x)
+            if (codes[x] >= 0) pair(codes[x]);
+    } else {
+        for (int x = e0; x < e1; ++x) pair(inc[x]);
     }
     F[0] = fx;
     F[1] = fy;
@@ -368,14 +383,14 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
     const int nblob = (int)((P - p0 < sp.ppb ? P - p0 : sp.ppb) * sp.nb);
     const bool own = (int)threadIdx.x < nblob;
     const int64_t ib = p0 * sp.nb + threadIdx.x;
-    int tl = 0, rk = 0;
+    int tl = 0, rk = 0, off = 0;
     if (own) {
         tl = tile_of[ib];
         rk = rank[ib];
+        off = offs[tl];  // in flight while the block stages its positions
     }
     double fe[3];
     const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe);
-    const int off = own ? offs[tl] : 0;
     double F[3];
     int64_t i;
     springs_forces(sp, B, fe, F, &i);

@@ -20,7 +20,7 @@ def _declared():
     return sorted(set(re.findall(r"\b(mb_[a-z_]+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_step_calls():
     names = _declared()
     for n in ("mb_grid_create", "mb_spread", "mb_interpolate", "mb_fluid_solve",
               "mb_spring_forces", "mb_step"):
