@@ -55,47 +55,25 @@ __device__ __forceinline__ AxisSrc box_src_z(const Tiles& tl, int z) {
 
 // Sum of the entries of component array Ea (E + a * tiles * box volume)
 // holding the node with the given sources, formed so that the loads of a
-// node are issued together: an absent x or y/z source reads the node's own
-// entry again and is multiplied by zero.  With UNI the y and z sources are
-// known to be the same across the wave (lanes along one row in x, sources
-// computed from wave-uniform y and z): they then select a branch and only
-// the rows present are read.
-template <bool UNI, typename T>
+// node are issued together: an absent x, y or z source reads the node's own
+// entry again and is multiplied by zero.
+template <typename T>
 __device__ __forceinline__ T box_sum(const T* __restrict__ Ea, const AxisSrc& sx,
                                      const AxisSrc& sy, const AxisSrc& sz) {
     const int x0 = sx.off[0];
     const int x1 = sx.n > 1 ? sx.off[1] : x0;
     const T mx = sx.n > 1 ? T(1) : T(0);
+    const int y1 = sy.n > 1 ? sy.off[1] : sy.off[0];
+    const int z1 = sz.n > 1 ? sz.off[1] : sz.off[0];
+    const T my = sy.n > 1 ? T(1) : T(0);
+    const T mz = sz.n > 1 ? T(1) : T(0);
 #define MB_ROW(o) (Ea[(o) + x0] + mx * Ea[(o) + x1])
-    if constexpr (UNI) {
-        if (sz.n == 1 && sy.n == 1) return MB_ROW(sz.off[0] + sy.off[0]);
-        if (sz.n == 1) {
-            const T r0 = MB_ROW(sz.off[0] + sy.off[0]);
-            const T r1 = MB_ROW(sz.off[0] + sy.off[1]);
-            return r0 + r1;
-        }
-        if (sy.n == 1) {
-            const T r0 = MB_ROW(sz.off[0] + sy.off[0]);
-            const T r1 = MB_ROW(sz.off[1] + sy.off[0]);
-            return r0 + r1;
-        }
-        const T r0 = MB_ROW(sz.off[0] + sy.off[0]);
-        const T r1 = MB_ROW(sz.off[0] + sy.off[1]);
-        const T r2 = MB_ROW(sz.off[1] + sy.off[0]);
-        const T r3 = MB_ROW(sz.off[1] + sy.off[1]);
-        return (r0 + r1) + (r2 + r3);
-    } else {
-        const int y1 = sy.n > 1 ? sy.off[1] : sy.off[0];
-        const int z1 = sz.n > 1 ? sz.off[1] : sz.off[0];
-        const T my = sy.n > 1 ? T(1) : T(0);
-        const T mz = sz.n > 1 ? T(1) : T(0);
-        const T r0 = MB_ROW(sz.off[0] + sy.off[0]);
-        const T r1 = MB_ROW(sz.off[0] + y1);
-        const T r2 = MB_ROW(z1 + sy.off[0]);
-        const T r3 = MB_ROW(z1 + y1);
-        return (r0 + my * r1) + mz * (r2 + my * r3);
-    }
+    const T r0 = MB_ROW(sz.off[0] + sy.off[0]);
+    const T r1 = MB_ROW(sz.off[0] + y1);
+    const T r2 = MB_ROW(z1 + sy.off[0]);
+    const T r3 = MB_ROW(z1 + y1);
 #undef MB_ROW
+    return (r0 + my * r1) + mz * (r2 + my * r3);
 }
 
 // The entries of component array Ea holding a node, loaded without
@@ -142,7 +120,7 @@ template <typename T>
 __device__ __forceinline__ T box_sum(const T* __restrict__ E, const Tiles& tl,
                                      int a, int x, int y, int z) {
     const T* Ea = E + (size_t)a * tl.n * box_volume(tl);
-    return box_sum<false>(Ea, box_src_x(tl, x), box_src_y(tl, y), box_src_z(tl, z));
+    return box_sum(Ea, box_src_x(tl, x), box_src_y(tl, y), box_src_z(tl, z));
 }
 
 

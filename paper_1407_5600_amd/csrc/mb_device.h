@@ -56,9 +56,21 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // Weights of the 3-point kernel at the nodes i0-1, i0, i0+1 of a point at
 // offset t in [-1/2, 1/2] from node i0 (t = x/h - i0).  With s = sqrt(1-3t^2):
 // Phi(t) = (1+s)/3 and Phi(1 -+ t) = (2 +- 3t - s)/6.
+// sqrt(x) for the kernel weights, x in [1/4, 1]: the hardware square root
+// for float32 (within an ulp; the correctly rounded sequence costs ~16
+// instructions), x (1/sqrt x) with the Newton-refined reciprocal square root
+// for float64.
+__device__ __forceinline__ float weight_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double weight_sqrt(double x) { return x * rsqrt_nr(x); }
+
+// 1/x: the hardware reciprocal for float32 (within an ulp), the division
+// for float64.
+__device__ __forceinline__ float field_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double field_rcp(double x) { return 1.0 / x; }
+
 template <typename T>
 __device__ __forceinline__ void kernel_weights(T t, T w[3]) {
-    const T s = sqrt(T(1) - T(3) * t * t);
+    const T s = weight_sqrt(T(1) - T(3) * t * t);
     const T sixth = T(1) / T(6);
     w[1] = (T(1) + s) * (T(1) / T(3));
     w[2] = (T(2) + T(3) * t - s) * sixth;

@@ -486,8 +486,8 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
         const T D2 = d2x + d2[ky] + d2[kz];
         const cplx<T> rx = X[0], ry = X[W * LS], rz = X[2 * W * LS];
         const cplx<T> div = cadd(cadd(cmul(Dx, rx), cmul(Dy, ry)), cmul(Dz, rz));
-        const T inv_d2 = T(1) / D2;
-        const T scale = T(1) / (c0 + c1 * D2);
+        const T inv_d2 = field_rcp(D2);
+        const T scale = field_rcp(c0 + c1 * D2);
         const cplx<T> g = {div.x * inv_d2, div.y * inv_d2};
         const cplx<T> px = csub(rx, cmul(cconj(Dx), g));
         const cplx<T> py = csub(ry, cmul(cconj(Dy), g));

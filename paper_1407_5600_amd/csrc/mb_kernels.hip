@@ -810,15 +810,20 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
          const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
          double* __restrict__ u_out, double uscale, double* __restrict__ q, double dt,
          double inv_h, double* __restrict__ part, BinNext bn) {
+    // Staged nodes of component a: [lo-1, lo+T+1] along the axes b != a and
+    // [lo-1, lo+T] along its own (half-cell shifted) axis, rows of EX nodes
+    // along x; the components' regions follow one another in vt.
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
-    constexpr int EV = EX * EY * EZ;
     constexpr int TV = TX * TY * TZ;
     constexpr int RP = BLK / EX;             // rows staged per pass
-    constexpr int NR = (EY * EZ + RP - 1) / RP;
     constexpr int CPT = (TV + BLK - 1) / BLK; // own cells per thread
     constexpr int NCS = sizeof(T) == 4 ? 3 : 1;  // components staged together
-    __shared__ T vt[NCS * EV];
-    __shared__ int rowoff[EY * EZ];
+    constexpr int EYA[3] = {EY, EY - 1, EY};   // rows along y per component
+    constexpr int EZA[3] = {EZ, EZ, EZ - 1};   // along z
+    constexpr int VOFF[4] = {0, EX * EY * EZ, EX * EY * EZ + EX * (EY - 1) * EZ,
+                             EX * EY * EZ + EX * (EY - 1) * EZ + EX * EY * (EZ - 1)};
+    constexpr int NR = (EY * EZ + RP - 1) / RP;  // staged rows per thread (at most)
+    __shared__ T vt[NCS == 3 ? VOFF[3] : EX * EY * EZ];
     __shared__ double red[16];
     __shared__ int lcount[27];
     __shared__ int lbase[27];
@@ -827,10 +832,6 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
     const int N = L * L * L;  // 3 L^3 < 2^31 for L <= 512
     if (bn.count && threadIdx.x < 27) lcount[threadIdx.x] = 0;
     v += (size_t)tb.box * 3 * N;
-    for (int r = threadIdx.x; r < EY * EZ; r += BLK) {
-        const int ey = r % EY, ez = r / EY;
-        rowoff[r] = (wrapL(tb.lo[2] - 1 + ez, L) * L + wrapL(tb.lo[1] - 1 + ey, L)) * L;
-    }
     // the tile's own records
     const int first = offs[tile];
     const int total = offs[tile + 1] - first;
@@ -852,7 +853,6 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             q0[2] = q[3 * i0 + 2];
         }
     }
-    __syncthreads();  // rowoff
     double u0[3] = {0.0, 0.0, 0.0};  // velocity of the first record
     double sv[3] = {0.0, 0.0, 0.0};
     double dv[CPT];
@@ -862,24 +862,34 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
     for (int a0 = 0; a0 < 3; a0 += NCS) {
         if (a0 > 0) __syncthreads();  // the previous component's gathers are done
         if (sr < RP) {
-            // all loads of the thread first, then the LDS stores
+            // all loads of the thread first, then the LDS stores; row r of
+            // component a is (ey, ez) = (r mod EYA[a], r / EYA[a])
             T ld[NCS][NR];
 #pragma unroll
             for (int c = 0; c < NCS; ++c) {
-                const T* va = v + (int64_t)(a0 + c) * N + gx;
+                const int a = a0 + c;
+                const int rows = EYA[a] * EZA[a];
+                const T* va = v + (int64_t)a * N + gx;
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
-                    const int r = sr + k * RP;
-                    ld[c][k] = va[rowoff[r < EY * EZ ? r : sr]];
+                    int r = sr + k * RP;
+                    r = r < rows ? r : sr;
+                    const int ey = r % EYA[a], ez = r / EYA[a];
+                    ld[c][k] = va[(wrapL(tb.lo[2] - 1 + ez, L) * L +
+                                   wrapL(tb.lo[1] - 1 + ey, L)) * L];
                 }
             }
 #pragma unroll
-            for (int c = 0; c < NCS; ++c)
+            for (int c = 0; c < NCS; ++c) {
+                const int a = a0 + c;
+                const int rows = EYA[a] * EZA[a];
+                const int off = NCS == 3 ? VOFF[a] : 0;
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     const int r = sr + k * RP;
-                    if (r < EY * EZ) vt[c * EV + r * EX + sx] = ld[c][k];
+                    if (r < rows) vt[off + r * EX + sx] = ld[c][k];
                 }
+            }
         }
         __syncthreads();
         for (int k = threadIdx.x; k < total; k += BLK) {
@@ -899,13 +909,14 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
                     const int up = (int)((r.cell >> (27 + b)) & 1u);
                     e0[b] = a == b ? cc : cc + up;
                 }
-                const T* base = vt + c * EV + (e0[2] * EY + e0[1]) * EX + e0[0];
+                const int eya = EYA[a];
+                const T* base = vt + (NCS == 3 ? VOFF[a] : 0) + (e0[2] * eya + e0[1]) * EX + e0[0];
                 T acc = T(0);
 #pragma unroll
                 for (int oz = 0; oz < 3; ++oz) {
 #pragma unroll
                     for (int oy = 0; oy < 3; ++oy) {
-                        const T* row = base + (oz * EY + oy) * EX;
+                        const T* row = base + (oz * eya + oy) * EX;
                         const T sxv = w[0][0] * row[0] + w[0][1] * row[1] + w[0][2] * row[2];
                         acc += (w[2][oz] * w[1][oy]) * sxv;
                     }
@@ -928,7 +939,8 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
 #pragma unroll
             for (int c = 0; c < NCS; ++c) {
                 const int a = a0 + c;
-                const int str = a == 0 ? 1 : (a == 1 ? EX : EX * EY);
+                const int eya = EYA[a];
+                const int str = a == 0 ? 1 : (a == 1 ? EX : EX * eya);
 #pragma unroll
                 for (int j = 0; j < CPT; ++j) {
                     const int i = threadIdx.x + j * BLK;
@@ -936,7 +948,7 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
                         const int x = i % TX + 1;
                         const int y = (i / TX) % TY + 1;
                         const int z = i / (TX * TY) + 1;
-                        const int c0 = c * EV + (z * EY + y) * EX + x;
+                        const int c0 = (NCS == 3 ? VOFF[a] : 0) + (z * eya + y) * EX + x;
                         const T val = vt[c0];
                         sv[a] += (double)val;
                         dv[j] += (double)(val - vt[c0 - str]);
