@@ -103,9 +103,11 @@ def measured_traffic(kernel):
 
 def run_steps(torch, g, sp, q, v, Fe, n):
     # one call of n steps (steps after a call's first take their binning
-    # from the previous step's interpolation)
+    # from the previous step's interpolation), returning the diagnostics
+    # (momentum, net force, max |Dv|) of the last step
     if n > 0:
-        g.step(sp, q, v, Fe, n)
+        diag = torch.zeros(7, dtype=torch.float64, device=q.device)
+        g.step(sp, q, v, Fe, n, diag_out=diag)
 
 
 def bench_precision(torch, w, prec, steps, warmup, live_kernel=None):

@@ -177,7 +177,12 @@ mb_status mb_spring_forces(const mb_springs* springs, int64_t nparticles,
  * Sec. Multiblob particle model) receive the last step's values and may be
  * NULL.  diag_out (may be NULL) receives 7 float64 on the device:
  * {Pi_x, Pi_y, Pi_z, sumF_x, sumF_y, sumF_z, max|D v|} of the last step,
- * with Pi = rho h^3 sum_x v after the step.  nsteps >= 0. */
+ * with Pi = rho h^3 sum_x v after the step (their partial sums are formed
+ * on that step only, and only when diag_out is given).  Within one call,
+ * each step after the first takes the binning of its blobs from the
+ * interpolation of the step before (same results, one kernel fewer); a
+ * call always starts by binning q afresh, so q may be changed between
+ * calls.  nsteps >= 0. */
 mb_status mb_step(mb_grid* grid, const mb_springs* springs,
                   int64_t nparticles, double* q, void* v, const double* Fext,
                   double* u_out, double* U0_out, double* diag_out,

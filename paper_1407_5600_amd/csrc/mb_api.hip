@@ -497,23 +497,27 @@ template <typename T>
 static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t M,
                             double* q, T* v, const double* Fext, const double* Gblob,
                             const T* ffluid, double* u_dst, hipStream_t s,
-                            bool binned = false, bool bin_next = false) {
+                            bool binned = false, bool bin_next = false, bool diag = true) {
     T* ff = (T*)g->d_ffield;
     // forces at positions x, spread into the boxes (and folded with the
-    // fluid force when there is one); binned: the counts of q are in place
-    auto forces = [&](const double* x, bool counted) {
+    // fluid force when there is one); binned: the counts of q are in place;
+    // sums: the force sums of the diagnostics.  The diagnostics' partial
+    // sums (forces, momentum, max |Dv|) are formed only when diag is set
+    // (the step whose diagnostics are returned).
+    auto forces = [&](const double* x, bool counted, bool sums) {
         hipError_t e = bin_blobs<T>(g, M, x, s, counted);
-        if (e == hipSuccess) e = scatter_springs<T>(g, sd, P, x, Fext, s, Gblob);
+        if (e == hipSuccess) e = scatter_springs<T>(g, sd, P, x, Fext, s, Gblob, sums);
         if (e == hipSuccess) e = spread_boxes<T>(g, s);
         if (e == hipSuccess && ffluid) e = fold_boxes<T>(g, ff, s, ffluid);
         return e;
     };
     auto solve = [&]() { return fluid_solve<T>(g, v, ff, v, s, !ffluid); };
     hipError_t e;
+    const int dg = diag ? 1 : 0;
     if (g->scheme == MB_SCHEME_EULER) {
-        e = forces(q, binned);
+        e = forces(q, binned, diag);
         if (e == hipSuccess) e = solve();
-        if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 1, s, 1.0, bin_next);
+        if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, dg, s, 1.0, bin_next);
         return e;
     }
     // midpoint predictor-corrector: q* in d_mid, the second half of the
@@ -523,12 +527,12 @@ static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t
     e = blob_axpy(3 * M, nullptr, 1.0, q, qs, s);  // q* = q^n
     if (g->d.mode == MB_STEADY_STOKES) {
         // q* += (dt/2) J(q^n) v(q^n);  q += dt J(q*) v(q*)
-        if (e == hipSuccess) e = forces(q, false);
+        if (e == hipSuccess) e = forces(q, false, false);
         if (e == hipSuccess) e = solve();
         if (e == hipSuccess) e = interpolate<T>(g, M, v, nullptr, qs, 0, s, 0.5);
-        if (e == hipSuccess) e = forces(qs, false);
+        if (e == hipSuccess) e = forces(qs, false, diag);
         if (e == hipSuccess) e = solve();
-        if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 1, s);
+        if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, dg, s);
         return e;
     }
     // q* += (dt/2) J(q^n) v^n on the records of q^n
@@ -536,10 +540,10 @@ static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t
     if (e == hipSuccess) e = scatter_records<T>(g, M, q, nullptr, s);
     if (e == hipSuccess) e = interpolate<T>(g, M, v, nullptr, qs, 0, s, 0.5);
     // forces at q*; q += (dt/2) J(q*) v^n; solve; q += (dt/2) J(q*) v^{n+1}
-    if (e == hipSuccess) e = forces(qs, false);
+    if (e == hipSuccess) e = forces(qs, false, diag);
     if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst, q, 0, s, 0.5);
     if (e == hipSuccess) e = solve();
-    if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst ? u2 : nullptr, q, 1, s, 0.5);
+    if (e == hipSuccess) e = interpolate<T>(g, M, v, u_dst ? u2 : nullptr, q, dg, s, 0.5);
     if (e == hipSuccess && u_dst) e = blob_add(3 * M, u2, u_dst, s);
     return e;
 }
@@ -588,12 +592,13 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
         const bool binned = carry && n > 0, bin_next = carry && !last;
         double* u_dst = nullptr;
         if (last) u_dst = u_out ? u_out : (U0_out ? g->d_u : nullptr);
+        const bool diag = last && diag_out;  // partial sums only where they are read
         if (g->fsz == 4)
             e = step_once<float>(g, sd, P, M, q, (float*)v, Fext, Gblob, (const float*)ffluid,
-                                 u_dst, s, binned, bin_next);
+                                 u_dst, s, binned, bin_next, diag);
         else
             e = step_once<double>(g, sd, P, M, q, (double*)v, Fext, Gblob,
-                                  (const double*)ffluid, u_dst, s, binned, bin_next);
+                                  (const double*)ffluid, u_dst, s, binned, bin_next, diag);
         if (!last && e != hipSuccess && bin_next)
             (void)hipMemsetAsync(g->d_count, 0,
                                  sizeof(int) * (size_t)g->tiles.n * g->tiles.nbox, s);

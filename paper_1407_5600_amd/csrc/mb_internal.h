@@ -163,10 +163,12 @@ hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s,
 template <typename T>
 hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
                            const double* F, hipStream_t s, double fscale = 0.0);
+// Springs and records; force_sums: also the per-block sums of the blob
+// forces read by the diagnostics.
 template <typename T>
 hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
                            const double* q, const double* Fext, hipStream_t s,
-                           const double* Gblob = nullptr);
+                           const double* Gblob = nullptr, bool force_sums = true);
 hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
                          const double* Fext, double* F, hipStream_t s,
                          mb_grid* timing_grid, const double* Gblob = nullptr);

@@ -398,12 +398,14 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
         const Geom g = blob_geom(B.qs, threadIdx.x, inv_h, L);
         write_record<T>(rec, recf, perm, (int64_t)off + rk, i, g, F, inv_vol);
     }
-    double tot[3] = {F[0], F[1], F[2]};
-    block_reduce3(tot, red);
-    if (threadIdx.x == 0) {
-        fpart[3 * blockIdx.x] = tot[0];
-        fpart[3 * blockIdx.x + 1] = tot[1];
-        fpart[3 * blockIdx.x + 2] = tot[2];
+    if (fpart) {  // (a kernel argument: uniform over the block)
+        double tot[3] = {F[0], F[1], F[2]};
+        block_reduce3(tot, red);
+        if (threadIdx.x == 0) {
+            fpart[3 * blockIdx.x] = tot[0];
+            fpart[3 * blockIdx.x + 1] = tot[1];
+            fpart[3 * blockIdx.x + 2] = tot[2];
+        }
     }
 }
 
@@ -1269,14 +1271,14 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
 template <typename T>
 hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
                            const double* q, const double* Fext, hipStream_t s,
-                           const double* Gblob) {
+                           const double* Gblob, bool force_sums) {
     const int64_t M = P * sp.nb;
     if (M == 0) return hipSuccess;
     const double h = g->d.h;
     MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, springs_blocks(sp, P), BLK,
               springs_lds(sp), sp, q, Fext, Gblob, P, 1.0 / h, g->L, 1.0 / (h * h * h), g->d_offs,
               g->d_tile, g->d_rank, rec_geo<T>(g), rec_force<T>(g), g->d_perm,
-              g->d_force_part);
+              force_sums ? g->d_force_part : nullptr);
     g->perm_m = M;
     return hipGetLastError();
 }
@@ -1455,8 +1457,8 @@ template hipError_t bin_blobs<float>(mb_grid*, int64_t, const double*, hipStream
 template hipError_t bin_blobs<double>(mb_grid*, int64_t, const double*, hipStream_t, bool);
 template hipError_t scatter_records<float>(mb_grid*, int64_t, const double*, const double*, hipStream_t, double);
 template hipError_t scatter_records<double>(mb_grid*, int64_t, const double*, const double*, hipStream_t, double);
-template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*);
-template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*);
+template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*, bool);
+template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*, bool);
 template hipError_t spread_boxes<float>(mb_grid*, hipStream_t);
 template hipError_t spread_boxes<double>(mb_grid*, hipStream_t);
 template hipError_t fold_boxes<float>(mb_grid*, float*, hipStream_t, const float*);
