@@ -121,7 +121,7 @@ def bench_precision(torch, w, prec, steps, warmup, live_kernel=None):
     torch.cuda.synchronize()
     # calibration pass: every kernel timed, to find the dominant one
     g.set_timing("all")
-    ncal = 3
+    ncal = 20
     run_steps(torch, g, sp, q, v, Fe, ncal)
     kt = g.kernel_times()
     g.set_timing(None)

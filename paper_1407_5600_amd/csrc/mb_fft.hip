@@ -232,8 +232,13 @@ struct Geo {
     static constexpr int H = L / 2;
     static constexpr int PS = (lpad(H) + 1) | 1;
     static constexpr int PLANE_BYTES = L * PS * 2 * (int)sizeof(T);
-    // used when two planes fit in a CU's 160 KB of LDS
-    static constexpr bool XY = PLANE_BYTES <= 72 * 1024;
+    // used when two planes fit in a CU's 160 KB of LDS (float32 L <= 128,
+    // float64 L <= 72), or one plane with L <= 144 (float32 L = 144, float64
+    // L = 96, 128: faster than the two passes it replaces; float32 L = 192,
+    // one block per CU in 1.1 rounds, was slower)
+    static constexpr int XY_LDS = PLANE_BYTES + (L + H) * 2 * (int)sizeof(T);
+    static constexpr bool XY =
+        PLANE_BYTES <= 72 * 1024 || (XY_LDS <= 160 * 1024 && L <= 144);
     static constexpr int TXY_RAW = ((L * H / 16 + WAVE - 1) / WAVE) * WAVE;
     static constexpr int TXY = TXY_RAW > 512 ? 512 : TXY_RAW;  // threads
     static constexpr int NBXY = 3 * L;                         // blocks per box

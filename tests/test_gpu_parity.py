@@ -172,6 +172,25 @@ def test_fluid_solve(torch_cuda, prec, L, mode):
     check(f"solve in place {prec} L={L} {mode}", vt.double().cpu().numpy(), ref, prec)
 
 
+@pytest.mark.parametrize("prec,L", [("mixed", 128), ("mixed", 144), ("fp64", 128)])
+def test_fluid_solve_plane_pass_sizes(torch_cuda, prec, L):
+    """The largest sizes whose inverse y and x transforms run as one plane
+    per block (float32 L = 144 and float64 L = 128 with one block per CU),
+    against the oracle on random fields."""
+    torch = torch_cuda
+    say("solve plane pass", prec, L)
+    rng = np.random.default_rng(1000 + L)
+    kw = dict(rho=1.3, eta=0.7, dt=0.05)
+    g = grid(L, prec, 0, **kw)
+    vt = torch.from_numpy(rng.standard_normal((3, L, L, L))).to(g.field_dtype).cuda()
+    ft = torch.from_numpy(rng.standard_normal((3, L, L, L)) + 0.3).to(g.field_dtype).cuda()
+    out = g.fluid_solve(vt, ft)
+    torch.cuda.synchronize()
+    prm = oracle.params(L, rho=kw["rho"], eta=kw["eta"], dt=kw["dt"])
+    ref = oracle.fluid_solve(prm, vt.double().cpu().numpy(), ft.double().cpu().numpy())
+    check(f"solve {prec} L={L}", out.double().cpu().numpy(), ref, prec)
+
+
 @pytest.mark.parametrize("prec,L", [("fp64", 256), ("mixed", 256), ("mixed", 512)])
 def test_fluid_solve_large_shear_mode(torch_cuda, prec, L):
     """Largest grids, checked by a property that holds at any size: a shear
