@@ -197,15 +197,19 @@ constexpr int cols_y(int L) {
     return w < nc ? w : nc;
 }
 // ky columns per block of the z pass (a divisor of L; LDS <= 64 KB).  At
-// 128^3 eight columns give 1,040 blocks of 384 threads, which fill the CUs
-// in one round (sixteen gave 520 blocks of 768 threads: two per CU, and a
-// nearly empty second round).
+// 128^3 float32, eight columns give 1,040 blocks of 384 threads, which fill
+// the CUs in one round (sixteen gave 520 blocks of 768 threads: two per CU,
+// and a nearly empty second round); float64 takes four (2,080 blocks of 192
+// threads: 26.5 us against 38.5 us with eight).
 #ifndef MB_ZCOLS
 #define MB_ZCOLS 8
 #endif
+#ifndef MB_ZCOLS_F64
+#define MB_ZCOLS_F64 4
+#endif
 template <typename T>
 constexpr int cols_z(int L) {
-    int w = MB_ZCOLS;
+    int w = sizeof(T) == 8 ? MB_ZCOLS_F64 : MB_ZCOLS;
     while (w > 1 && (L % w != 0 || 3 * L * w * 2 * (int)sizeof(T) > 65536 ||
                      3 * w * L / EPT > 1024))
         w /= 2;
