@@ -261,7 +261,19 @@ def cpu_baseline(w, nsteps):
     return {"value": nsteps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{nsteps} float64 steps of the same workload "
                       f"({w.L}^3, {w.P} particles), single-threaded C oracle",
-            "seconds": dt}
+            "seconds": dt, "host_cpu": host_cpu()}
+
+
+def host_cpu():
+    """Model name of the host CPU (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_batch(torch, nbox, steps, sample=32):
@@ -341,7 +353,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="dense", choices=["dense", "large", "single"])
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="run one precision (profiling)")
