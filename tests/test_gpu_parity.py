@@ -191,7 +191,26 @@ def test_fluid_solve_plane_pass_sizes(torch_cuda, prec, L):
     check(f"solve {prec} L={L}", out.double().cpu().numpy(), ref, prec)
 
 
-@pytest.mark.parametrize("prec,L", [("fp64", 256), ("mixed", 256), ("mixed", 512)])
+@pytest.mark.parametrize("prec,L", [("fp64", 144), ("fp64", 192)])
+def test_fluid_solve_z_pass_widths(torch_cuda, prec, L):
+    """Float64 sizes above 128, whose z pass takes eight ky columns per block
+    (one block per CU), against the oracle on random fields."""
+    torch = torch_cuda
+    say("solve z widths", prec, L)
+    rng = np.random.default_rng(2000 + L)
+    kw = dict(rho=1.3, eta=0.7, dt=0.05)
+    g = grid(L, prec, 0, **kw)
+    vt = torch.from_numpy(rng.standard_normal((3, L, L, L))).to(g.field_dtype).cuda()
+    ft = torch.from_numpy(rng.standard_normal((3, L, L, L)) + 0.3).to(g.field_dtype).cuda()
+    out = g.fluid_solve(vt, ft)
+    torch.cuda.synchronize()
+    prm = oracle.params(L, rho=kw["rho"], eta=kw["eta"], dt=kw["dt"])
+    ref = oracle.fluid_solve(prm, vt.double().cpu().numpy(), ft.double().cpu().numpy())
+    check(f"solve {prec} L={L}", out.double().cpu().numpy(), ref, prec)
+
+
+@pytest.mark.parametrize("prec,L", [("fp64", 256), ("mixed", 256), ("fp64", 384),
+                                    ("fp64", 512), ("mixed", 512)])
 def test_fluid_solve_large_shear_mode(torch_cuda, prec, L):
     """Largest grids, checked by a property that holds at any size: a shear
     mode v_x = sin(2 pi m y / L) decays by exactly g = (1 - nu dt lam/2) /
