@@ -291,8 +291,10 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
     }
     // KG iterations (2 KG nodes) per round: all loads of a round, the box
     // entries included (box_entries: loads only, in uniform branches), are
-    // issued before its arithmetic
-    constexpr int KG = sizeof(T) == 4 ? 2 : 1;  // registers
+    // issued before its arithmetic.  One iteration: two took 96 registers in
+    // float32 (five waves per SIMD, 1.2 rounds of blocks at 128^3); one fits
+    // six waves and one round (25.4 against 26.7 us).
+    constexpr int KG = 1;
     static_assert(EPT % KG == 0, "rounds of the x pass");
     // a wave's lanes share y when L is a multiple of the wave
     constexpr bool UNI = L % WAVE == 0 && NTHR % L == 0;
