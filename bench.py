@@ -119,7 +119,8 @@ def bench_precision(torch, w, prec, steps, warmup, live_kernel=None):
     Fe = torch.from_numpy(w.Fext).cuda()
     run_steps(torch, g, sp, q, v, Fe, warmup)
     torch.cuda.synchronize()
-    # calibration pass: every kernel timed, to find the dominant one
+    # calibration pass: every kernel timed (each launch records its own
+    # start and end), to find the dominant one
     g.set_timing("all")
     ncal = 20
     run_steps(torch, g, sp, q, v, Fe, ncal)
@@ -128,23 +129,32 @@ def bench_precision(torch, w, prec, steps, warmup, live_kernel=None):
     per_step = {k: ms / ncal for k, (ms, n) in kt.items()}
     avg = {k: ms / n for k, (ms, n) in kt.items()}
     dominant = live_kernel or max(per_step, key=per_step.get)
-    # timed region: only the dominant kernel is bracketed by events
-    g.set_timing([dominant])
+    # timed region of the headline: no events, one call of all the steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run_steps(torch, g, sp, q, v, Fe, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same steps again with the dominant kernel's launches timed (on the
+    # stream they run on), for its live duration
+    g.set_timing([dominant])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    run_steps(torch, g, sp, q, v, Fe, steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     live = g.kernel_times()
     g.set_timing(None)
     ms, n = live[dominant]
     assert bool(torch.isfinite(v).all()), "non-finite velocity"
     return {
         "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "timed_pass_ms_per_step": (t3 - t2) * 1e3 / steps,
         "per_step_ms": per_step,
         "avg_launch_ms": avg,
         "dominant": dominant,
         "dominant_live_ms": ms / n,
+        "dominant_launches": n,
     }
 
 
@@ -250,27 +260,83 @@ def bench_stokes(torch, oracle_sample=True):
     return out
 
 
-def cpu_baseline(w, nsteps):
-    import numpy as np
-    import oracle
-    prm = oracle.params(w.L, h=w.h, rho=w.rho, eta=w.eta, dt=w.dt)
-    v = np.zeros((3, w.L, w.L, w.L))
+# Child process of the CPU baseline: times single float64 oracle steps of the
+# cached workload with the OpenMP build (the library path and thread count
+# come from the environment), until `budget` seconds or `max_steps` steps,
+# at least `min_steps`; prints the step times as JSON.
+_CPU_CHILD = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_1407_5600_amd import inputs
+w = inputs.cached(sys.argv[2])
+budget, min_steps, max_steps = float(sys.argv[3]), int(sys.argv[4]), int(sys.argv[5])
+prm = oracle.params(w.L, h=w.h, rho=w.rho, eta=w.eta, dt=w.dt)
+q, v = w.q.copy(), np.zeros((3, w.L, w.L, w.L))
+times = []
+t_start = time.perf_counter()
+while len(times) < max_steps and (len(times) < min_steps or
+                                   time.perf_counter() - t_start < budget):
     t0 = time.perf_counter()
-    oracle.step(prm, w.springs(), w.q, v, w.Fext, nsteps)
-    dt = time.perf_counter() - t0
-    return {"value": nsteps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} float64 steps of the same workload "
-                      f"({w.L}^3, {w.P} particles), single-threaded C oracle",
-            "seconds": dt, "host_cpu": host_cpu()}
+    r = oracle.step(prm, w.springs(), q, v, w.Fext, 1)
+    times.append(time.perf_counter() - t0)
+    q, v = r["q"], r["v"]
+print(json.dumps(times))
+"""
+
+
+def cpu_baseline(workload, budget_s=12.0, min_steps=3, max_steps=30):
+    """The float64 oracle (plain C, its OpenMP build at -O3) timed on the
+    host's cores: single steps of the same workload from rest, the median
+    step time.  Threads: the CPUs this process may run on, capped by
+    OMP_NUM_THREADS when the environment sets it."""
+    import statistics
+    import subprocess
+    from oracle import build as obuild
+    if not os.path.exists(obuild.LIB_OMP):
+        obuild.build(openmp=True)
+    ncpu = len(os.sched_getaffinity(0))
+    threads = ncpu
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = max(1, min(ncpu, int(os.environ["OMP_NUM_THREADS"])))
+    env = dict(os.environ, MBO_ORACLE_LIB=obuild.LIB_OMP, OMP_NUM_THREADS=str(threads),
+               OMP_PROC_BIND="close")
+    r = subprocess.run([sys.executable, "-c", _CPU_CHILD, ROOT, workload, str(budget_s),
+                        str(min_steps), str(max_steps)], env=env, capture_output=True,
+                       text=True, check=True)
+    times = json.loads(r.stdout.strip().splitlines()[-1])
+    med = statistics.median(times)
+    return {"value": 1.0 / med, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(times)} single float64 steps of the same workload from rest, "
+                      f"median step time; C oracle built -O3 -fopenmp, {threads} threads",
+            "step_seconds": [round(t, 4) for t in times], "affinity_cpus": ncpu,
+            "host_cpu": host_cpu()}
 
 
 def host_cpu():
-    """Model name of the host CPU (Linux), or None."""
+    """The host CPU as lscpu reports it (model name, sockets, cores per
+    socket, threads per core), else /proc/cpuinfo's model name, or None."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    keys = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+            "CPU(s)", "CPU max MHz")
+    got = {k: info[k] for k in keys if k in info}
+    if got:
+        return got
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
                 if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                    return {"Model name": line.split(":", 1)[1].strip()}
     except OSError:
         pass
     return None
@@ -353,7 +419,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="dense", choices=["dense", "large", "single"])
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU time budget of the oracle baseline (at least 3 steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="run one precision (profiling)")
@@ -432,7 +499,9 @@ def main():
                      "traffic": (measured_traffic(dom)
                                  if args.workload == "dense" and head_prec == "mixed" else None),
                      "alg_bytes_per_launch": dom_bytes,
-                     "live_avg_launch_ms": round(head["dominant_live_ms"], 5)},
+                     "live_avg_launch_ms": round(head["dominant_live_ms"], 5),
+                     "live_launches": head["dominant_launches"],
+                     "live_pass_ms_per_step": round(head["timed_pass_ms_per_step"], 5)},
     }
     if "fp64" in res:
         out["kernels_fp64"] = {k: round(ms, 5) for k, ms in res["fp64"]["per_step_ms"].items()}
@@ -451,7 +520,7 @@ def main():
         out["batch"] = bench_batch(torch, args.batch_boxes, args.batch_steps)
     if not args.no_cpu_baseline and args.workload != "large":
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -21,8 +21,11 @@
  *     and fluctuating stresses of eq. vf are not included).
  *
  * Memory: every pointer argument except those marked "host" is a device
- * pointer on the grid's device.  The caller owns all buffers; the library
- * never frees or keeps them beyond the call.  Layouts:
+ * pointer on the grid's device, aligned to 256 bytes (as every hipMalloc
+ * and torch allocation is); a misaligned pointer gives MB_ERR_INVALID.  The
+ * caller owns all buffers; the library never frees them and keeps none
+ * beyond the call, except a workspace given to mb_grid_set_workspace.
+ * Layouts:
  *   q, F, u     [M][3] float64, row-major; blob nb*p + b belongs to
  *               particle p (b = 0..11 vertices, 12 the centre).
  *   Fext, U0    [P][3] float64.
@@ -37,9 +40,13 @@
  * at once (it owns scratch buffers).
  *
  * Errors: every call returns an mb_status and never throws.  Invalid
- * arguments (null pointers, sizes out of range, a grid from another
- * device) give MB_ERR_INVALID; no usable GPU gives MB_ERR_DEVICE;
- * allocation failure gives MB_ERR_NOMEM.
+ * arguments (null or misaligned pointers, sizes out of range, a grid from
+ * another device, a grid without its workspace) give MB_ERR_INVALID; a
+ * valid configuration this library has no kernels for gives
+ * MB_ERR_UNSUPPORTED; no usable GPU, a failed launch or a device error
+ * reported while enqueueing gives MB_ERR_DEVICE; allocation failure gives
+ * MB_ERR_NOMEM; with check_finite, a non-finite blob position or force
+ * gives MB_ERR_NONFINITE (see mb_grid_desc).
  */
 #ifndef MULTIBLOB_H
 #define MULTIBLOB_H
@@ -56,7 +63,8 @@ typedef enum {
     MB_ERR_INVALID = -1,
     MB_ERR_UNSUPPORTED = -2,
     MB_ERR_NOMEM = -3,
-    MB_ERR_DEVICE = -4
+    MB_ERR_DEVICE = -4,
+    MB_ERR_NONFINITE = -5
 } mb_status;
 
 typedef enum {
@@ -89,13 +97,46 @@ typedef enum {
                                with a steady solve at q^n and one at q*. */
 } mb_scheme;
 
-/* Grid description.  L = 2^a 3^b with 8 <= L <= 512 and L a multiple of 8;
+/* Grid description.
+ *
+ * L: cells per side, 8 <= L <= 512, L = 2^a 3^b (the FFT plans are radix 2,
+ * 3, 4, 8 and 16, compiled per size), and L a multiple of 8: the binning,
+ * spreading and interpolation kernels work on tiles of 8 or 16 cells per
+ * axis (tile indices by shifts, one workgroup per tile).  The sizes with
+ * kernels are 8, 16, 24, 32, 48, 64, 72, 96, 128, 144, 192, 216, 256, 288,
+ * 384, 432 and 512; other 2^a 3^b sizes (12, 18, 27, 36, 54, 81, 108, ...)
+ * give MB_ERR_UNSUPPORTED, any other L MB_ERR_INVALID.
  * h > 0, dt > 0; rho > 0 in MB_UNSTEADY_CN; eta > 0 in MB_STEADY_STOKES
  * (eta = 0 is allowed in MB_UNSTEADY_CN: ideal fluid).  zero_mean = 1 holds
  * the k = 0 velocity mode at zero (a periodic array of particles with no net
  * flow, the setting of eq. rhinf); zero_mean = 0 evolves it exactly,
  * mean(v') = mean(v) + (dt/rho) mean(f).  max_blobs bounds the M of every
- * later call on this grid (blob-sized scratch is allocated once). */
+ * later call on this grid (blob-sized scratch is sized once).
+ *
+ * deterministic = 1: every result is the same bit for bit from run to run.
+ * Spreading always sums in fixed point (independent of the order of the
+ * blobs and of the atomic additions); the one order-dependent path, float64
+ * LDS atomics for a float64 spreading box tile (16^3 cells) of more than
+ * 2^20 blobs, is then replaced by two 64-bit fixed-point sums (the
+ * contributions, then their rounding remainders; up to 2^25 blobs in one
+ * box tile, beyond which the atomics remain), and mb_step_adjoint sums the
+ * stiffness and rest-length derivatives per block in a fixed order instead
+ * of with float64 atomics.  deterministic = 0 allows those paths.
+ *
+ * check_finite = 1: the calls that read blob positions or blob forces
+ * (mb_spread, mb_interpolate, mb_interpolate_grad and every step call)
+ * check each position and force they use, at every step; if one is NaN or
+ * infinite the call finishes its launches, waits for its stream and
+ * returns MB_ERR_NONFINITE (its outputs are then undefined).  The check
+ * costs one stream synchronisation per call, so mb_step_graph checks only
+ * after its last replay.  check_finite = 0 (the default): no check and no
+ * synchronisation; non-finite inputs give non-finite or meaningless
+ * outputs, never an access outside the library's buffers.
+ *
+ * external_workspace = 1: mb_grid_create allocates no scratch; every call
+ * on the grid returns MB_ERR_INVALID until a workspace of at least
+ * mb_workspace_size bytes is given with mb_grid_set_workspace (for example
+ * a torch tensor, so that one allocator holds all device memory). */
 typedef struct {
     int32_t L;
     int32_t precision; /* mb_precision */
@@ -106,16 +147,44 @@ typedef struct {
     double eta;
     double dt;
     int64_t max_blobs;
+    int32_t deterministic;
+    int32_t check_finite;
+    int32_t external_workspace;
+    int32_t reserved;  /* must be 0 */
 } mb_grid_desc;
 
 typedef struct mb_grid mb_grid;       /* opaque; owns FFT tables and scratch */
 typedef struct mb_springs mb_springs; /* opaque; owns the pair table */
 
-/* Create a grid on the current HIP device.  Allocates the spectrum (about
- * 1.5 L^3 complex values), the spread boxes (about 6.75 L^3 values of the
- * field precision), the per-tile binning arrays and ~100 B per blob of
- * scratch.  *out is set to NULL on error. */
+/* Create a grid on the current HIP device.  Unless desc->external_workspace
+ * is set, allocates its workspace (mb_workspace_size bytes: the FFT tables,
+ * the spectrum of about 1.5 L^3 complex values, the spread boxes of about
+ * 5-7 L^3 values of the field precision, the per-tile binning arrays and
+ * ~100 B per blob), which it frees at mb_grid_destroy.  *out is set to NULL
+ * on error. */
 mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out);
+
+/* Bytes of device workspace a grid of this description holds (nbox boxes;
+ * nbox = 1 for mb_grid_create): the FFT twiddle and symbol tables, the
+ * spectrum, the spread boxes (sized for every tile shape that fits L, so
+ * mb_grid_set_tiles and mb_grid_autotune never reallocate), the binning
+ * arrays, the sorted blob records and the partial sums of the diagnostics.
+ * The midpoint scheme (mb_grid_set_scheme), forced steps and the reverse
+ * step keep their extra scratch outside it (allocated by the library when
+ * first enabled or called).  0 for an invalid description or nbox. */
+size_t mb_workspace_size(const mb_grid_desc* desc, int32_t nbox);
+
+/* Give the grid a caller-owned device workspace of `bytes` bytes (at least
+ * mb_workspace_size of the grid's description and box count, 256-byte
+ * aligned, on the grid's device), replacing the workspace it had (a
+ * library-allocated one is freed).  Waits for the device first (no work of
+ * this grid may be in flight), then initialises the workspace (FFT tables,
+ * zeroed counters) on the NULL stream and waits for that.  The caller must
+ * keep the buffer alive and unused by anything else until mb_grid_destroy
+ * or the next mb_grid_set_workspace.  The sorted order of the last binning
+ * is forgotten (results are unchanged).  MB_ERR_INVALID if dev_ptr is NULL
+ * or misaligned, or bytes too small. */
+mb_status mb_grid_set_workspace(mb_grid* grid, void* dev_ptr, size_t bytes);
 
 /* A grid holding a batch of nbox independent periodic boxes of the same
  * description (1 <= nbox <= 65536), each call advancing all of them in one
@@ -129,7 +198,9 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out);
 mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox,
                                mb_grid** out);
 
-/* Release a grid (synchronises its device first).  NULL is accepted. */
+/* Release a grid and the workspace it allocated (synchronises its device
+ * first; a caller-given workspace is left to the caller).  NULL is
+ * accepted. */
 mb_status mb_grid_destroy(mb_grid* grid);
 
 /* Spring table of one particle template (Fig. 1: hard springs joining the
@@ -143,6 +214,14 @@ mb_status mb_springs_create(int32_t blobs_per_particle, int32_t npairs,
                             const double* rest_len, double k,
                             mb_springs** out);
 mb_status mb_springs_destroy(mb_springs* springs);
+
+/* New rest lengths (HOST array of npairs values > 0, read before the call
+ * returns and copied to the device in the order of `stream`) and stiffness
+ * k >= 0 of a spring table, for every call enqueued after this one (fitting
+ * k and the particle size changes them between trajectories without a new
+ * table or a device synchronisation). */
+mb_status mb_springs_set_params(mb_springs* springs, const double* rest_len,
+                                double k, void* stream);
 
 /* Spreading S (definition of S_i after eq. jm): f_out = sum_i
  * delta_h(x - q_i) F_i at every staggered node, overwriting f_out.
@@ -277,10 +356,10 @@ mb_status mb_step_adjoint(mb_grid* grid, const mb_springs* springs,
 /* Human-readable text for a status. */
 const char* mb_status_string(mb_status status);
 
-/* Per-kernel timing (measurement support).  Kernels whose id bit is set in
- * kernel_mask (bit i = kernel id i; 0 disables timing) are bracketed by HIP
- * events on the caller's stream, and their durations are accumulated per
- * kernel id.  mb_grid_kernel_times synchronises the stream, then writes up
+/* Per-kernel timing (measurement support).  Each launch of a kernel whose
+ * id bit is set in kernel_mask (bit i = kernel id i; 0 disables timing)
+ * records a pair of HIP events at its own start and end (hipExtLaunchKernel),
+ * and the durations are accumulated per kernel id.  mb_grid_kernel_times synchronises the stream, then writes up
  * to `cap` entries of total milliseconds and launch counts per kernel id
  * (ids are stable; names from mb_kernel_name) and returns the number of ids
  * in *n_out.  Setting a mask clears the accumulators. */

@@ -22,12 +22,28 @@ import torch
 from .binding import Springs
 
 
+def _springs_for(grid, nb, pa, pb, r0, k):
+    """The grid's spring table for this template, created once and given the
+    trajectory's rest lengths and stiffness (mb_springs_set_params) on
+    later calls."""
+    key = (int(nb), pa.tobytes(), pb.tobytes())
+    cache = getattr(grid, "_traj_springs", None)
+    if cache is not None and cache[0] == key:
+        cache[1].set_params(r0, k)
+        return cache[1]
+    sp = Springs(nb, pa, pb, r0, k)
+    grid._traj_springs = (key, sp)
+    return sp
+
+
 class _Trajectory(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q0, v0, G, k, r0, grid, nb, pa, pb, nsteps, every):
         if grid.precision != "fp64":
             raise ValueError("differentiable trajectories need a float64 grid")
-        springs = Springs(nb, pa, pb, r0.detach().cpu().numpy(), float(k))
+        r0h = r0.detach().cpu().numpy().astype(np.float64)
+        springs = _springs_for(grid, nb, pa, pb, r0h, float(k))
+        ctx.r0h = r0h
         q = q0.detach().clone()
         v = v0.detach().clone()
         Gd = G.detach().contiguous()
@@ -46,6 +62,8 @@ class _Trajectory(torch.autograd.Function):
     @staticmethod
     def backward(ctx, du):
         grid, springs, G = ctx.grid, ctx.springs, ctx.G
+        # another trajectory on this grid may have changed the shared table
+        springs.set_params(ctx.r0h, ctx.k)
         nb, nsteps, every = ctx.nb, ctx.nsteps, ctx.every
         dev = G.device
         f64 = torch.float64

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmultiblob.so")
 
 MB_OK, MB_ERR_INVALID, MB_ERR_UNSUPPORTED, MB_ERR_NOMEM, MB_ERR_DEVICE = 0, -1, -2, -3, -4
+MB_ERR_NONFINITE = -5
 MB_FP64, MB_MIXED = 0, 1
 MB_UNSTEADY_CN, MB_STEADY_STOKES = 0, 1
 MB_SCHEME_EULER, MB_SCHEME_MIDPOINT = 0, 1
@@ -38,6 +39,10 @@ class GridDesc(ctypes.Structure):
         ("eta", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("max_blobs", ctypes.c_int64),
+        ("deterministic", ctypes.c_int32),
+        ("check_finite", ctypes.c_int32),
+        ("external_workspace", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -59,6 +64,9 @@ def lib():
             "mb_grid_create_batch": ([ctypes.POINTER(GridDesc), i32, ctypes.POINTER(vp)], i32),
             "mb_step_graph": ([i32, vp, vp, vp, vp, vp, vp, vp, i32, vp], i32),
             "mb_grid_destroy": ([vp], i32),
+            "mb_workspace_size": ([ctypes.POINTER(GridDesc), i32], ctypes.c_size_t),
+            "mb_grid_set_workspace": ([vp, vp, ctypes.c_size_t], i32),
+            "mb_springs_set_params": ([vp, vp, d, vp], i32),
             "mb_springs_create": ([i32, i32, vp, vp, vp, d, ctypes.POINTER(vp)], i32),
             "mb_springs_destroy": ([vp], i32),
             "mb_spread": ([vp, i64, vp, vp, vp, vp], i32),
@@ -97,7 +105,8 @@ EXPORTED = ("mb_grid_create", "mb_grid_destroy", "mb_springs_create",
             "mb_interpolate_grad", "mb_spring_adjoint", "mb_step_adjoint",
             "mb_grid_create_batch", "mb_step_graph", "mb_step_forced",
             "mb_grid_set_scheme", "mb_grid_set_tiles", "mb_grid_get_tiles",
-            "mb_grid_autotune")
+            "mb_grid_autotune", "mb_workspace_size", "mb_grid_set_workspace",
+            "mb_springs_set_params")
 
 
 def status_string(st: int) -> str:
@@ -155,6 +164,19 @@ class Springs:
         self.npairs = len(pa)
         self.k = float(k)
 
+    def set_params(self, rest_len, k, stream=None):
+        """mb_springs_set_params: new rest lengths (host values, copied in
+        stream order) and stiffness for the later calls."""
+        import numpy as np
+        r0 = np.ascontiguousarray(rest_len, dtype=np.float64)
+        if r0.shape != (self.npairs,):
+            raise ValueError(f"rest_len must have shape ({self.npairs},)")
+        _check(lib().mb_springs_set_params(self.handle, r0.ctypes.data_as(ctypes.c_void_p),
+                                           float(k), _stream(stream)),
+               "mb_springs_set_params")
+        self._r0_keep = r0  # the copy may still read it
+        self.k = float(k)
+
     def close(self):
         if self.handle:
             lib().mb_springs_destroy(self.handle)
@@ -171,12 +193,17 @@ class Grid:
     """A periodic MAC grid with its FFT tables and scratch (mb_grid_create)."""
 
     def __init__(self, L, h=1.0, rho=1.0, eta=1.0, dt=0.01, precision="fp64",
-                 mode="unsteady", zero_mean=False, max_blobs=0, nbox=1, scheme="euler"):
+                 mode="unsteady", zero_mean=False, max_blobs=0, nbox=1, scheme="euler",
+                 deterministic=False, check_finite=False, workspace=None):
+        """workspace: None (the library allocates the grid's scratch),
+        "torch" (a torch uint8 tensor of mb_workspace_size bytes, allocated
+        here and kept by this object), or such a tensor of the caller's."""
         import torch
         prec = {"fp64": MB_FP64, "mixed": MB_MIXED}[precision]
         md = {"unsteady": MB_UNSTEADY_CN, "steady": MB_STEADY_STOKES}[mode]
         self.desc = GridDesc(int(L), prec, md, int(bool(zero_mean)), float(h), float(rho),
-                             float(eta), float(dt), int(max_blobs))
+                             float(eta), float(dt), int(max_blobs), int(bool(deterministic)),
+                             int(bool(check_finite)), int(workspace is not None), 0)
         h_ = ctypes.c_void_p()
         if nbox == 1:
             _check(lib().mb_grid_create(ctypes.byref(self.desc), ctypes.byref(h_)),
@@ -191,8 +218,29 @@ class Grid:
         self.field_dtype = torch.float64 if prec == MB_FP64 else torch.float32
         self.device = torch.cuda.current_device()
         self.scheme = "euler"
+        self.workspace = None
+        if workspace is not None:
+            self.set_workspace(None if isinstance(workspace, str) else workspace)
         if scheme != "euler":
             self.set_scheme(scheme)
+
+    def workspace_size(self):
+        """mb_workspace_size of this grid's description and box count."""
+        return int(lib().mb_workspace_size(ctypes.byref(self.desc), self.nbox))
+
+    def set_workspace(self, buf=None):
+        """mb_grid_set_workspace: the grid's scratch in a torch uint8 tensor
+        (allocated here when buf is None), kept alive by this object."""
+        import torch
+        n = self.workspace_size()
+        if buf is None:
+            buf = torch.empty(n, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.is_contiguous()):
+            raise ValueError("workspace must be a contiguous GPU tensor")
+        nbytes = buf.numel() * buf.element_size()
+        _check(lib().mb_grid_set_workspace(self.handle, ctypes.c_void_p(buf.data_ptr()), nbytes),
+               "mb_grid_set_workspace")
+        self.workspace = buf
 
     @property
     def tiles(self):
@@ -228,6 +276,7 @@ class Grid:
         if self.handle:
             lib().mb_grid_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
         try:

@@ -30,12 +30,14 @@ const char* const kKernelNames[K_NUM] = {
     "diag",        "fold",        "interp_grad",      "springs_adjoint",
     "fft_xy_inv"};
 
-bool size_ok(int L) {
-    if (L < 8 || L > 512 || L % 8 != 0) return false;
+// Grid sizes: 2^a 3^b in [8, 512]; kernels exist for the multiples of 8.
+mb_status size_status(int L) {
+    if (L < 8 || L > 512) return MB_ERR_INVALID;
     int n = L;
     while (n % 2 == 0) n /= 2;
     while (n % 3 == 0) n /= 3;
-    return n == 1;
+    if (n != 1) return MB_ERR_INVALID;
+    return L % 8 == 0 ? MB_OK : MB_ERR_UNSUPPORTED;
 }
 
 bool device_ok(int* dev) {
@@ -55,27 +57,6 @@ mb_status from_hip(hipError_t e) {
     if (e == hipSuccess) return MB_OK;
     if (e == hipErrorOutOfMemory) return MB_ERR_NOMEM;
     return MB_ERR_DEVICE;
-}
-
-template <typename T>
-void upload_tables(mb_grid* g, std::vector<T>& tw, std::vector<T>& ds,
-                   std::vector<T>& d2) {
-    const int L = g->L;
-    const double h = g->d.h;
-    tw.resize(2 * L);
-    ds.resize(2 * L);
-    d2.resize(L);
-    for (int k = 0; k < L; ++k) {
-        const double ang = 2.0 * M_PI * (double)k / (double)L;
-        tw[2 * k] = (T)std::cos(ang);
-        tw[2 * k + 1] = (T)(-std::sin(ang));
-        // divergence symbol (1 - e^{-i ang}) / h = (1 - cos ang + i sin ang) / h
-        // with 1 - cos = 2 sin^2(ang/2) to keep small modes accurate
-        const double sh = std::sin(0.5 * ang);
-        ds[2 * k] = (T)(2.0 * sh * sh / h);
-        ds[2 * k + 1] = (T)(std::sin(ang) / h);
-        d2[k] = (T)(4.0 * sh * sh / (h * h));
-    }
 }
 
 // Tile geometry of a box of edge L cut into tiles of tx x ty x tz cells.
@@ -116,36 +97,140 @@ Tiles make_box_tiles(int L, const Tiles& t) {
     return make_tiles(L, t.nbox, sx, sy, sz);
 }
 
-// (Re)allocates the scratch indexed by tile for g->tiles: counts (zeroed),
-// offsets, scan block sums, diagnostics partials (zeroed) and the spread
-// boxes.  The caller has synchronised any work using the old buffers.
-hipError_t alloc_tile_buffers(mb_grid* g) {
-    void* old[] = {g->d_count, g->d_offs, g->d_bsum, g->d_tile_part, g->d_box};
-    for (void* p : old)
-        if (p) (void)hipFree(p);
-    g->d_count = g->d_offs = g->d_bsum = nullptr;
-    g->d_tile_part = nullptr;
-    g->d_box = nullptr;
-    const int64_t ntiles = (int64_t)g->tiles.n * g->tiles.nbox;
-    g->nscan = (int)((ntiles + 4095) / 4096);
-    hipError_t e = hipMalloc((void**)&g->d_count, (size_t)ntiles * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc((void**)&g->d_offs, (size_t)(ntiles + 1) * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc((void**)&g->d_bsum, (size_t)g->nscan * sizeof(int));
-    if (e == hipSuccess)
-        e = hipMalloc((void**)&g->d_tile_part, (size_t)ntiles * 4 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&g->d_box, box_elems(g->btiles) * g->fsz);
-    if (e == hipSuccess) e = hipMemset(g->d_count, 0, (size_t)ntiles * sizeof(int));
-    if (e == hipSuccess) e = hipMemset(g->d_tile_part, 0, (size_t)ntiles * 4 * sizeof(double));
-    return e;
+// Validity of a grid description (the checks of mb_grid_create).
+mb_status desc_status(const mb_grid_desc& d, int nbox) {
+    if (nbox < 1 || nbox > 65536) return MB_ERR_INVALID;
+    const mb_status ss = size_status(d.L);
+    if (ss != MB_OK) return ss;
+    if (d.precision != MB_FP64 && d.precision != MB_MIXED) return MB_ERR_INVALID;
+    if (d.mode != MB_UNSTEADY_CN && d.mode != MB_STEADY_STOKES) return MB_ERR_INVALID;
+    if (d.zero_mean != 0 && d.zero_mean != 1) return MB_ERR_INVALID;
+    if ((d.deterministic != 0 && d.deterministic != 1) ||
+        (d.check_finite != 0 && d.check_finite != 1) ||
+        (d.external_workspace != 0 && d.external_workspace != 1) || d.reserved != 0)
+        return MB_ERR_INVALID;
+    if (!(d.h > 0.0) || !std::isfinite(d.h)) return MB_ERR_INVALID;
+    if (!(d.dt > 0.0) || !std::isfinite(d.dt)) return MB_ERR_INVALID;
+    if (!(d.eta >= 0.0) || !std::isfinite(d.eta)) return MB_ERR_INVALID;
+    if (d.mode == MB_UNSTEADY_CN && (!(d.rho > 0.0) || !std::isfinite(d.rho)))
+        return MB_ERR_INVALID;
+    if (d.mode == MB_STEADY_STOKES && !(d.eta > 0.0)) return MB_ERR_INVALID;
+    if (d.max_blobs < 0 || d.max_blobs > (int64_t)1 << 30) return MB_ERR_INVALID;
+    const int64_t N = (int64_t)d.L * d.L * d.L;
+    if ((N / 512) * nbox + 1 > ((int64_t)1 << 30) || 3 * N * nbox > ((int64_t)1 << 40))
+        return MB_ERR_INVALID;
+    return MB_OK;
+}
+
+// The default tiles of a box of edge L: 16 x 8 x 8 cells, 8 x 8 x 8 when 16
+// does not divide L (mb_grid_set_tiles and mb_grid_autotune choose others).
+Tiles default_tiles(int L, int nbox) {
+    return make_tiles(L, nbox, (L % 16 == 0) ? 16 : 8, 8, 8);
+}
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The grid's scratch as regions of one workspace, each 256-byte aligned, in
+// this order: FFT tables (twiddles, divergence symbol, |symbol|^2), the
+// spectrum, the x-pass partial sums, the per-tile arrays (counts, offsets,
+// scan block sums, diagnostics partials) and the spread boxes, both sized
+// for the tile shape of L with the most tiles / box entries, the per-blob
+// arrays (tile, rank, sorted blob, records, velocities), the springs
+// blocks' force sums and the non-finite flag.
+struct WsLayout {
+    enum { TW, DSYM, D2, SPEC, PSUM, COUNT, OFFS, BSUM, TPART, BOX, TILE, RANK, PERM,
+           REC, U, FPART, FLAG, NREG };
+    size_t off[NREG];
+    size_t total;
+    int ntiles_cap;  // tiles per box
+    int nscan;       // scan blocks over ntiles_cap * nbox tiles
+};
+
+WsLayout ws_layout(const mb_grid_desc& d, int nbox) {
+    WsLayout w{};
+    const int L = d.L;
+    const size_t fsz = d.precision == MB_MIXED ? 4 : 8;
+    const size_t NC = (size_t)L / 2 + 1;
+    const int64_t cap = std::max<int64_t>(d.max_blobs, 1);
+    int ntiles = 0;
+    size_t boxe = 0;
+#define MB_SHAPE(X, Y, Z)                                                        \
+    if (L % X == 0 && L % Y == 0 && L % Z == 0) {                                \
+        const Tiles t = make_tiles(L, nbox, X, Y, Z);                            \
+        ntiles = std::max(ntiles, t.n);                                          \
+        boxe = std::max(boxe, box_elems(make_box_tiles(L, t)));                  \
+    }
+    MB_TILE_SHAPES(MB_SHAPE)
+#undef MB_SHAPE
+    const int64_t nt = (int64_t)ntiles * nbox;
+    w.ntiles_cap = ntiles;
+    w.nscan = (int)((nt + 4095) / 4096);
+    size_t sz[WsLayout::NREG];
+    sz[WsLayout::TW] = (size_t)L * 2 * fsz;
+    sz[WsLayout::DSYM] = (size_t)L * 2 * fsz;
+    sz[WsLayout::D2] = (size_t)L * fsz;
+    sz[WsLayout::SPEC] = (size_t)nbox * 3 * L * L * NC * 2 * fsz;
+    sz[WsLayout::PSUM] = (size_t)nbox * fft_x_blocks(L, d.precision) * 2 * sizeof(double);
+    sz[WsLayout::COUNT] = (size_t)nt * sizeof(int);
+    sz[WsLayout::OFFS] = (size_t)(nt + 1) * sizeof(int);
+    sz[WsLayout::BSUM] = (size_t)w.nscan * sizeof(int);
+    sz[WsLayout::TPART] = (size_t)nt * 4 * sizeof(double);
+    sz[WsLayout::BOX] = boxe * fsz;
+    sz[WsLayout::TILE] = (size_t)cap * sizeof(int);
+    sz[WsLayout::RANK] = (size_t)cap * sizeof(int);
+    sz[WsLayout::PERM] = (size_t)cap * sizeof(int);
+    sz[WsLayout::REC] = (size_t)cap * record_size(d.precision);
+    sz[WsLayout::U] = (size_t)cap * 3 * sizeof(double);
+    sz[WsLayout::FPART] = (size_t)cap * 3 * sizeof(double);  // one springs block per blob at most
+    sz[WsLayout::FLAG] = sizeof(int);
+    size_t o = 0;
+    for (int r = 0; r < WsLayout::NREG; ++r) {
+        w.off[r] = o;
+        o += up256(sz[r]);
+    }
+    w.total = o;
+    return w;
+}
+
+// Points the grid's scratch pointers into workspace `base` (layout of the
+// grid's description and box count).
+void ws_bind(mb_grid* g, void* base) {
+    const WsLayout w = ws_layout(g->d, g->tiles.nbox);
+    char* b = (char*)base;
+    g->ws = base;
+    g->ws_bytes = w.total;
+    g->ntiles_cap = w.ntiles_cap;
+    g->nscan = w.nscan;
+    g->d_tw = b + w.off[WsLayout::TW];
+    g->d_dsym = b + w.off[WsLayout::DSYM];
+    g->d_d2 = b + w.off[WsLayout::D2];
+    g->d_spec = b + w.off[WsLayout::SPEC];
+    g->d_psum = (double*)(b + w.off[WsLayout::PSUM]);
+    g->d_count = (int*)(b + w.off[WsLayout::COUNT]);
+    g->d_offs = (int*)(b + w.off[WsLayout::OFFS]);
+    g->d_bsum = (int*)(b + w.off[WsLayout::BSUM]);
+    g->d_tile_part = (double*)(b + w.off[WsLayout::TPART]);
+    g->d_box = b + w.off[WsLayout::BOX];
+    g->d_tile = (int*)(b + w.off[WsLayout::TILE]);
+    g->d_rank = (int*)(b + w.off[WsLayout::RANK]);
+    g->d_perm = (int*)(b + w.off[WsLayout::PERM]);
+    g->d_rec = b + w.off[WsLayout::REC];
+    g->d_u = (double*)(b + w.off[WsLayout::U]);
+    g->d_force_part = (double*)(b + w.off[WsLayout::FPART]);
+    g->d_flag = (int*)(b + w.off[WsLayout::FLAG]);
+    g->perm_m = -1;
+}
+
+// Scan blocks for the current tiles (at most the workspace's).
+void set_scan_blocks(mb_grid* g) {
+    const int64_t nt = (int64_t)g->tiles.n * g->tiles.nbox;
+    g->nscan = (int)((nt + 4095) / 4096);
 }
 
 void free_grid(mb_grid* g) {
     if (!g) return;
-    void* ptrs[] = {g->d_tw,    g->d_dsym,  g->d_d2,   g->d_spec,
-                    g->d_psum,  g->d_count, g->d_offs, g->d_bsum,
-                    g->d_rank,  g->d_perm,  g->d_rec,  g->d_tile_part,
-                    g->d_force_part, g->d_box, g->d_u, g->d_tile, g->d_adj,
-                    g->d_ffield, g->d_mid};
+    if (g->ws_owned && g->ws) (void)hipFree(g->ws);
+    void* ptrs[] = {g->d_adj, g->d_adj_part, g->d_ffield, g->d_mid};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& tp : g->pending) {
@@ -156,14 +241,30 @@ void free_grid(mb_grid* g) {
     delete g;
 }
 
-bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+// Device buffers passed to the library are 256-byte aligned (null passes).
+bool aligned(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
+// Makes the grid's device current; the grid must have its workspace.
 mb_status enter(mb_grid* g) {
+    if (!g->ws) return MB_ERR_INVALID;
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
     if (cur != g->device && hipSetDevice(g->device) != hipSuccess)
         return MB_ERR_DEVICE;
     return MB_OK;
+}
+
+// Result of a call whose launches gave e: with check_finite, waits for the
+// stream and reports (then clears) the non-finite flag its kernels set.
+mb_status finish(mb_grid* g, hipError_t e, hipStream_t s) {
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
+    if (!g->d.check_finite) return MB_OK;
+    int flag = 0;
+    e = hipMemcpyAsync(&flag, g->d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && flag) e = zero_words(g->d_flag, 1, s);
+    if (e != hipSuccess) return MB_ERR_DEVICE;
+    return flag ? MB_ERR_NONFINITE : MB_OK;
 }
 
 SpringsDev springs_dev(const mb_springs* sp) {
@@ -184,32 +285,22 @@ SpringsDev springs_dev(const mb_springs* sp) {
 
 namespace mb {
 
-void timer_begin(mb_grid* g, int id, hipStream_t s, hipEvent_t* ev) {
-    *ev = nullptr;
-    if (!g || !((g->timing >> id) & 1u)) return;
-    hipEvent_t e;
-    if (!g->free_events.empty()) {
-        e = g->free_events.back();
-        g->free_events.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-        return;
+bool timer_pair(mb_grid* g, int id, hipEvent_t* start, hipEvent_t* stop) {
+    if (!g || !((g->timing >> id) & 1u)) return false;
+    hipEvent_t ev[2];
+    for (int k = 0; k < 2; ++k) {
+        if (!g->free_events.empty()) {
+            ev[k] = g->free_events.back();
+            g->free_events.pop_back();
+        } else if (hipEventCreate(&ev[k]) != hipSuccess) {
+            if (k == 1) g->free_events.push_back(ev[0]);
+            return false;
+        }
     }
-    (void)hipEventRecord(e, s);
-    *ev = e;
-}
-
-void timer_end(mb_grid* g, int id, hipStream_t s, hipEvent_t ev) {
-    if (!g || !((g->timing >> id) & 1u) || !ev) return;
-    hipEvent_t e;
-    if (!g->free_events.empty()) {
-        e = g->free_events.back();
-        g->free_events.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-        g->free_events.push_back(ev);
-        return;
-    }
-    (void)hipEventRecord(e, s);
-    g->pending.push_back(TimerPair{ev, e, id});
+    g->pending.push_back(TimerPair{ev[0], ev[1], id});
+    *start = ev[0];
+    *stop = ev[1];
+    return true;
 }
 
 }  // namespace mb
@@ -223,6 +314,7 @@ const char* mb_status_string(mb_status st) {
         case MB_ERR_UNSUPPORTED: return "unsupported configuration";
         case MB_ERR_NOMEM: return "out of device memory";
         case MB_ERR_DEVICE: return "no usable GPU or device error";
+        case MB_ERR_NONFINITE: return "non-finite blob position or force";
     }
     return "unknown status";
 }
@@ -239,19 +331,10 @@ mb_status mb_grid_create(const mb_grid_desc* desc, mb_grid** out) {
 mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox, mb_grid** out) {
     if (!out) return MB_ERR_INVALID;
     *out = nullptr;
-    if (!desc || nbox < 1 || nbox > 65536) return MB_ERR_INVALID;
+    if (!desc) return MB_ERR_INVALID;
     const mb_grid_desc d = *desc;
-    if (!size_ok(d.L)) return MB_ERR_INVALID;
-    if (d.precision != MB_FP64 && d.precision != MB_MIXED) return MB_ERR_INVALID;
-    if (d.mode != MB_UNSTEADY_CN && d.mode != MB_STEADY_STOKES) return MB_ERR_INVALID;
-    if (d.zero_mean != 0 && d.zero_mean != 1) return MB_ERR_INVALID;
-    if (!(d.h > 0.0) || !std::isfinite(d.h)) return MB_ERR_INVALID;
-    if (!(d.dt > 0.0) || !std::isfinite(d.dt)) return MB_ERR_INVALID;
-    if (!(d.eta >= 0.0) || !std::isfinite(d.eta)) return MB_ERR_INVALID;
-    if (d.mode == MB_UNSTEADY_CN && (!(d.rho > 0.0) || !std::isfinite(d.rho)))
-        return MB_ERR_INVALID;
-    if (d.mode == MB_STEADY_STOKES && !(d.eta > 0.0)) return MB_ERR_INVALID;
-    if (d.max_blobs < 0 || d.max_blobs > (int64_t)1 << 30) return MB_ERR_INVALID;
+    const mb_status ds = desc_status(d, nbox);
+    if (ds != MB_OK) return ds;
     int dev = 0;
     if (!device_ok(&dev)) return MB_ERR_DEVICE;
 
@@ -263,57 +346,27 @@ mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox, mb_grid**
     g->NC = d.L / 2 + 1;
     g->N = (int64_t)d.L * d.L * d.L;
     g->fsz = d.precision == MB_MIXED ? 4 : 8;
-    const int L = d.L;
-    g->nblk_x = fft_x_blocks(L, d.precision);
-    // tiles: x extent 16 or 8 (dividing L), y and z extent 8 (mb_grid_set_tiles
-    // and mb_grid_autotune choose others)
-    const Tiles t = make_tiles(L, nbox, (L % 16 == 0) ? 16 : 8, 8, 8);
-    g->tiles = t;
-    g->btiles = make_box_tiles(L, t);
+    g->nblk_x = fft_x_blocks(d.L, d.precision);
+    g->tiles = default_tiles(d.L, nbox);
+    g->btiles = make_box_tiles(d.L, g->tiles);
     g->rec_size = record_size(d.precision);
     // springs blocks hold at least one particle of at least one blob
     g->force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
-    const int64_t ntiles = (int64_t)t.n * nbox;
-    if (ntiles + 1 > ((int64_t)1 << 30) || (int64_t)3 * g->N * nbox > ((int64_t)1 << 40)) {
-        delete g;
-        return MB_ERR_INVALID;
-    }
     g->perm_m = -1;
-
-    const size_t cbytes = 2 * g->fsz;
-    hipError_t e = hipSuccess;
-    auto alloc = [&](void** p, size_t bytes) {
-        if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 16);
-    };
-    alloc(&g->d_tw, (size_t)L * cbytes);
-    alloc(&g->d_dsym, (size_t)L * cbytes);
-    alloc(&g->d_d2, (size_t)L * g->fsz);
-    alloc(&g->d_spec, (size_t)nbox * 3 * L * L * g->NC * cbytes);
-    alloc((void**)&g->d_psum, (size_t)nbox * g->nblk_x * 2 * sizeof(double));
-    if (e == hipSuccess) e = alloc_tile_buffers(g);
-    alloc((void**)&g->d_tile, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
-    alloc((void**)&g->d_rank, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
-    alloc((void**)&g->d_perm, (size_t)std::max<int64_t>(d.max_blobs, 1) * sizeof(int));
-    alloc(&g->d_rec, (size_t)std::max<int64_t>(d.max_blobs, 1) * g->rec_size);
-    alloc((void**)&g->d_u, (size_t)std::max<int64_t>(d.max_blobs, 1) * 3 * sizeof(double));
-    alloc((void**)&g->d_force_part, (size_t)g->force_blocks_cap * 3 * sizeof(double));
-    if (e == hipSuccess) e = hipMemset(g->d_force_part, 0, (size_t)g->force_blocks_cap * 3 * sizeof(double));
-    if (e == hipSuccess) {
-        if (d.precision == MB_MIXED) {
-            std::vector<float> tw, ds, d2;
-            upload_tables<float>(g, tw, ds, d2);
-            e = hipMemcpy(g->d_tw, tw.data(), tw.size() * 4, hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = hipMemcpy(g->d_dsym, ds.data(), ds.size() * 4, hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = hipMemcpy(g->d_d2, d2.data(), d2.size() * 4, hipMemcpyHostToDevice);
-        } else {
-            std::vector<double> tw, ds, d2;
-            upload_tables<double>(g, tw, ds, d2);
-            e = hipMemcpy(g->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = hipMemcpy(g->d_dsym, ds.data(), ds.size() * 8, hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = hipMemcpy(g->d_d2, d2.data(), d2.size() * 8, hipMemcpyHostToDevice);
-        }
+    if (d.external_workspace) {
+        *out = g;  // no scratch until mb_grid_set_workspace
+        return MB_OK;
     }
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    const size_t bytes = ws_layout(d, nbox).total;
+    void* ws = nullptr;
+    hipError_t e = hipMalloc(&ws, bytes);
+    if (e == hipSuccess) {
+        g->ws_owned = true;
+        ws_bind(g, ws);
+        set_scan_blocks(g);
+        e = init_workspace(g, nullptr);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_grid(g);
@@ -323,14 +376,52 @@ mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox, mb_grid**
     return MB_OK;
 }
 
+size_t mb_workspace_size(const mb_grid_desc* desc, int32_t nbox) {
+    if (!desc || desc_status(*desc, nbox) != MB_OK) return 0;
+    return ws_layout(*desc, nbox).total;
+}
+
+mb_status mb_grid_set_workspace(mb_grid* g, void* ptr, size_t bytes) {
+    if (!g || !ptr || !aligned(ptr)) return MB_ERR_INVALID;
+    const size_t need = ws_layout(g->d, g->tiles.nbox).total;
+    if (bytes < need) return MB_ERR_INVALID;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
+    if (cur != g->device && hipSetDevice(g->device) != hipSuccess) return MB_ERR_DEVICE;
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.device != g->device ||
+        attr.type == hipMemoryTypeHost) {
+        (void)hipGetLastError();
+        if (cur >= 0 && cur != g->device) (void)hipSetDevice(cur);
+        return MB_ERR_INVALID;
+    }
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) {
+        if (g->ws_owned && g->ws) (void)hipFree(g->ws);
+        g->ws_owned = false;
+        ws_bind(g, ptr);
+        set_scan_blocks(g);
+        e = init_workspace(g, nullptr);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (cur >= 0 && cur != g->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        g->ws = nullptr;  // unusable until a workspace is set again
+        return from_hip(e);
+    }
+    return MB_OK;
+}
+
 mb_status mb_grid_destroy(mb_grid* g) {
     if (!g) return MB_OK;
+    const int dev = g->device;
     int cur = -1;
     (void)hipGetDevice(&cur);
-    if (cur != g->device) (void)hipSetDevice(g->device);
+    if (cur != dev) (void)hipSetDevice(dev);
     (void)hipDeviceSynchronize();
     free_grid(g);
-    if (cur >= 0 && cur != g->device) (void)hipSetDevice(cur);
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
     return MB_OK;
 }
 
@@ -415,12 +506,30 @@ mb_status mb_springs_destroy(mb_springs* sp) {
     return MB_OK;
 }
 
+mb_status mb_springs_set_params(mb_springs* sp, const double* r0, double k, void* stream) {
+    if (!sp || (sp->npairs > 0 && !r0)) return MB_ERR_INVALID;
+    if (!(k >= 0.0) || !std::isfinite(k)) return MB_ERR_INVALID;
+    for (int e = 0; e < sp->npairs; ++e)
+        if (!(r0[e] > 0.0) || !std::isfinite(r0[e])) return MB_ERR_INVALID;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
+    if (cur != sp->device && hipSetDevice(sp->device) != hipSuccess) return MB_ERR_DEVICE;
+    hipError_t e = hipSuccess;
+    if (sp->npairs > 0)
+        e = hipMemcpyAsync(sp->d_r0, r0, (size_t)sp->npairs * sizeof(double),
+                           hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (cur >= 0 && cur != sp->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return from_hip(e);
+    sp->k = k;
+    return MB_OK;
+}
+
 mb_status mb_spread(mb_grid* g, int64_t M, const double* q, const double* F,
                     void* f_out, void* stream) {
     if (!g || !f_out || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
     if (M % g->tiles.nbox) return MB_ERR_INVALID;  // the same number of blobs per box
-    if (M > 0 && (!q || !F || !aligned8(q) || !aligned8(F))) return MB_ERR_INVALID;
-    if (!aligned8(f_out) && g->fsz == 8) return MB_ERR_INVALID;
+    if (M > 0 && (!q || !F || !aligned(q) || !aligned(F))) return MB_ERR_INVALID;
+    if (!aligned(f_out)) return MB_ERR_INVALID;
     mb_status st = enter(g);
     if (st != MB_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -436,14 +545,15 @@ mb_status mb_spread(mb_grid* g, int64_t M, const double* q, const double* F,
         if (e == hipSuccess) e = spread_boxes<double>(g, s);
         if (e == hipSuccess) e = fold_boxes<double>(g, (double*)f_out, s);
     }
-    return from_hip(e);
+    return finish(g, e, s);
 }
 
 mb_status mb_interpolate(mb_grid* g, int64_t M, const double* q, const void* v,
                          double* u_out, void* stream) {
     if (!g || !v || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
     if (M % g->tiles.nbox) return MB_ERR_INVALID;
-    if (M > 0 && (!q || !u_out || !aligned8(q) || !aligned8(u_out))) return MB_ERR_INVALID;
+    if (M > 0 && (!q || !u_out || !aligned(q) || !aligned(u_out))) return MB_ERR_INVALID;
+    if (!aligned(v)) return MB_ERR_INVALID;
     mb_status st = enter(g);
     if (st != MB_OK) return st;
     if (M == 0) return MB_OK;
@@ -458,7 +568,7 @@ mb_status mb_interpolate(mb_grid* g, int64_t M, const double* q, const void* v,
         if (e == hipSuccess) e = scatter_records<double>(g, M, q, nullptr, s);
         if (e == hipSuccess) e = interpolate<double>(g, M, (const double*)v, u_out, nullptr, 0, s);
     }
-    return from_hip(e);
+    return finish(g, e, s);
 }
 
 mb_status mb_fluid_solve(mb_grid* g, const void* v_in, const void* f,
@@ -466,6 +576,7 @@ mb_status mb_fluid_solve(mb_grid* g, const void* v_in, const void* f,
     if (!g || !f || !v_out) return MB_ERR_INVALID;
     const bool steady = g->d.mode == MB_STEADY_STOKES;
     if (!steady && !v_in) return MB_ERR_INVALID;
+    if (!aligned(v_in) || !aligned(f) || !aligned(v_out)) return MB_ERR_INVALID;
     if (!v_in) v_in = v_out;  // unread in steady mode
     mb_status st = enter(g);
     if (st != MB_OK) return st;
@@ -481,7 +592,8 @@ mb_status mb_fluid_solve(mb_grid* g, const void* v_in, const void* f,
 mb_status mb_spring_forces(const mb_springs* sp, int64_t P, const double* q,
                            const double* Fext, double* F_out, void* stream) {
     if (!sp || P < 0) return MB_ERR_INVALID;
-    if (P > 0 && (!q || !F_out || !aligned8(q) || !aligned8(F_out))) return MB_ERR_INVALID;
+    if (P > 0 && (!q || !F_out || !aligned(q) || !aligned(F_out))) return MB_ERR_INVALID;
+    if (!aligned(Fext)) return MB_ERR_INVALID;
     if ((int64_t)P * sp->nb > ((int64_t)1 << 31) - 1) return MB_ERR_INVALID;
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
@@ -556,16 +668,23 @@ static hipError_t alloc_lazy(void** p, size_t bytes) {
     return e;
 }
 
+// Steps of one grid; check: report the non-finite flag at the end (false
+// inside a graph capture, where the caller checks after the replays).
 static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
                            void* v, const double* Fext, const double* Gblob,
                            double* u_out, double* U0_out, double* diag_out,
-                           int32_t nsteps, void* stream, const void* ffluid = nullptr) {
+                           int32_t nsteps, void* stream, const void* ffluid = nullptr,
+                           bool check = true) {
     if (!g || !sp || !v || P < 0 || nsteps < 0) return MB_ERR_INVALID;
     const int64_t M = P * sp->nb;
     if (M > g->d.max_blobs) return MB_ERR_INVALID;
     if (P % g->tiles.nbox) return MB_ERR_INVALID;  // the same particles per box
-    if (M > 0 && (!q || !aligned8(q))) return MB_ERR_INVALID;
+    if (M > 0 && !q) return MB_ERR_INVALID;
+    if (!aligned(q) || !aligned(v) || !aligned(Fext) || !aligned(Gblob) || !aligned(u_out) ||
+        !aligned(U0_out) || !aligned(diag_out) || !aligned(ffluid))
+        return MB_ERR_INVALID;
     if (sp->device != g->device) return MB_ERR_INVALID;
+    if (g->scheme == MB_SCHEME_MIDPOINT && !g->d_mid) return MB_ERR_INVALID;
     mb_status st = enter(g);
     if (st != MB_OK) return st;
     if (nsteps == 0) return MB_OK;
@@ -574,13 +693,10 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
     const int fb = springs_blocks(sd, P);
     hipError_t e = hipSuccess;
     if (ffluid) e = alloc_lazy(&g->d_ffield, (size_t)3 * g->N * g->tiles.nbox * g->fsz);
-    if (e == hipSuccess && g->scheme == MB_SCHEME_MIDPOINT)
-        e = alloc_lazy((void**)&g->d_mid,
-                       (size_t)6 * std::max<int64_t>(g->d.max_blobs, 1) * sizeof(double));
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
     if (M == 0 && diag_out) {
         // no blobs: the force partials of the diagnostics are zero
-        e = hipMemsetAsync(g->d_force_part, 0, 3 * sizeof(double), s);
+        e = zero_words(g->d_force_part, 3 * 2, s);
         if (e != hipSuccess) return from_hip(e);
     }
     // first-order steps after the first of the call take their binning from
@@ -600,14 +716,14 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
             e = step_once<double>(g, sd, P, M, q, (double*)v, Fext, Gblob,
                                   (const double*)ffluid, u_dst, s, binned, bin_next, diag);
         if (!last && e != hipSuccess && bin_next)
-            (void)hipMemsetAsync(g->d_count, 0,
-                                 sizeof(int) * (size_t)g->tiles.n * g->tiles.nbox, s);
+            (void)zero_words(g->d_count, (size_t)g->tiles.n * g->tiles.nbox, s);
         if (last && e == hipSuccess && U0_out)
             e = particle_means(g, P, sp->nb, u_dst, U0_out, s);
         if (last && e == hipSuccess && diag_out)
             e = diagnostics(g, M > 0 ? fb : 1, diag_out, s);
     }
-    return from_hip(e);
+    if (!check) return from_hip(e);
+    return finish(g, e, s);
 }
 
 mb_status mb_step(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
@@ -621,7 +737,6 @@ mb_status mb_step_ext(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
                       void* v, const double* Fext, const double* F_blob,
                       double* u_out, double* U0_out, double* diag_out,
                       int32_t nsteps, void* stream) {
-    if (F_blob && !aligned8(F_blob)) return MB_ERR_INVALID;
     return step_impl(g, sp, P, q, v, Fext, F_blob, u_out, U0_out, diag_out, nsteps,
                      stream);
 }
@@ -630,8 +745,7 @@ mb_status mb_step_forced(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
                          void* v, const double* Fext, const double* F_blob,
                          const void* f_fluid, double* u_out, double* U0_out,
                          double* diag_out, int32_t nsteps, void* stream) {
-    if (F_blob && !aligned8(F_blob)) return MB_ERR_INVALID;
-    if (!f_fluid || ((uintptr_t)f_fluid & (g ? g->fsz - 1 : 7))) return MB_ERR_INVALID;
+    if (!f_fluid) return MB_ERR_INVALID;
     return step_impl(g, sp, P, q, v, Fext, F_blob, u_out, U0_out, diag_out, nsteps,
                      stream, f_fluid);
 }
@@ -648,21 +762,35 @@ mb_status mb_step_graph(int32_t ngrids, mb_grid* const* grids,
         if (!g || !sp || !v[i] || nparticles[i] < 0) return MB_ERR_INVALID;
         const int64_t M = nparticles[i] * sp->nb;
         if (M > g->d.max_blobs || nparticles[i] % g->tiles.nbox) return MB_ERR_INVALID;
-        if (M > 0 && (!q[i] || !aligned8(q[i]))) return MB_ERR_INVALID;
-        if (F_blob && F_blob[i] && !aligned8(F_blob[i])) return MB_ERR_INVALID;
+        if (M > 0 && !q[i]) return MB_ERR_INVALID;
+        if (!aligned(q[i]) || !aligned(v[i]) || (F_blob && !aligned(F_blob[i])) ||
+            (Fext && !aligned(Fext[i])))
+            return MB_ERR_INVALID;
         if (sp->device != g->device || g->device != grids[0]->device) return MB_ERR_INVALID;
+        if (!g->ws) return MB_ERR_INVALID;
+        if (g->scheme == MB_SCHEME_MIDPOINT && !g->d_mid) return MB_ERR_INVALID;
     }
     mb_status st = enter(grids[0]);
     if (st != MB_OK) return st;
     if (nsteps == 0) return MB_OK;
+    // the non-finite checks of the grids that ask for them are read once,
+    // after the last step
     auto one_step = [&](hipStream_t s) -> mb_status {
         for (int i = 0; i < ngrids; ++i) {
             mb_status r = step_impl(grids[i], springs[i], nparticles[i], q[i], v[i],
                                     Fext ? Fext[i] : nullptr, F_blob ? F_blob[i] : nullptr,
-                                    nullptr, nullptr, nullptr, 1, (void*)s);
+                                    nullptr, nullptr, nullptr, 1, (void*)s, nullptr, false);
             if (r != MB_OK) return r;
         }
         return MB_OK;
+    };
+    auto check_all = [&](hipError_t e) -> mb_status {
+        mb_status r = MB_OK;
+        for (int i = 0; i < ngrids; ++i) {
+            const mb_status ri = finish(grids[i], e, (hipStream_t)stream);
+            if (r == MB_OK) r = ri;
+        }
+        return r;
     };
     hipStream_t caller = (hipStream_t)stream;
     int done = 0;
@@ -676,7 +804,7 @@ mb_status mb_step_graph(int32_t ngrids, mb_grid* const* grids,
         if (st != MB_OK) return st;
         done = 1;
     }
-    if (done == nsteps) return MB_OK;
+    if (done == nsteps) return check_all(hipSuccess);
     hipStream_t cs = nullptr;
     hipEvent_t ev = nullptr;
     hipGraph_t graph = nullptr;
@@ -706,15 +834,16 @@ mb_status mb_step_graph(int32_t ngrids, mb_grid* const* grids,
     if (ev) (void)hipEventDestroy(ev);
     if (cs) (void)hipStreamDestroy(cs);
     if (st != MB_OK) return st;
-    return from_hip(e);
+    return check_all(e);
 }
 
 mb_status mb_spring_forces_ext(const mb_springs* sp, int64_t P, const double* q,
                                const double* Fext, const double* F_blob, double* F_out,
                                void* stream) {
     if (!sp || P < 0) return MB_ERR_INVALID;
-    if (P > 0 && (!q || !F_out || !aligned8(q) || !aligned8(F_out))) return MB_ERR_INVALID;
-    if (F_blob && !aligned8(F_blob)) return MB_ERR_INVALID;
+    if (P > 0 && (!q || !F_out)) return MB_ERR_INVALID;
+    if (!aligned(q) || !aligned(F_out) || !aligned(Fext) || !aligned(F_blob))
+        return MB_ERR_INVALID;
     if ((int64_t)P * sp->nb > ((int64_t)1 << 31) - 1) return MB_ERR_INVALID;
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
@@ -727,8 +856,8 @@ mb_status mb_interpolate_grad(mb_grid* g, int64_t M, const double* q, const void
                               const double* W, double* g_inout, void* stream) {
     if (!g || !v || M < 0 || M > g->d.max_blobs) return MB_ERR_INVALID;
     if (M % g->tiles.nbox) return MB_ERR_INVALID;
-    if (M > 0 && (!q || !W || !g_inout || !aligned8(q) || !aligned8(W) || !aligned8(g_inout)))
-        return MB_ERR_INVALID;
+    if (M > 0 && (!q || !W || !g_inout)) return MB_ERR_INVALID;
+    if (!aligned(q) || !aligned(W) || !aligned(g_inout) || !aligned(v)) return MB_ERR_INVALID;
     mb_status st = enter(g);
     if (st != MB_OK) return st;
     if (M == 0) return MB_OK;
@@ -744,16 +873,16 @@ mb_status mb_interpolate_grad(mb_grid* g, int64_t M, const double* q, const void
         if (e == hipSuccess)
             e = interpolate_grad<double>(g, (const double*)v, W, 1.0, g_inout, s);
     }
-    return from_hip(e);
+    return finish(g, e, s);
 }
 
 mb_status mb_spring_adjoint(const mb_springs* sp, int64_t P, const double* q,
                             const double* Fbar, double* qbar, double* kbar, double* r0bar,
                             void* stream) {
     if (!sp || P < 0) return MB_ERR_INVALID;
-    if (P > 0 && (!q || !Fbar || !qbar || !aligned8(q) || !aligned8(Fbar) || !aligned8(qbar)))
+    if (P > 0 && (!q || !Fbar || !qbar)) return MB_ERR_INVALID;
+    if (!aligned(q) || !aligned(Fbar) || !aligned(qbar) || !aligned(kbar) || !aligned(r0bar))
         return MB_ERR_INVALID;
-    if ((kbar && !aligned8(kbar)) || (r0bar && !aligned8(r0bar))) return MB_ERR_INVALID;
     if ((int64_t)P * sp->nb > ((int64_t)1 << 31) - 1) return MB_ERR_INVALID;
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
@@ -771,10 +900,10 @@ mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const dou
     const int64_t M = P * sp->nb;
     if (M > g->d.max_blobs) return MB_ERR_INVALID;
     if (P % g->tiles.nbox) return MB_ERR_INVALID;
-    if (M > 0 && (!q_n || !qbar || !aligned8(q_n) || !aligned8(qbar))) return MB_ERR_INVALID;
-    if ((F_blob && !aligned8(F_blob)) || (ubar_loss && !aligned8(ubar_loss)) ||
-        (Fblob_bar && !aligned8(Fblob_bar)) || (kbar && !aligned8(kbar)) ||
-        (r0bar && !aligned8(r0bar)) || !aligned8(v_np1) || !aligned8(vbar))
+    if (M > 0 && (!q_n || !qbar)) return MB_ERR_INVALID;
+    if (!aligned(q_n) || !aligned(qbar) || !aligned(Fext) || !aligned(F_blob) ||
+        !aligned(ubar_loss) || !aligned(Fblob_bar) || !aligned(kbar) || !aligned(r0bar) ||
+        !aligned(v_np1) || !aligned(vbar))
         return MB_ERR_INVALID;
     if (sp->device != g->device) return MB_ERR_INVALID;
     mb_status st = enter(g);
@@ -793,6 +922,24 @@ mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const dou
             g->d_adj = nullptr;
             return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
         }
+    }
+    // deterministic: per-block partial sums of kbar and r0bar, added in
+    // block order, instead of float64 atomics
+    double* part = nullptr;
+    if (g->d.deterministic && (kbar || r0bar) && M > 0) {
+        const size_t need = springs_adjoint_part_size(springs_dev(sp), P);
+        if (g->adj_part_cap < need) {
+            if (g->d_adj_part) (void)hipFree(g->d_adj_part);
+            g->d_adj_part = nullptr;
+            g->adj_part_cap = 0;
+            e = hipMalloc((void**)&g->d_adj_part, need * sizeof(double));
+            if (e != hipSuccess) {
+                g->d_adj_part = nullptr;
+                return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
+            }
+            g->adj_part_cap = need;
+        }
+        part = g->d_adj_part;
     }
     double* wbar = g->d_adj;
     double* fbar = wbar + nf;
@@ -819,7 +966,7 @@ mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const dou
     // commute; steady: vbar = 0)
     if (e == hipSuccess) e = fluid_solve<double>(g, zero, wbar, fbar, s);
     if (e == hipSuccess) {
-        if (g->d.mode == MB_STEADY_STOKES) e = hipMemsetAsync(vb, 0, nf * sizeof(double), s);
+        if (g->d.mode == MB_STEADY_STOKES) e = zero_words(vb, nf * 2, s);
         else e = apply_cn<double>(g, fbar, vb, s);
     }
     // F^n = springs(q^n) + Fext/nb + G
@@ -829,14 +976,29 @@ mb_status mb_step_adjoint(mb_grid* g, const mb_springs* sp, int64_t P, const dou
         e = interpolate<double>(g, M, fbar, Fbar, nullptr, 0, s, 1.0 / h3);
     if (e == hipSuccess && M > 0) e = interpolate_grad<double>(g, fbar, F, 1.0 / h3, qbar, s);
     // springs: qbar, kbar, r0bar; the blob forces: Fblob_bar += Fbar
-    if (e == hipSuccess) e = springs_adjoint(sd, P, q_n, Fbar, qbar, kbar, r0bar, s, g);
+    if (e == hipSuccess) e = springs_adjoint(sd, P, q_n, Fbar, qbar, kbar, r0bar, s, g, part);
     if (e == hipSuccess && Fblob_bar) e = blob_add(3 * M, Fbar, Fblob_bar, s);
-    return from_hip(e);
+    return finish(g, e, s);
 }
 
 mb_status mb_grid_set_scheme(mb_grid* g, int32_t scheme) {
     if (!g || (scheme != MB_SCHEME_EULER && scheme != MB_SCHEME_MIDPOINT))
         return MB_ERR_INVALID;
+    if (scheme == MB_SCHEME_MIDPOINT && !g->d_mid) {
+        // q* and the second half-velocity of every blob, allocated here so
+        // that no step (nor a graph capture of one) allocates
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return MB_ERR_DEVICE;
+        if (cur != g->device && hipSetDevice(g->device) != hipSuccess) return MB_ERR_DEVICE;
+        const hipError_t e = hipMalloc(
+            (void**)&g->d_mid, (size_t)6 * std::max<int64_t>(g->d.max_blobs, 1) * sizeof(double));
+        if (cur >= 0 && cur != g->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) {
+            g->d_mid = nullptr;
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
+        }
+    }
     g->scheme = scheme;
     return MB_OK;
 }
@@ -850,11 +1012,14 @@ static mb_status set_tiles(mb_grid* g, int tx, int ty, int tz) {
     if (g->tiles.tx == tx && g->tiles.ty == ty && g->tiles.tz == tz) return MB_OK;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return from_hip(e);
+    // the workspace holds the tile arrays and boxes of every shape of L;
+    // the counts start from zero under the new numbering
     g->tiles = make_tiles(g->L, g->tiles.nbox, tx, ty, tz);
     g->btiles = make_box_tiles(g->L, g->tiles);
-    e = alloc_tile_buffers(g);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : from_hip(e);
-    return MB_OK;
+    set_scan_blocks(g);
+    e = zero_words(g->d_count, (size_t)g->ntiles_cap * g->tiles.nbox, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    return from_hip(e);
 }
 
 mb_status mb_grid_set_tiles(mb_grid* g, int32_t tx, int32_t ty, int32_t tz) {
@@ -879,7 +1044,8 @@ mb_status mb_grid_autotune(mb_grid* g, const mb_springs* sp, int64_t P, const do
     const int64_t M = P * sp->nb;
     if (M > g->d.max_blobs || P % g->tiles.nbox || sp->device != g->device)
         return MB_ERR_INVALID;
-    if (M > 0 && (!q || !aligned8(q))) return MB_ERR_INVALID;
+    if (M > 0 && !q) return MB_ERR_INVALID;
+    if (!aligned(q) || !aligned(v) || !aligned(Fext)) return MB_ERR_INVALID;
     mb_status st = enter(g);
     if (st != MB_OK) return st;
     hipStream_t s = (hipStream_t)stream;

@@ -2,6 +2,7 @@
 // plans, tile geometry and the per-kernel timing hooks.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -92,6 +93,13 @@ struct mb_springs {
 struct mb_grid {
     mb_grid_desc d;
     int device;
+    // workspace: every O(N) and O(M) scratch buffer below (tables to force
+    // partials and the non-finite flag) lies in this one region
+    void* ws;           // null until a workspace is set (external_workspace)
+    size_t ws_bytes;
+    bool ws_owned;      // allocated by the library (freed at destroy)
+    int* d_flag;        // non-finite flag (check_finite)
+    int ntiles_cap;     // tiles per box the workspace holds (all shapes)
     int L, NC;          // cells per side, complex columns L/2 + 1
     int64_t N;          // L^3 (cells of one box)
     size_t fsz;         // bytes per scalar (8 or 4)
@@ -118,6 +126,8 @@ struct mb_grid {
     void* d_box;           // [3][tiles][box nodes] spread boxes of the step
     double* d_u;           // [max_blobs][3] blob velocities of the last step
     double* d_adj;         // reverse-step scratch (allocated on first use)
+    double* d_adj_part;    // per-block k / r0 derivative sums (deterministic)
+    size_t adj_part_cap;   // doubles in d_adj_part
     void* d_ffield;        // force field of forced steps (allocated on first use)
     double* d_mid;         // midpoint scheme: q* and a velocity per blob (first use)
     int scheme;            // mb_scheme of the steps
@@ -134,21 +144,31 @@ struct mb_grid {
 
 namespace mb {
 
-// Timer hooks around each launch (no-ops unless timing is enabled).
-void timer_begin(mb_grid* g, int id, hipStream_t s, hipEvent_t* ev);
-void timer_end(mb_grid* g, int id, hipStream_t s, hipEvent_t ev);
+// Timing of a launch of kernel `id` (when timing is enabled for it): two
+// events, queued for mb_grid_kernel_times, that the launch itself records
+// at its start and end (hipExtLaunchKernel), so the duration is the
+// kernel's execution without the gaps around it.  False: not timed.
+bool timer_pair(mb_grid* g, int id, hipEvent_t* start, hipEvent_t* stop);
 
-#define MB_LAUNCH(g, id, s, kern, grid, block, shm, ...)              \
-    do {                                                              \
-        hipEvent_t ev_ = nullptr;                                     \
-        ::mb::timer_begin((g), (id), (s), &ev_);                      \
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), (shm), (s), \
-                           __VA_ARGS__);                              \
-        ::mb::timer_end((g), (id), (s), ev_);                         \
+#define MB_LAUNCH(g, id, s, kern, grid, block, shm, ...)                          \
+    do {                                                                          \
+        hipEvent_t a_ = nullptr, b_ = nullptr;                                    \
+        if (::mb::timer_pair((g), (id), &a_, &b_))                                \
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), (shm), (s), a_, b_, \
+                                  0, __VA_ARGS__);                                \
+        else                                                                      \
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(block), (shm), (s),         \
+                               __VA_ARGS__);                                      \
     } while (0)
 
 // Blocks of an x pass of the FFT solve (one float64 partial sum pair each).
 int fft_x_blocks(int L, int precision);
+
+// Workspace set-up on stream s: the FFT twiddle and symbol tables (computed
+// on the device), zeroed tile counts, partial sums and non-finite flag.
+hipError_t init_workspace(mb_grid* g, hipStream_t s);
+// Zero n 32-bit words at p (a kernel, never a memset node in a graph).
+hipError_t zero_words(void* p, size_t n, hipStream_t s);
 
 // Launchers (templated on the field scalar type, float or double).  Each
 // returns hipSuccess or the launch error.
@@ -163,6 +183,8 @@ hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s,
 template <typename T>
 hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
                            const double* F, hipStream_t s, double fscale = 0.0);
+// Non-finite flag of the grid's checks (null unless check_finite).
+inline int* finite_flag(mb_grid* g) { return g->d.check_finite ? g->d_flag : nullptr; }
 // Springs and records; force_sums: also the per-block sums of the blob
 // forces read by the diagnostics.
 template <typename T>
@@ -176,7 +198,11 @@ hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
 // length parts.
 hipError_t springs_adjoint(const SpringsDev& sp, int64_t P, const double* q,
                            const double* Fbar, double* qbar, double* kbar,
-                           double* r0bar, hipStream_t s, mb_grid* timing_grid);
+                           double* r0bar, hipStream_t s, mb_grid* timing_grid,
+                           double* part = nullptr);
+// Doubles of per-block partial sums springs_adjoint writes to `part`
+// (then summed in block order) instead of its float64 atomics.
+size_t springs_adjoint_part_size(const SpringsDev& sp, int64_t P);
 // out = (a ? a : 0) + sc b; y += x (n doubles).
 hipError_t blob_axpy(int64_t n, const double* a, double sc, const double* b, double* out,
                      hipStream_t s);

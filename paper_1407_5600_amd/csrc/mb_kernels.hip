@@ -67,6 +67,9 @@ __device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
         double c = fl - floor(fl * invL) * Ld;
         if (c < 0.0) c += Ld;
         if (c >= Ld) c -= Ld;
+        // non-finite or beyond 2^53 cells: any in-range cell (such input
+        // has no meaningful result; no index may leave the grid)
+        if (!(c >= 0.0 && c < Ld)) c = 0.0;
         g.c[b] = (int)c;
         g.up[b] = s >= 0.5 ? 1 : 0;
         g.s[b] = s;
@@ -79,6 +82,13 @@ __device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
 __device__ __forceinline__ int tile_linear(const int c[3], const Tiles& tl) {
     return ((c[2] >> (__ffs(tl.tz) - 1)) * tl.nty + (c[1] >> (__ffs(tl.ty) - 1))) * tl.ntx +
            (c[0] >> (__ffs(tl.tx) - 1));
+}
+
+// 1 when any of the n values is NaN or infinite.
+__device__ __forceinline__ int nonfinite(const double* x, int n) {
+    int bad = 0;
+    for (int k = 0; k < n; ++k) bad |= !isfinite(x[k]);
+    return bad;
 }
 
 __device__ __forceinline__ uint32_t cell_pack(const Geom& g) {
@@ -239,7 +249,7 @@ k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
               int64_t M, double inv_h, int L, double inv_vol,
               const int* __restrict__ offs, const int* __restrict__ tile_of,
               const int* __restrict__ rank, RecG<T>* __restrict__ rec,
-              T* __restrict__ recf, int* __restrict__ perm) {
+              T* __restrict__ recf, int* __restrict__ perm, int* __restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (i >= M) return;
     const Geom g = blob_geom(q, i, inv_h, L);
@@ -249,6 +259,7 @@ k_bin_scatter(const double* __restrict__ q, const double* __restrict__ F,
         f[1] = F[3 * i + 1];
         f[2] = F[3 * i + 2];
     }
+    if (flag && (nonfinite(q + 3 * i, 3) | nonfinite(f, 3))) atomicOr(flag, 1);
     const int64_t pos = (int64_t)offs[tile_of[i]] + rank[i];
     write_record<T>(rec, F ? recf : nullptr, perm, pos, i, g, f, inv_vol);
 }
@@ -376,7 +387,7 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
                   double inv_vol, const int* __restrict__ offs,
                   const int* __restrict__ tile_of, const int* __restrict__ rank,
                   RecG<T>* __restrict__ rec, T* __restrict__ recf, int* __restrict__ perm,
-                  double* __restrict__ fpart) {
+                  double* __restrict__ fpart, int* __restrict__ flag) {
     extern __shared__ double smem[];
     __shared__ double red[16 * 3];
     const int64_t p0 = (int64_t)blockIdx.x * sp.ppb;
@@ -397,6 +408,8 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
     if (i >= 0) {
         const Geom g = blob_geom(B.qs, threadIdx.x, inv_h, L);
         write_record<T>(rec, recf, perm, (int64_t)off + rk, i, g, F, inv_vol);
+        if (flag && (nonfinite(B.qs + 3 * threadIdx.x, 3) | nonfinite(F, 3)))
+            atomicOr(flag, 1);
     }
     if (fpart) {  // (a kernel argument: uniform over the block)
         double tot[3] = {F[0], F[1], F[2]};
@@ -433,12 +446,16 @@ k_springs(SpringsDev sp, const double* __restrict__ q,
 // Per blob also kbar += Fbar_i . (1 - r0/|d|) d and r0bar_e += -k Fbar_i .
 // d/|d| (both ends of a pair together give the pair's full term); the block
 // sums these in LDS and adds them to kbar / r0bar with one float64 atomic
-// per entry (their order, hence the last bits, may vary run to run).
+// per entry (their order, hence the last bits, may vary run to run).  With
+// part (deterministic sums) the block instead writes its kbar sum and, per
+// pair e = (a, b), the sum over its particles of
+// -k (Fbar_a - Fbar_b) . d/|d| (d = q_b - q_a), in particle order, to
+// part[block][1 + npairs]; k_sum_parts adds the blocks in order.
 __global__ void __launch_bounds__(BLK)
 k_springs_adjoint(SpringsDev sp, const double* __restrict__ q,
                   const double* __restrict__ Fbar, int64_t P,
                   double* __restrict__ qbar, double* __restrict__ kbar,
-                  double* __restrict__ r0bar) {
+                  double* __restrict__ r0bar, double* __restrict__ part) {
     extern __shared__ double smem[];
     __shared__ double red[16];
     double fe[3];
@@ -479,7 +496,7 @@ k_springs_adjoint(SpringsDev sp, const double* __restrict__ q,
             gz += sc * lz + tc * dz * ld;
             const double fd = fx * dx + fy * dy + fz * dz;
             kb += fd * (1.0 - r0 / len);
-            atomicAdd(&rb[e], -sp.k * fd / len);
+            if (!part) atomicAdd(&rb[e], -sp.k * fd / len);
         }
         double* qo = qbar + 3 * (B.p0 * nb + j);
         qo[0] += gx;
@@ -487,10 +504,71 @@ k_springs_adjoint(SpringsDev sp, const double* __restrict__ q,
         qo[2] += gz;
     }
     const double kt = block_reduce<false>(kb, red);  // also orders the LDS sums
+    if (part) {
+        double* pb = part + (size_t)blockIdx.x * (1 + sp.npairs);
+        if (threadIdx.x == 0) pb[0] = kt;
+        for (int e = threadIdx.x; e < sp.npairs; e += BLK) {
+            const int a = sp.pa[e], b = sp.pb[e];
+            double acc = 0.0;
+            for (int pl = 0; pl < B.npart; ++pl) {
+                const double* qa = B.qs + 3 * (pl * nb + a);
+                const double* qb = B.qs + 3 * (pl * nb + b);
+                const double* fa = fb + 3 * (pl * nb + a);
+                const double* fbb = fb + 3 * (pl * nb + b);
+                const double dx = qb[0] - qa[0], dy = qb[1] - qa[1], dz = qb[2] - qa[2];
+                const double len = sqrt(dx * dx + dy * dy + dz * dz);
+                acc += -sp.k * ((fa[0] - fbb[0]) * dx + (fa[1] - fbb[1]) * dy +
+                                (fa[2] - fbb[2]) * dz) / len;
+            }
+            pb[1 + e] = acc;
+        }
+        return;
+    }
     if (threadIdx.x == 0 && kbar) atomicAdd(kbar, kt);
     if (r0bar)
         for (int e = threadIdx.x; e < sp.npairs; e += BLK)
             if (rb[e] != 0.0) atomicAdd(&r0bar[e], rb[e]);
+}
+
+// Block partials of k_springs_adjoint summed in block order: entry 0 into
+// *kbar, entry 1 + e into r0bar[e] (either may be null).
+__global__ void __launch_bounds__(BLK)
+k_sum_parts(const double* __restrict__ part, int nblocks, int nent,
+            double* __restrict__ kbar, double* __restrict__ r0bar) {
+    const int j = blockIdx.x * BLK + threadIdx.x;
+    if (j >= nent) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; ++b) acc += part[(size_t)b * nent + j];
+    if (j == 0) {
+        if (kbar) *kbar += acc;
+    } else if (r0bar) {
+        r0bar[j - 1] += acc;
+    }
+}
+
+// FFT tables of an L-point grid of spacing h: twiddles W_L^k = e^{-2 pi i
+// k/L}, the divergence symbol (1 - e^{-2 pi i k/L})/h (its real part as
+// 2 sin^2(pi k/L)/h, accurate for small k) and |symbol|^2 = 4 sin^2(pi
+// k/L)/h^2, from float64 sin/cos of multiples of pi, cast to T.
+template <typename T>
+__global__ void __launch_bounds__(BLK)
+k_fft_tables(int L, double h, T* __restrict__ tw, T* __restrict__ ds, T* __restrict__ d2) {
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k >= L) return;
+    double s2, c2;
+    sincospi(2.0 * (double)k / (double)L, &s2, &c2);
+    const double sh = sinpi((double)k / (double)L);
+    tw[2 * k] = (T)c2;
+    tw[2 * k + 1] = (T)(-s2);
+    ds[2 * k] = (T)(2.0 * sh * sh / h);
+    ds[2 * k + 1] = (T)(s2 / h);
+    d2[k] = (T)(4.0 * sh * sh / (h * h));
+}
+
+__global__ void __launch_bounds__(BLK)
+k_zero(uint32_t* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 // Blob arrays: out = (a ? a : 0) + s b, and y += x, over n entries.
@@ -623,7 +701,8 @@ constexpr int spread_threads(int f) {
 template <typename T, int TX, int TY, int TZ, int FX, int FY, int FZ>
 __global__ void __launch_bounds__(spread_threads<T>(FX * FY * FZ))
 k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
-         const int* __restrict__ offs, int L, Tiles btl, Tiles tl, T* __restrict__ E) {
+         const int* __restrict__ offs, int L, Tiles btl, Tiles tl, int det,
+         T* __restrict__ E) {
     constexpr int NT = spread_threads<T>(FX * FY * FZ);
     constexpr int NR = FX * FY * FZ;  // binning tiles of this box tile
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
@@ -682,11 +761,19 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
         mode = total <= 2048 ? 0 : 1;
         e = fixed_exponent(fmx, total, mode == 0 ? 0x1p31 : 0x1p63, 0x1p30);
     } else {
-        mode = total <= (1 << 20) ? 0 : 1;
-        e = mode == 0 ? fixed_exponent(fmx, total, 0x1p63, 0x1p50) : 0;
+        // up to 2^20 records one 64-bit fixed-point sum (mode 0); beyond,
+        // float64 LDS atomics (mode 1, whose last bits depend on the order)
+        // or, with det, two 64-bit fixed-point sums (mode 2): the
+        // contributions rounded to the quantum 2^-e, then their rounding
+        // remainders to 2^-(e+38), which cannot overflow up to 2^25 records
+        // (each remainder at most 2^37 quanta)
+        mode = total <= (1 << 20) ? 0 : ((det && total <= (1 << 25)) ? 2 : 1);
+        e = mode != 1 ? fixed_exponent(fmx, total, 0x1p63, 0x1p50) : 0;
     }
+    const int npass = mode == 2 ? 2 : 1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+      for (int pass = 0; pass < npass; ++pass) {
         for (int k = threadIdx.x; k < total; k += NT) {
             RecG<T> r = r0;
             T Fr = F0[a];
@@ -728,12 +815,23 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
 #undef MB_ADD
                 }
             } else {
-                if (mode == 0) {
+                if (mode == 0 || (mode == 2 && pass == 0)) {
                     // round to the nearest integer (|v| <= 2^50): adding
                     // 1.5 * 2^52 leaves it in the low bits of the sum
 #define MB_ADD(i, v)                                                               \
     atomicAdd(&acc[i], (unsigned long long)(__double_as_longlong((double)(v) + 0x1.8p52) - \
                                             __double_as_longlong(0x1.8p52)))
+                    MB_SPREAD_27(MB_ADD)
+#undef MB_ADD
+                } else if (mode == 2) {
+                    // the remainder v - rint(v) (exact), in units of 2^-38
+#define MB_ADD(i, v)                                                                   \
+    do {                                                                               \
+        const double v_ = (double)(v);                                                 \
+        const double r_ = v_ - ((v_ + 0x1.8p52) - 0x1.8p52);                           \
+        atomicAdd(&acc[i], (unsigned long long)(__double_as_longlong(r_ * 0x1p38 + 0x1.8p52) - \
+                                                __double_as_longlong(0x1.8p52)));      \
+    } while (0)
                     MB_SPREAD_27(MB_ADD)
 #undef MB_ADD
                 } else {
@@ -752,8 +850,11 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
             if (F32 && mode == 0) {
                 val = ldexpf((float)(int)acc32[i], -e);
                 acc32[i] = 0u;
-            } else if (F32 || mode == 0) {
+            } else if (F32 || mode == 0 || (mode == 2 && pass == 0)) {
                 val = (T)ldexp((double)(long long)acc[i], -e);
+                acc[i] = 0ull;
+            } else if (mode == 2) {  // the remainders, added to the first sum
+                val = Ea[i] + (T)ldexp((double)(long long)acc[i], -(e + 38));
                 acc[i] = 0ull;
             } else {
                 val = (T)accd[i];
@@ -762,6 +863,7 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
             Ea[i] = val;
         }
         __syncthreads();
+      }
     }
 }
 
@@ -1265,7 +1367,7 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
     const double sc = fscale > 0.0 ? fscale : 1.0 / (h * h * h);
     MB_LAUNCH(g, K_BIN_SCATTER, s, k_bin_scatter<T>, blocks_for(M), BLK, 0, q, F,
               M, 1.0 / h, g->L, sc, g->d_offs, g->d_tile, g->d_rank,
-              rec_geo<T>(g), rec_force<T>(g), g->d_perm);
+              rec_geo<T>(g), rec_force<T>(g), g->d_perm, finite_flag(g));
     g->perm_m = M;
     return hipGetLastError();
 }
@@ -1280,7 +1382,7 @@ hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
     MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, springs_blocks(sp, P), BLK,
               springs_lds(sp), sp, q, Fext, Gblob, P, 1.0 / h, g->L, 1.0 / (h * h * h), g->d_offs,
               g->d_tile, g->d_rank, rec_geo<T>(g), rec_force<T>(g), g->d_perm,
-              force_sums ? g->d_force_part : nullptr);
+              force_sums ? g->d_force_part : nullptr, finite_flag(g));
     g->perm_m = M;
     return hipGetLastError();
 }
@@ -1302,12 +1404,46 @@ size_t springs_adjoint_lds(const SpringsDev& sp) {
 
 hipError_t springs_adjoint(const SpringsDev& sp, int64_t P, const double* q,
                            const double* Fbar, double* qbar, double* kbar,
-                           double* r0bar, hipStream_t s, mb_grid* tg) {
+                           double* r0bar, hipStream_t s, mb_grid* tg, double* part) {
     const int64_t M = P * sp.nb;
     if (M == 0) return hipSuccess;
-    MB_LAUNCH(tg, K_SPRINGS_ADJ, s, k_springs_adjoint, springs_blocks(sp, P), BLK,
-              springs_adjoint_lds(sp), sp, q, Fbar, P, qbar, kbar, r0bar);
+    const int nblk = springs_blocks(sp, P);
+    MB_LAUNCH(tg, K_SPRINGS_ADJ, s, k_springs_adjoint, nblk, BLK,
+              springs_adjoint_lds(sp), sp, q, Fbar, P, qbar, kbar, r0bar, part);
+    if (part && (kbar || r0bar)) {
+        const int nent = 1 + sp.npairs;
+        hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(nent)), dim3(BLK), 0, s, part, nblk,
+                           nent, kbar, r0bar);
+    }
     return hipGetLastError();
+}
+
+size_t springs_adjoint_part_size(const SpringsDev& sp, int64_t P) {
+    return (size_t)springs_blocks(sp, P) * (1 + sp.npairs);
+}
+
+hipError_t zero_words(void* p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for((int64_t)n)), dim3(BLK), 0, s, (uint32_t*)p,
+                       (int64_t)n);
+    return hipGetLastError();
+}
+
+hipError_t init_workspace(mb_grid* g, hipStream_t s) {
+    const int L = g->L;
+    if (g->fsz == 4)
+        hipLaunchKernelGGL(k_fft_tables<float>, dim3(blocks_for(L)), dim3(BLK), 0, s, L,
+                           g->d.h, (float*)g->d_tw, (float*)g->d_dsym, (float*)g->d_d2);
+    else
+        hipLaunchKernelGGL(k_fft_tables<double>, dim3(blocks_for(L)), dim3(BLK), 0, s, L,
+                           g->d.h, (double*)g->d_tw, (double*)g->d_dsym, (double*)g->d_d2);
+    const size_t nt = (size_t)g->ntiles_cap * g->tiles.nbox;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = zero_words(g->d_count, nt, s);
+    if (e == hipSuccess) e = zero_words(g->d_tile_part, nt * 4 * 2, s);
+    if (e == hipSuccess) e = zero_words(g->d_force_part, (size_t)g->force_blocks_cap * 3 * 2, s);
+    if (e == hipSuccess) e = zero_words(g->d_flag, 1, s);
+    return e;
 }
 
 hipError_t blob_axpy(int64_t n, const double* a, double sc, const double* b, double* out,
@@ -1385,7 +1521,7 @@ hipError_t spread_boxes(mb_grid* g, hipStream_t s) {
         SY == FY * t.ty && SZ == FZ * t.tz) {                                            \
         MB_LAUNCH(g, K_SPREAD, s, (k_spread<T, SX, SY, SZ, FX, FY, FZ>), b.n * b.nbox,   \
                   spread_threads<T>(FX * FY * FZ), 0, rec_geo<T>(g), rec_force<T>(g),    \
-                  g->d_offs, g->L, b, t, (T*)g->d_box);                                  \
+                  g->d_offs, g->L, b, t, g->d.deterministic, (T*)g->d_box);              \
         ok = true;                                                                       \
     }
     MB_BOX_SHAPES(MB_BOX)

@@ -21,10 +21,11 @@ Workloads (all h = 1, periodic cubic boxes):
            Fext ~ N(0, 1) per component.
   large    256^3 box, 391,139 particles at volume fraction 0.4; random
            sequential addition cannot reach 0.4 (its jamming limit is about
-           0.38), so centres are a random subset of a 74^3 simple-cubic
-           lattice with a bounded random displacement that keeps every pair
-           at least 3.2 h apart (a valid hard-sphere configuration, as used
-           for the paper's viscosity runs).
+           0.38), so centres start on a random subset of a 74^3 simple-cubic
+           lattice (bounded random displacements keep every pair at least
+           3.2 h apart) and are then moved by hard-sphere Monte Carlo sweeps,
+           the paper's preparation of dense configurations for its
+           viscosity runs.
   pair     two particles separated along x (pair-mobility set-up).
   diff     64^3 box with 16 particles by random sequential addition.
 The seeded generator is numpy's PCG64 (``numpy.random.default_rng``).
@@ -308,13 +309,24 @@ def dense(seed: int = 2, L: int = 128, phi: float = 0.3,
 
 
 def large(seed: int = 5, L: int = 256, phi: float = 0.4,
-          n: int | None = None) -> Workload:
-    """Large suspension: 391,139 particles in 256^3 at phi = 0.4."""
+          n: int | None = None, sweeps: int = 20) -> Workload:
+    """Large suspension: 391,139 particles in 256^3 at phi = 0.4: a random
+    subset of a simple-cubic lattice (random sequential addition jams below
+    0.4), then `sweeps` hard-sphere Monte Carlo sweeps (hard_sphere_sweeps)
+    with centre distance >= 3.2 h."""
     rng = np.random.default_rng(seed)
     P = particles_for_fraction(L, phi) if n is None else n
     c = lattice_centres(rng, float(L), P)
+    start = c.copy()
+    free = (L ** 3 / P) ** (1.0 / 3.0) - 2 * EFFECTIVE_RADIUS
+    mc = hard_sphere_sweeps(rng, c, float(L), 2 * EFFECTIVE_RADIUS, sweeps, 0.5 * free)
+    d = c - start
+    d -= L * np.round(d / L)
     F = rng.standard_normal((P, 3))
-    return _make("large", L, c, rng, True, F, 100, extra={"phi": phi})
+    return _make("large", L, c, rng, True, F, 100,
+                 extra={"phi": phi, "mc_sweeps": sweeps,
+                        "mc_acceptance": float(np.mean(mc["acceptance"])),
+                        "mc_rms_displacement": float(np.sqrt((d * d).sum(1).mean()))})
 
 
 def pair(seed: int = 3, L: int = 32, sep: float | None = None) -> Workload:
@@ -394,6 +406,10 @@ def random_field(seed: int, L: int, scale: float = 1.0) -> np.ndarray:
     return scale * rng.standard_normal((3, L, L, L))
 
 
+# Changes whenever a generator changes what it returns (the cache key
+# includes it, so no stale file is loaded).
+_GENERATOR_VERSION = 2
+
 _GENERATORS = {"single": single, "dense": dense, "large": large, "pair": pair,
                "diff": diff}
 
@@ -406,7 +422,8 @@ def cached(name: str, **kw) -> Workload:
     import hashlib
     import os
     import tempfile
-    key = hashlib.sha1(repr((name, sorted(kw.items()))).encode()).hexdigest()[:16]
+    key = hashlib.sha1(repr((name, sorted(kw.items()), _GENERATOR_VERSION)).encode()
+                       ).hexdigest()[:16]
     root = os.environ.get("MB_INPUT_CACHE",
                           os.path.join(tempfile.gettempdir(), "mb_input_cache"))
     path = os.path.join(root, f"{name}_{key}.npz")
@@ -418,7 +435,8 @@ def cached(name: str, **kw) -> Workload:
         return Workload(name, int(sc[0]), float(sc[1]), float(sc[2]), float(sc[3]),
                         float(sc[4]), int(sc[5]), z["q"], z["Fext"], int(sc[6]),
                         pa, pb, r0, float(sc[7]), tmpl,
-                        {k[6:]: float(z[k]) for k in z.files if k.startswith("extra_")})
+                        {k[6:]: (float(z[k]) if z[k].ndim == 0 else z[k])
+                         for k in z.files if k.startswith("extra_")})
     w = _GENERATORS[name](**kw)
     os.makedirs(root, exist_ok=True)
     tmp = path + f".{os.getpid()}.tmp.npz"
@@ -427,3 +445,53 @@ def cached(name: str, **kw) -> Workload:
              **{f"extra_{k}": v for k, v in w.extra.items()})
     os.replace(tmp, path)
     return w
+
+
+def hard_sphere_sweeps(rng: np.random.Generator, c: np.ndarray, L: float, dmin: float,
+                       sweeps: int, step: float, target_accept: float = 0.4) -> dict:
+    """Hard-sphere Monte Carlo on the centres c (n, 3) in place: `sweeps`
+    sweeps of single-sphere displacements, uniform in +-step per axis,
+    rejected on overlap (minimum-image distance < dmin), as in the Monte
+    Carlo preparation of Sec. Stresslet and Viscosity.  Vectorised by a
+    checkerboard of cells of side >= dmin + 2 step (an even number per
+    axis): in each sub-step one random sphere of every occupied cell of one
+    of the 8 parity classes moves; spheres of same-class cells are at least
+    dmin + 2 step apart along some axis, so their moves cannot conflict, and
+    each trial position is checked against the current centres (a periodic
+    k-d tree: only the mover itself may lie within dmin).  A sweep is as
+    many attempts as spheres.  The step is scaled after each sweep towards
+    `target_accept`.  Returns the acceptance per sweep and the final step."""
+    from scipy.spatial import cKDTree
+    n = c.shape[0]
+    accept_hist = []
+    for _ in range(sweeps):
+        ncell = int(L // (dmin + 2.0 * step))
+        ncell -= ncell % 2
+        if ncell < 4:
+            raise ValueError("box too small for the checkerboard")
+        cs = L / ncell
+        attempts = accepted = 0
+        while attempts < n:
+            for cls in rng.permutation(8):
+                ci = np.floor(c / cs).astype(np.int64) % ncell
+                par = (ci[:, 0] & 1) | ((ci[:, 1] & 1) << 1) | ((ci[:, 2] & 1) << 2)
+                members = np.nonzero(par == cls)[0]
+                if members.size == 0:
+                    continue
+                members = members[rng.permutation(members.size)]
+                cid = (ci[members, 2] * ncell + ci[members, 1]) * ncell + ci[members, 0]
+                _, first = np.unique(cid, return_index=True)
+                mover = members[first]  # one random sphere per occupied cell
+                trial = (c[mover] + rng.uniform(-step, step, size=(mover.size, 3))) % L
+                tree = cKDTree(c % L, boxsize=L, balanced_tree=False, compact_nodes=False)
+                near = tree.query_ball_point(trial, dmin * (1.0 - 1e-12), return_length=True)
+                ok = near <= 1  # the mover itself (within sqrt(3) step < dmin)
+                c[mover[ok]] = trial[ok]
+                attempts += mover.size
+                accepted += int(ok.sum())
+                if attempts >= n:
+                    break
+        rate = accepted / max(attempts, 1)
+        accept_hist.append(rate)
+        step *= min(2.0, max(0.5, rate / target_accept))
+    return {"acceptance": accept_hist, "step": step}

@@ -35,17 +35,24 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_status_strings():
-    for st in (0, -1, -2, -3, -4):
+    for st in (0, -1, -2, -3, -4, -5):
         assert b.status_string(st)
     assert "invalid" in b.status_string(-1)
+    assert "non-finite" in b.status_string(b.MB_ERR_NONFINITE)
+
+
+def _desc(**kw):
+    d = dict(L=32, precision=0, mode=0, zero_mean=0, h=1.0, rho=1.0, eta=1.0,
+             dt=0.01, max_blobs=100, deterministic=0, check_finite=0,
+             external_workspace=0, reserved=0)
+    d.update(kw)
+    return b.GridDesc(d["L"], d["precision"], d["mode"], d["zero_mean"], d["h"],
+                      d["rho"], d["eta"], d["dt"], d["max_blobs"], d["deterministic"],
+                      d["check_finite"], d["external_workspace"], d["reserved"])
 
 
 def _create(**kw):
-    d = dict(L=32, precision=0, mode=0, zero_mean=0, h=1.0, rho=1.0, eta=1.0,
-             dt=0.01, max_blobs=100)
-    d.update(kw)
-    desc = b.GridDesc(d["L"], d["precision"], d["mode"], d["zero_mean"], d["h"],
-                      d["rho"], d["eta"], d["dt"], d["max_blobs"])
+    desc = _desc(**kw)
     h = ctypes.c_void_p(123)
     st = b.lib().mb_grid_create(ctypes.byref(desc), ctypes.byref(h))
     return st, h
@@ -56,20 +63,52 @@ def _create(**kw):
     dict(precision=2), dict(mode=5), dict(zero_mean=3),
     dict(h=0.0), dict(h=-1.0), dict(h=float("nan")), dict(dt=0.0),
     dict(rho=0.0), dict(eta=-1.0), dict(mode=1, eta=0.0), dict(max_blobs=-1),
+    dict(L=648), dict(deterministic=2), dict(check_finite=-1), dict(external_workspace=2),
+    dict(reserved=1),
 ])
 def test_grid_create_rejects_invalid(kw):
     st, h = _create(**kw)
     assert st == b.MB_ERR_INVALID
     assert h.value is None
+    assert b.lib().mb_workspace_size(ctypes.byref(_desc(**kw)), 1) == 0
+
+
+@pytest.mark.parametrize("L", [12, 18, 27, 36, 54, 81, 108, 162, 324, 486])
+def test_grid_create_unsupported_sizes(L):
+    """2^a 3^b sizes that are not multiples of 8 have no tile kernels."""
+    st, h = _create(L=L)
+    assert st == b.MB_ERR_UNSUPPORTED
+    assert h.value is None
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(L=24), dict(L=512), dict(precision=1),
-                                dict(mode=1, rho=0.0), dict(eta=0.0)])
+                                dict(mode=1, rho=0.0), dict(eta=0.0), dict(deterministic=1),
+                                dict(check_finite=1), dict(external_workspace=1)])
 def test_grid_create_valid_needs_device(kw):
     """Valid descriptions pass validation and then report the missing GPU."""
     st, h = _create(**kw)
     assert st == b.MB_ERR_DEVICE
     assert h.value is None
+
+
+def test_workspace_size():
+    """mb_workspace_size is host arithmetic: it covers the spectrum, the spread
+    boxes and the per-blob scratch, grows with max_blobs, the precision and
+    the box count, and is a multiple of 256 bytes."""
+    ws = lambda nbox=1, **kw: b.lib().mb_workspace_size(ctypes.byref(_desc(**kw)), nbox)
+    for L in (8, 24, 32, 128, 144, 512):
+        for prec, s in ((0, 8), (1, 4)):
+            n = ws(L=L, precision=prec, max_blobs=1000)
+            spectrum = 3 * L * L * (L // 2 + 1) * 2 * s
+            boxes = 3 * L ** 3 * s  # at least one entry per node
+            assert n % 256 == 0 and n > spectrum + boxes + 1000 * 48
+    assert ws(L=64, precision=0) > ws(L=64, precision=1)
+    assert ws(L=64, max_blobs=10 ** 6) - ws(L=64, max_blobs=1000) >= 999000 * 48
+    assert ws(nbox=4, L=32) > 3 * ws(nbox=1, L=32)
+    assert ws(nbox=0) == 0 and ws(nbox=70000) == 0
+    assert b.lib().mb_workspace_size(None, 1) == 0
+    # the description flags do not change the size
+    assert ws(L=48, deterministic=1, check_finite=1, external_workspace=1) == ws(L=48)
 
 
 def test_null_arguments():
@@ -83,6 +122,8 @@ def test_null_arguments():
     assert L.mb_spring_forces(None, 0, None, None, None, None) == b.MB_ERR_INVALID
     assert L.mb_step(None, None, 0, None, None, None, None, None, None, 1, None) == b.MB_ERR_INVALID
     assert L.mb_grid_destroy(None) == b.MB_OK
+    assert L.mb_grid_set_workspace(None, None, 0) == b.MB_ERR_INVALID
+    assert L.mb_springs_set_params(None, None, 1.0, None) == b.MB_ERR_INVALID
     assert L.mb_springs_destroy(None) == b.MB_OK
     assert L.mb_grid_set_timing(None, 1) == b.MB_ERR_INVALID
     assert L.mb_kernel_name(0) == b"bin_count"

@@ -62,3 +62,29 @@ def test_hard_sphere_centres_no_overlap_and_moved():
     np.fill_diagonal(r, np.inf)
     assert r.min() >= 2 * R
     assert np.abs(c - c0).max() > 0.1
+
+
+def test_hard_sphere_sweeps_keep_spheres_apart():
+    """The checkerboard Monte Carlo moves spheres (from a dense lattice start)
+    without ever letting two come closer than dmin, with an acceptance near
+    its target."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(3)
+    L, n, dmin = 48.0, 2000, 3.2
+    c = inputs.lattice_centres(rng, L, n, dmin=dmin)
+    c0 = c.copy()
+    out = inputs.hard_sphere_sweeps(rng, c, L, dmin, 8, 0.2)
+    assert len(out["acceptance"]) == 8 and 0.2 < np.mean(out["acceptance"][2:]) < 0.6
+    assert not cKDTree(c % L, boxsize=L).query_pairs(dmin * (1 - 1e-12))
+    d = c - c0
+    d -= L * np.round(d / L)
+    assert np.sqrt((d * d).sum(1)).mean() > 0.1
+
+
+def test_cached_reloads_array_extras(tmp_path, monkeypatch):
+    monkeypatch.setenv("MB_INPUT_CACHE", str(tmp_path))
+    a = inputs.cached("diff")
+    b = inputs.cached("diff")  # from the file
+    for k in ("centres", "rotations", "V"):
+        assert np.array_equal(a.extra[k], b.extra[k])
+    assert np.array_equal(a.q, b.q)
