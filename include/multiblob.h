@@ -353,6 +353,27 @@ mb_status mb_step_adjoint(mb_grid* grid, const mb_springs* springs,
                           double* qbar, void* vbar, double* Fblob_bar,
                           double* kbar, double* r0bar, void* stream);
 
+/* ---- Allocation-free step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  mb_step on a first-order grid described by desc (nbox = 1,
+ * desc->external_workspace ignored), with the grid's whole workspace in a
+ * static device array of MB_NOALLOC_SCRATCH_BYTES held by the library on
+ * each GPU it runs on until the process ends: no hipMalloc, hipFree or
+ * other allocation.  Inputs, outputs and springs as mb_step (the caller
+ * passes them; the springs table is made beforehand with
+ * mb_springs_create).  Each call rebuilds the FFT tables and clears the
+ * counters in the array on `stream`, by kernels, then steps; results equal
+ * mb_step's on a grid of the same description.  MB_ERR_UNSUPPORTED when
+ * mb_workspace_size(desc, 1) exceeds MB_NOALLOC_SCRATCH_BYTES (for example
+ * L <= 64 with ~10^5 blobs fits; 128^3 does not).  All calls on one GPU
+ * share its array: calls that overlap on one GPU (different streams or
+ * threads) race and give undefined results. */
+#define MB_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+mb_status mb_step_noalloc(const mb_grid_desc* desc, const mb_springs* springs,
+                          int64_t nparticles, double* q, void* v, const double* Fext,
+                          double* u_out, double* U0_out, double* diag_out,
+                          int32_t nsteps, void* stream);
+
 /* Human-readable text for a status. */
 const char* mb_status_string(mb_status status);
 

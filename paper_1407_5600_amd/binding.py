@@ -67,6 +67,8 @@ def lib():
             "mb_workspace_size": ([ctypes.POINTER(GridDesc), i32], ctypes.c_size_t),
             "mb_grid_set_workspace": ([vp, vp, ctypes.c_size_t], i32),
             "mb_springs_set_params": ([vp, vp, d, vp], i32),
+            "mb_step_noalloc": ([ctypes.POINTER(GridDesc), vp, i64, vp, vp, vp, vp, vp, vp, i32,
+                                 vp], i32),
             "mb_springs_create": ([i32, i32, vp, vp, vp, d, ctypes.POINTER(vp)], i32),
             "mb_springs_destroy": ([vp], i32),
             "mb_spread": ([vp, i64, vp, vp, vp, vp], i32),
@@ -106,7 +108,7 @@ EXPORTED = ("mb_grid_create", "mb_grid_destroy", "mb_springs_create",
             "mb_grid_create_batch", "mb_step_graph", "mb_step_forced",
             "mb_grid_set_scheme", "mb_grid_set_tiles", "mb_grid_get_tiles",
             "mb_grid_autotune", "mb_workspace_size", "mb_grid_set_workspace",
-            "mb_springs_set_params")
+            "mb_springs_set_params", "mb_step_noalloc")
 
 
 def status_string(st: int) -> str:
@@ -507,6 +509,34 @@ def step_graph(grids, springs, qs, vs, Fexts=None, F_blobs=None, nsteps=1, strea
     FB = opt(F_blobs, lambda i: (qs[i].shape[0], 3), "F_blob")
     _check(lib().mb_step_graph(n, G, S, P, Q, V, FE, FB, int(nsteps), _stream(stream)),
            "mb_step_graph")
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20  # MB_NOALLOC_SCRATCH_BYTES
+
+
+def step_noalloc(springs, q, v, Fext, nsteps=1, u_out=None, U0_out=None, diag_out=None,
+                 stream=None, L=None, h=1.0, rho=1.0, eta=1.0, dt=0.01, precision="fp64",
+                 mode="unsteady", zero_mean=False, deterministic=False, check_finite=False):
+    """mb_step_noalloc: nsteps first-order steps of a grid of these
+    parameters (max_blobs = the blob count) whose workspace is the library's
+    static device array: the call allocates nothing."""
+    import torch
+    M = q.shape[0]
+    P = M // springs.nb
+    if P * springs.nb != M:
+        raise ValueError("blob count is not a multiple of blobs per particle")
+    prec = {"fp64": MB_FP64, "mixed": MB_MIXED}[precision]
+    md = {"unsteady": MB_UNSTEADY_CN, "steady": MB_STEADY_STOKES}[mode]
+    desc = GridDesc(int(L), prec, md, int(bool(zero_mean)), float(h), float(rho), float(eta),
+                    float(dt), int(M), int(bool(deterministic)), int(bool(check_finite)), 0, 0)
+    fdt = torch.float64 if prec == MB_FP64 else torch.float32
+    f64 = torch.float64
+    _check(lib().mb_step_noalloc(
+        ctypes.byref(desc), springs.handle, P, _ptr(q, f64, (M, 3), "q"),
+        _ptr(v, fdt, (3, L, L, L), "v"), _ptr(Fext, f64, (P, 3), "Fext"),
+        _ptr(u_out, f64, (M, 3), "u_out"), _ptr(U0_out, f64, (P, 3), "U0_out"),
+        _ptr(diag_out, f64, (NDIAG,), "diag_out"), int(nsteps), _stream(stream)),
+        "mb_step_noalloc")
 
 
 def kernel_names():

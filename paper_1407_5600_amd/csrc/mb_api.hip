@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1147,6 +1148,78 @@ mb_status mb_grid_kernel_times(mb_grid* g, void* stream, double* ms_out,
     }
     if (n_out) *n_out = K_NUM;
     return MB_OK;
+}
+
+// ---- Allocation-free step: the grid's workspace in a static device array.
+}  // extern "C"
+
+// The scratch of mb_step_noalloc: one array per device (each GPU the library
+// runs on holds it until the process ends).  Host code never uses its name
+// as an address: the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[MB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current), looked up once.
+mb_status scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return MB_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return MB_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+mb_status mb_step_noalloc(const mb_grid_desc* desc, const mb_springs* sp, int64_t P,
+                          double* q, void* v, const double* Fext, double* u_out,
+                          double* U0_out, double* diag_out, int32_t nsteps, void* stream) {
+    if (!desc || !sp) return MB_ERR_INVALID;
+    const mb_grid_desc d = *desc;
+    const mb_status ds = desc_status(d, 1);
+    if (ds != MB_OK) return ds;
+    if (P < 0 || P * sp->nb > d.max_blobs) return MB_ERR_INVALID;
+    const WsLayout w = ws_layout(d, 1);
+    if (w.total > MB_NOALLOC_SCRATCH_BYTES) return MB_ERR_UNSUPPORTED;
+    int dev = 0;
+    if (!device_ok(&dev)) return MB_ERR_DEVICE;
+    void* base = nullptr;
+    mb_status st = scratch_address(dev, &base);
+    if (st != MB_OK) return st;
+    // a grid handle on the stack over the static scratch (no allocation:
+    // its timing vectors stay empty)
+    mb_grid g{};
+    g.d = d;
+    g.device = dev;
+    g.L = d.L;
+    g.NC = d.L / 2 + 1;
+    g.N = (int64_t)d.L * d.L * d.L;
+    g.fsz = d.precision == MB_MIXED ? 4 : 8;
+    g.nblk_x = fft_x_blocks(d.L, d.precision);
+    g.tiles = default_tiles(d.L, 1);
+    g.btiles = make_box_tiles(d.L, g.tiles);
+    g.rec_size = record_size(d.precision);
+    g.force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
+    g.ws_owned = false;
+    ws_bind(&g, base);
+    set_scan_blocks(&g);
+    // tables, zero counts, partial sums and flag, on the caller's stream by
+    // kernels (the array keeps the last call's contents)
+    hipError_t e = init_workspace(&g, (hipStream_t)stream);
+    if (e != hipSuccess) return from_hip(e);
+    return step_impl(&g, sp, P, q, v, Fext, nullptr, u_out, U0_out, diag_out, nsteps, stream);
 }
 
 }  // extern "C"
