@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mb_device.h"
 #include "mb_internal.h"
 
 namespace mb {
@@ -90,22 +91,23 @@ __device__ __forceinline__ void box_entries(const T* __restrict__ Ea, const Axis
                                             T e[4][2]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) e[k][0] = e[k][1] = T(0);
-    const int o0 = sz.off[0] + sy.off[0];
-    e[0][0] = Ea[o0 + sx.off[0]];
-    if (sx.n > 1) e[0][1] = Ea[o0 + sx.off[1]];
+    const unsigned x0 = (unsigned)sx.off[0], x1 = (unsigned)sx.off[1];
+    const unsigned o0 = (unsigned)(sz.off[0] + sy.off[0]);
+    e[0][0] = ld32(Ea, o0 + x0);
+    if (sx.n > 1) e[0][1] = ld32(Ea, o0 + x1);
     if (sy.n > 1) {
-        const int o1 = sz.off[0] + sy.off[1];
-        e[1][0] = Ea[o1 + sx.off[0]];
-        if (sx.n > 1) e[1][1] = Ea[o1 + sx.off[1]];
+        const unsigned o1 = (unsigned)(sz.off[0] + sy.off[1]);
+        e[1][0] = ld32(Ea, o1 + x0);
+        if (sx.n > 1) e[1][1] = ld32(Ea, o1 + x1);
     }
     if (sz.n > 1) {
-        const int o2 = sz.off[1] + sy.off[0];
-        e[2][0] = Ea[o2 + sx.off[0]];
-        if (sx.n > 1) e[2][1] = Ea[o2 + sx.off[1]];
+        const unsigned o2 = (unsigned)(sz.off[1] + sy.off[0]);
+        e[2][0] = ld32(Ea, o2 + x0);
+        if (sx.n > 1) e[2][1] = ld32(Ea, o2 + x1);
         if (sy.n > 1) {
-            const int o3 = sz.off[1] + sy.off[1];
-            e[3][0] = Ea[o3 + sx.off[0]];
-            if (sx.n > 1) e[3][1] = Ea[o3 + sx.off[1]];
+            const unsigned o3 = (unsigned)(sz.off[1] + sy.off[1]);
+            e[3][0] = ld32(Ea, o3 + x0);
+            if (sx.n > 1) e[3][1] = ld32(Ea, o3 + x1);
         }
     }
 }

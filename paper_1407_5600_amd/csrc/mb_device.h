@@ -301,6 +301,20 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* scratch,
 
 // Block index -> work index such that each of the 8 XCDs (which receive
 // blocks round-robin) works on one contiguous range of work items.
+// Element `i` of an array from its (wave-uniform) base with a 32-bit
+// unsigned byte offset, so the load takes the base from scalar registers and
+// one offset register, with no 64-bit address arithmetic per load (every
+// array the kernels index this way is below 4 GiB).
+template <typename T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, unsigned i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                       i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* __restrict__ base, unsigned i, const T& x) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = x;
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int n) {
     const int per = n / 8;
     return (b % 8) * per + b / 8;

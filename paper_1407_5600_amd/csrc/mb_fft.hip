@@ -311,17 +311,17 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 const int y = y0 + 2 * line + hh;
-                const int row = cbase + (z * L + y) * L;
-                if (!BOX) fv[g][hh] = f[row + x];
+                const unsigned row = (unsigned)(cbase + (z * L + y) * L);
+                if (!BOX) fv[g][hh] = ld32(f, row + x);
                 if (!STEADY) {
                     const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-                    vc[g][hh] = v[row + x];
-                    vn[g][hh][0] = v[row + xm];
-                    vn[g][hh][1] = v[row + xp];
-                    vn[g][hh][2] = v[cbase + (z * L + ym) * L + x];
-                    vn[g][hh][3] = v[cbase + (z * L + yp) * L + x];
-                    vn[g][hh][4] = v[cbase + (zm * L + y) * L + x];
-                    vn[g][hh][5] = v[cbase + (zp * L + y) * L + x];
+                    vc[g][hh] = ld32(v, row + x);
+                    vn[g][hh][0] = ld32(v, row + xm);
+                    vn[g][hh][1] = ld32(v, row + xp);
+                    vn[g][hh][2] = ld32(v, (unsigned)(cbase + (z * L + ym) * L + x));
+                    vn[g][hh][3] = ld32(v, (unsigned)(cbase + (z * L + yp) * L + x));
+                    vn[g][hh][4] = ld32(v, (unsigned)(cbase + (zm * L + y) * L + x));
+                    vn[g][hh][5] = ld32(v, (unsigned)(cbase + (zp * L + y) * L + x));
                 }
             }
             if constexpr (BOX) {
@@ -372,7 +372,7 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
         } else {       // (Z + Zc) / 2
             o = cplx<T>{T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
         }
-        out[kx * L + rl] = o;
+        st32(out, (unsigned)(kx * L + rl), o);
     }
     // the block's sums of v and f (one barrier; red holds 16 doubles, at
     // most 8 waves of two partials each)
@@ -413,9 +413,11 @@ k_y(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw) {
     for (int i = tid; i < L; i += NTHR) tws[i] = tw[i];
     // first stage straight from A, last stage straight back (a short last
     // chunk re-reads its first row and stores only its own rows)
-    auto gload = [base, wc](int line, int e) { return base[(line < wc ? line : 0) * L + e]; };
+    auto gload = [base, wc](int line, int e) {
+        return ld32(base, (unsigned)((line < wc ? line : 0) * L + e));
+    };
     auto gstore = [base, wc](int line, int e, cplx<T> x) {
-        if (line < wc) base[line * L + e] = x;
+        if (line < wc) st32(base, (unsigned)(line * L + e), x);
     };
     __syncthreads();  // twiddles
     line_fft_io<T, L, INV, W, LS, NTHR, false, false, false>(buf, tws, tid, gload, gstore);
@@ -471,13 +473,16 @@ k_z_solve(cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     // line (c, w), w fastest: lanes read contiguous ky segments of A; the
     // forward transform reads A and leaves the spectrum in LDS, the inverse
     // reads LDS and writes A
-    auto gload = [A, kx, ky0](int line, int z) {
+    // unsigned 32-bit offsets from the block's column base (the spectrum of
+    // one box is below 4 GiB)
+    cplx<T>* Ak = A + (size_t)kx * L + ky0;
+    auto gload = [Ak](int line, int z) {
         const int c = line / W, w = line - (line / W) * W;
-        return A[((size_t)(c * L + z) * NC + kx) * L + ky0 + w];
+        return ld32(Ak, (unsigned)((c * L + z) * NC * L + w));
     };
-    auto gstore = [A, kx, ky0](int line, int z, cplx<T> x) {
+    auto gstore = [Ak](int line, int z, cplx<T> x) {
         const int c = line / W, w = line - (line / W) * W;
-        A[((size_t)(c * L + z) * NC + kx) * L + ky0 + w] = x;
+        st32(Ak, (unsigned)((c * L + z) * NC * L + w), x);
     };
     cplx<T>* lb = buf;
     auto lload = [lb](int line, int e) { return lb[line * LS + lpad(e)]; };
@@ -544,7 +549,7 @@ k_x_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
             const int e = tid + k * NTHR;
             const int kx = e / R;
             const int rl = e - kx * R;
-            ld[k] = in[e < NC * R ? kx * L + rl : 0];
+            ld[k] = ld32(in, (unsigned)(e < NC * R ? kx * L + rl : 0));
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -576,8 +581,8 @@ k_x_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     };
     T* out = vout + ((size_t)cz * L + y0) * L;
     auto st = [out](int line, int x, cplx<T> zz) {
-        out[(2 * line) * L + x] = zz.x;
-        out[(2 * line + 1) * L + x] = zz.y;
+        st32(out, (unsigned)((2 * line) * L + x), zz.x);
+        st32(out, (unsigned)((2 * line + 1) * L + x), zz.y);
     };
     line_fft_io<T, L, true, NL, LS, NTHR, false, false, false>(buf, tws, tid, ld, st);
 }
@@ -616,7 +621,7 @@ k_xy_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int e = tid + k * NTHR;
-            ld[k] = in[e < NC * L ? e : 0];
+            ld[k] = ld32(in, (unsigned)(e < NC * L ? e : 0));
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -672,7 +677,7 @@ k_xy_inv(const cplx<T>* __restrict__ A, const cplx<T>* __restrict__ tw,
     cplx<T>* out = reinterpret_cast<cplx<T>*>(vout + (size_t)cz * L * L);
     const cplx<T>* lb = buf;
     auto ldl = [lb](int line, int e) { return lb[line * PS + lpad(e)]; };
-    auto gst = [out](int line, int e, cplx<T> x) { out[line * H + e] = x; };
+    auto gst = [out](int line, int e, cplx<T> x) { st32(out, (unsigned)(line * H + e), x); };
     line_fft_io<T, H, true, L, PS, NTHR, false, true, false>(buf, twh, tid, ldl, gst);
 }
 

@@ -860,7 +860,7 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
                 val = (T)accd[i];
                 acc[i] = 0ull;
             }
-            Ea[i] = val;
+            st32(Ea, (unsigned)i, val);
         }
         __syncthreads();
       }
@@ -975,14 +975,14 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             for (int c = 0; c < NCS; ++c) {
                 const int a = a0 + c;
                 const int rows = EYA[a] * EZA[a];
-                const T* va = v + (int64_t)a * N + gx;
+                const T* va = v + (int64_t)a * N;  // uniform base, 32-bit offsets
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     int r = sr + k * RP;
                     r = r < rows ? r : sr;
                     const int ey = r % EYA[a], ez = r / EYA[a];
-                    ld[c][k] = va[(wrapL(tb.lo[2] - 1 + ez, L) * L +
-                                   wrapL(tb.lo[1] - 1 + ey, L)) * L];
+                    ld[c][k] = ld32(va, (unsigned)((wrapL(tb.lo[2] - 1 + ez, L) * L +
+                                                    wrapL(tb.lo[1] - 1 + ey, L)) * L + gx));
                 }
             }
 #pragma unroll
