@@ -137,10 +137,12 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // scan block sums, diagnostics partials) and the spread boxes, both sized
 // for the tile shape of L with the most tiles / box entries, the per-blob
 // arrays (tile, rank, sorted blob, records, velocities), the springs
-// blocks' force sums and the non-finite flag.
+// blocks' force sums, the non-finite flag, and the particle reordering of
+// the step calls (positions and a per-particle array in the calls' own
+// particle order, and that order).
 struct WsLayout {
     enum { TW, DSYM, D2, SPEC, PSUM, COUNT, OFFS, BSUM, TPART, BOX, TILE, RANK, PERM,
-           REC, U, FPART, FLAG, NREG };
+           REC, U, FPART, FLAG, QINT, PINT, ORDER, NREG };
     size_t off[NREG];
     size_t total;
     int ntiles_cap;  // tiles per box
@@ -184,6 +186,9 @@ WsLayout ws_layout(const mb_grid_desc& d, int nbox) {
     sz[WsLayout::U] = (size_t)cap * 3 * sizeof(double);
     sz[WsLayout::FPART] = (size_t)cap * 3 * sizeof(double);  // one springs block per blob at most
     sz[WsLayout::FLAG] = sizeof(int);
+    sz[WsLayout::QINT] = (size_t)cap * 3 * sizeof(double);
+    sz[WsLayout::PINT] = (size_t)cap * 3 * sizeof(double);  // particles <= blobs
+    sz[WsLayout::ORDER] = (size_t)cap * sizeof(int);
     size_t o = 0;
     for (int r = 0; r < WsLayout::NREG; ++r) {
         w.off[r] = o;
@@ -219,6 +224,9 @@ void ws_bind(mb_grid* g, void* base) {
     g->d_u = (double*)(b + w.off[WsLayout::U]);
     g->d_force_part = (double*)(b + w.off[WsLayout::FPART]);
     g->d_flag = (int*)(b + w.off[WsLayout::FLAG]);
+    g->d_qint = (double*)(b + w.off[WsLayout::QINT]);
+    g->d_pint = (double*)(b + w.off[WsLayout::PINT]);
+    g->d_order = (int*)(b + w.off[WsLayout::ORDER]);
     g->perm_m = -1;
 }
 
@@ -669,6 +677,9 @@ static hipError_t alloc_lazy(void** p, size_t bytes) {
     return e;
 }
 
+// Calls of at least this many steps reorder the particles for locality.
+constexpr int kReorderMinSteps = 8;
+
 // Steps of one grid; check: report the non-finite flag at the end (false
 // inside a graph capture, where the caller checks after the replays).
 static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* q,
@@ -700,29 +711,49 @@ static mb_status step_impl(mb_grid* g, const mb_springs* sp, int64_t P, double* 
         e = zero_words(g->d_force_part, 3 * 2, s);
         if (e != hipSuccess) return from_hip(e);
     }
+    // A call of many steps runs them on its own copy of the positions (and
+    // particle forces) with the particles ordered by tile, so that the blobs
+    // of a tile are near one another in memory (their position updates and
+    // records then share cache lines); results do not depend on the order.
+    const bool reorder = M > 0 && nsteps >= kReorderMinSteps && !Gblob && !ffluid;
+    double* qs = q;
+    const double* Fs = Fext;
+    if (reorder) {
+        e = order_particles(g, P, sp->nb, q, Fext, s);
+        qs = g->d_qint;
+        Fs = Fext ? g->d_pint : nullptr;
+        // the call's blob numbering is new: the first binning takes the blobs
+        // in index order, which is by tile now, so that each block counts
+        // into a few tiles (and ranks follow blob order within a tile)
+        g->perm_m = -1;
+    }
     // first-order steps after the first of the call take their binning from
     // the interpolation of the step before (the positions it wrote); the
     // last step leaves the counts at zero
     const bool carry = g->scheme == MB_SCHEME_EULER && M > 0;
+    double* U0_dst = reorder ? g->d_pint : U0_out;  // particle forces are done by then
     for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
         const bool last = n == nsteps - 1;
         const bool binned = carry && n > 0, bin_next = carry && !last;
         double* u_dst = nullptr;
-        if (last) u_dst = u_out ? u_out : (U0_out ? g->d_u : nullptr);
+        if (last && (u_out || U0_out)) u_dst = (u_out && !reorder) ? u_out : g->d_u;
         const bool diag = last && diag_out;  // partial sums only where they are read
         if (g->fsz == 4)
-            e = step_once<float>(g, sd, P, M, q, (float*)v, Fext, Gblob, (const float*)ffluid,
+            e = step_once<float>(g, sd, P, M, qs, (float*)v, Fs, Gblob, (const float*)ffluid,
                                  u_dst, s, binned, bin_next, diag);
         else
-            e = step_once<double>(g, sd, P, M, q, (double*)v, Fext, Gblob,
+            e = step_once<double>(g, sd, P, M, qs, (double*)v, Fs, Gblob,
                                   (const double*)ffluid, u_dst, s, binned, bin_next, diag);
         if (!last && e != hipSuccess && bin_next)
             (void)zero_words(g->d_count, (size_t)g->tiles.n * g->tiles.nbox, s);
         if (last && e == hipSuccess && U0_out)
-            e = particle_means(g, P, sp->nb, u_dst, U0_out, s);
+            e = particle_means(g, P, sp->nb, u_dst, U0_dst, s);
         if (last && e == hipSuccess && diag_out)
             e = diagnostics(g, M > 0 ? fb : 1, diag_out, s);
     }
+    if (reorder && e == hipSuccess)
+        e = unorder_particles(g, P, sp->nb, q, u_out ? g->d_u : nullptr, u_out,
+                              U0_out ? g->d_pint : nullptr, U0_out, s);
     if (!check) return from_hip(e);
     return finish(g, e, s);
 }

@@ -99,6 +99,9 @@ struct mb_grid {
     size_t ws_bytes;
     bool ws_owned;      // allocated by the library (freed at destroy)
     int* d_flag;        // non-finite flag (check_finite)
+    double* d_qint;     // [max_blobs][3] positions in the step calls' particle order
+    double* d_pint;     // [max_blobs][3] per-particle forces, then velocities, same order
+    int* d_order;       // [max_blobs] caller's particle of each internal particle
     int ntiles_cap;     // tiles per box the workspace holds (all shapes)
     int L, NC;          // cells per side, complex columns L/2 + 1
     int64_t N;          // L^3 (cells of one box)
@@ -237,6 +240,17 @@ hipError_t particle_means(mb_grid* g, int64_t P, int nb, const double* u,
                           double* U0, hipStream_t s);
 hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,
                        hipStream_t s);
+// Particle order of a step call: particles counting-sorted by the tile of
+// their last blob (the centre of the icosahedral template) into d_order
+// (internal particle -> caller's particle), and the positions q and forces
+// Fext (nullable) gathered into d_qint and d_pint in that order.
+hipError_t order_particles(mb_grid* g, int64_t P, int nb, const double* q,
+                           const double* Fext, hipStream_t s);
+// Back to the caller's order: positions into q, and (each nullable) the blob
+// velocities u_int into u_out and particle velocities U0_int into U0_out.
+hipError_t unorder_particles(mb_grid* g, int64_t P, int nb, double* q, const double* u_int,
+                             double* u_out, const double* U0_int, double* U0_out,
+                             hipStream_t s);
 size_t record_size(int precision);
 // Blocks and dynamic LDS bytes of the springs kernels for P particles.
 int springs_blocks(const SpringsDev& sp, int64_t P);

@@ -1299,6 +1299,55 @@ k_u0(const double* __restrict__ u, int64_t P, int nb, double* __restrict__ U0) {
     for (int c = 0; c < 3; ++c) U0[3 * p + c] = s[c] / (double)nb;
 }
 
+// Particle order of a step call.  Each particle is counted into the tile
+// (box included) of its last blob with one global atomic; after the scan of
+// the counts, internal particle offs[tile] + rank is that particle.  The
+// gather and the scatter run one thread per float64 of the positions, so
+// both sides of every copy are runs of 3 nb contiguous values.
+__global__ void __launch_bounds__(BLK)
+k_part_count(const double* __restrict__ q, int64_t P, int nb, int64_t pbox, double inv_h,
+             int L, Tiles tl, int* __restrict__ count, int* __restrict__ tile_of,
+             int* __restrict__ rank) {
+    const int64_t p = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (p >= P) return;
+    const Geom g = blob_geom(q, p * nb + nb - 1, inv_h, L);
+    const int t = (int)(p / pbox) * tl.n + tile_linear(g.c, tl);
+    tile_of[p] = t;
+    rank[p] = atomicAdd(&count[t], 1);
+}
+
+__global__ void __launch_bounds__(BLK)
+k_part_gather(const double* __restrict__ q, const double* __restrict__ Fext, int64_t P,
+              int nb, const int* __restrict__ offs, const int* __restrict__ tile_of,
+              const int* __restrict__ rank, int* __restrict__ order,
+              double* __restrict__ qi, double* __restrict__ Fi) {
+    const int64_t j = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const int64_t per = 3 * (int64_t)nb;
+    if (j >= per * P) return;
+    const int64_t p = j / per;
+    const int64_t c = j - p * per;
+    const int64_t pos = (int64_t)offs[tile_of[p]] + rank[p];
+    qi[pos * per + c] = q[j];
+    if (c < 3 && Fext) Fi[3 * pos + c] = Fext[3 * p + c];
+    if (c == 0) order[pos] = (int)p;
+}
+
+__global__ void __launch_bounds__(BLK)
+k_part_scatter(const double* __restrict__ qi, const int* __restrict__ order, int64_t P,
+               int nb, double* __restrict__ q, const double* __restrict__ ui,
+               double* __restrict__ u, const double* __restrict__ U0i,
+               double* __restrict__ U0) {
+    const int64_t j = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const int64_t per = 3 * (int64_t)nb;
+    if (j >= per * P) return;
+    const int64_t pi = j / per;
+    const int64_t c = j - pi * per;
+    const int64_t p = order[pi];
+    q[p * per + c] = qi[j];
+    if (u) u[p * per + c] = ui[j];
+    if (U0 && c < 3) U0[3 * p + c] = U0i[3 * pi + c];
+}
+
 __global__ void __launch_bounds__(BLK)
 k_diag(const double* __restrict__ tile_part, int ntiles,
        const double* __restrict__ force_part, int nfb, double mom_scale,
@@ -1341,9 +1390,18 @@ static T* rec_force(mb_grid* g) {
     return (T*)((char*)g->d_rec + cap * sizeof(RecG<T>));
 }
 
+// Exclusive scan of the tile counts into offs (the counts reset to zero).
+static void scan_tiles(mb_grid* g, hipStream_t s) {
+    const int nt = g->tiles.n * g->tiles.nbox;
+    if (g->nscan > 1)
+        MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
+                  (int64_t)nt, g->d_bsum);
+    MB_LAUNCH(g, K_SCAN_APPLY, s, k_scan_apply, g->nscan, BLK, 0, g->d_count,
+              (int64_t)nt, g->d_bsum, g->d_offs);
+}
+
 template <typename T>
 hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s, bool counted) {
-    const int nt = g->tiles.n * g->tiles.nbox;
     if (M > 0 && !counted) {
         // the previous sorted order, when it is a permutation of these blobs
         const int* order = g->perm_m == M ? g->d_perm : nullptr;
@@ -1351,11 +1409,28 @@ hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s, bool
                   M / g->tiles.nbox, 1.0 / g->d.h, g->L, g->tiles, g->d_count, g->d_tile,
                   g->d_rank);
     }
-    if (g->nscan > 1)
-        MB_LAUNCH(g, K_SCAN_REDUCE, s, k_scan_reduce, g->nscan, BLK, 0, g->d_count,
-                  (int64_t)nt, g->d_bsum);
-    MB_LAUNCH(g, K_SCAN_APPLY, s, k_scan_apply, g->nscan, BLK, 0, g->d_count,
-              (int64_t)nt, g->d_bsum, g->d_offs);
+    scan_tiles(g, s);
+    return hipGetLastError();
+}
+
+hipError_t order_particles(mb_grid* g, int64_t P, int nb, const double* q,
+                           const double* Fext, hipStream_t s) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_part_count, dim3(blocks_for(P)), dim3(BLK), 0, s, q, P, nb,
+                       P / g->tiles.nbox, 1.0 / g->d.h, g->L, g->tiles, g->d_count, g->d_tile,
+                       g->d_rank);
+    scan_tiles(g, s);
+    hipLaunchKernelGGL(k_part_gather, dim3(blocks_for(3 * nb * P)), dim3(BLK), 0, s, q, Fext, P,
+                       nb, g->d_offs, g->d_tile, g->d_rank, g->d_order, g->d_qint, g->d_pint);
+    return hipGetLastError();
+}
+
+hipError_t unorder_particles(mb_grid* g, int64_t P, int nb, double* q, const double* u_int,
+                             double* u_out, const double* U0_int, double* U0_out,
+                             hipStream_t s) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_part_scatter, dim3(blocks_for(3 * nb * P)), dim3(BLK), 0, s,
+                       g->d_qint, g->d_order, P, nb, q, u_int, u_out, U0_int, U0_out);
     return hipGetLastError();
 }
 

@@ -550,3 +550,46 @@ def test_step_call_binning_carry_is_exact(torch_cuda, prec, case):
     for o in out[1:]:
         for a, b in zip(out[0], o):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["suspension", "batch", "midpoint"])
+def test_step_call_particle_order_is_exact(torch_cuda, prec, case):
+    """A call of many steps runs them with the particles reordered by tile
+    (its own copy of the positions, scattered back at the end).  Its
+    positions, fluid velocity, blob and particle velocities and momentum
+    equal those of one call per step bit for bit; the net force, a float64
+    sum over blocks of particles, agrees to rounding."""
+    from paper_1407_5600_amd import Springs
+    torch = torch_cuda
+    say("particle order", prec, case)
+    nbox, n = 1, 10
+    if case == "batch":
+        nbox = 3
+        ws = [inputs.random_suspension(60 + b, 32, 40) for b in range(nbox)]
+        w = ws[0]
+        q0 = np.concatenate([x.q for x in ws])
+        Fe = np.concatenate([x.Fext for x in ws])
+    else:
+        w = inputs.random_suspension(62, 48, 150)
+        q0, Fe = w.q, w.Fext
+    M = q0.shape[0]
+    sp = Springs(w.nb, w.pa, w.pb, w.r0, w.k)
+    out = []
+    for calls in ([n], [1] * n):
+        g = grid(w.L, prec, M, rho=w.rho, eta=w.eta, dt=w.dt, nbox=nbox,
+                 scheme="midpoint" if case == "midpoint" else "euler")
+        q = dev(torch, q0)
+        v = g.field()
+        F = dev(torch, Fe)
+        u = torch.zeros_like(q)
+        U0 = torch.zeros((M // w.nb, 3), dtype=torch.float64, device="cuda")
+        diag = torch.zeros(7, dtype=torch.float64, device="cuda")
+        for k in calls:
+            g.step(sp, q, v, F, k, u, U0, diag)
+        torch.cuda.synchronize()
+        out.append([x.cpu().numpy() for x in (q, v, u, U0, diag)])
+    for a, b in zip(out[0][:4], out[1][:4]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(out[0][4][:3], out[1][4][:3]) and out[0][4][6] == out[1][4][6]
+    assert np.allclose(out[0][4][3:6], out[1][4][3:6], rtol=0, atol=1e-12 * np.abs(Fe).sum())
