@@ -342,23 +342,32 @@ def host_cpu():
     return None
 
 
+R_NOSLIP = 1.62  # no-slip radius of the d = h icosahedron (Table 2)
+
+
 def bench_batch(torch, nbox, steps, sample=32):
-    """Pair-mobility sweep: nbox boxes of edge 24/32/48/64 with two particles
-    each, mixed precision, grouped by edge into four batch grids stepped by
-    one graph-captured step per time step; against the same boxes stepped one
-    grid per box (a sample of them, eager)."""
+    """Pair-mobility sweep: nbox boxes of edge 24/32/48/64 with two d = h
+    icosahedra each (one random orientation per box) pulled towards each
+    other along their line of centres, steady Stokes with dt = 0.05 (the
+    Stokes-limit set-up of the paper's pair measurements), mixed precision,
+    grouped by edge into four batch grids stepped by one graph-captured step
+    per time step; against the same boxes stepped one grid per box (a
+    sample of them, eager).  Each box's relative velocity at the end gives
+    the pair mobility, compared with the two-sphere function of eq. ab for
+    separations beyond 2.5 R_s."""
     import numpy as np
-    from paper_1407_5600_amd import Grid, Springs, inputs
+    from paper_1407_5600_amd import Grid, Springs, inputs, stokes
     from paper_1407_5600_amd.binding import step_graph
-    boxes = inputs.pair_sweep(nbox=nbox)
-    tmpl = inputs.icosahedron_template(1.0)
+    tmpl = inputs.icosahedron_template(inputs.CIRCUMRADIUS_OVER_EDGE * 1.0)
+    boxes = inputs.pair_sweep(nbox=nbox, template=tmpl, rotate=True)
     pa, pb, r0 = inputs.pair_table(tmpl)
     sp = Springs(len(tmpl), pa, pb, r0, 100.0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    kw = dict(precision="mixed", mode="steady", zero_mean=True, dt=0.05)
     grids, qs, vs, fs, order = [], [], [], [], []
     for L in sorted({b["L"] for b in boxes}):
         idx = [i for i, b in enumerate(boxes) if b["L"] == L]
-        g = Grid(L, precision="mixed", max_blobs=26 * len(idx), nbox=len(idx))
+        g = Grid(L, max_blobs=26 * len(idx), nbox=len(idx), **kw)
         grids.append(g)
         qs.append(dev(np.concatenate([boxes[i]["q"] for i in idx])))
         vs.append(g.field())
@@ -376,15 +385,31 @@ def bench_batch(torch, nbox, steps, sample=32):
         g.step(sp, q, v, F, steps)
     torch.cuda.synchronize()
     t_eager = (time.perf_counter() - t0) / steps
-    # relative velocity U1 - U2 per box after the run (one more step)
-    rel_u = []
+    # relative velocity (U1 - U2).x per box after the run (one more step),
+    # and the blob positions it is taken at
+    rel_u = np.zeros(nbox)
+    q_at = np.zeros((nbox, 2 * len(tmpl), 3))
     for g, q, v, F, idx in zip(grids, qs, vs, fs, order):
+        q_at[idx] = q.view(len(idx), 2 * len(tmpl), 3).cpu().numpy()
         U0 = torch.empty((2 * len(idx), 3), dtype=torch.float64, device="cuda")
         g.step(sp, q, v, F, 1, U0_out=U0)
-        rel_u.append((U0[0::2, 0] - U0[1::2, 0]).cpu().numpy())
+        rel_u[idx] = (U0[0::2, 0] - U0[1::2, 0]).cpu().numpy()
+    # pair part of the mobility per box against eq. ab (untimed: each
+    # particle alone in a box of its own at the same blob positions)
+    F_x = np.array([b["Fext"][:, 0] for b in boxes])
+    pi = stokes.pair_sweep_interaction(torch, q_at, [b["L"] for b in boxes], F_x, rel_u,
+                                       tmpl, R_s=R_NOSLIP, dt=0.05)
+    far = pi["r"] > 2.5 * R_NOSLIP
+    err = np.abs(pi["interaction"] - pi["sphere"]) / pi["sphere"]
+    stat = lambda m: ({"boxes": int(m.sum()), "rel_err_mean": round(float(err[m].mean()), 4),
+                       "rel_err_max": round(float(err[m].max()), 4)} if m.any() else
+                      {"boxes": 0})
+    eq_ab = {"r_min": round(2.5 * R_NOSLIP, 3), "all": stat(far),
+             "by_L": {int(L): stat(far & (pi["L"] == L)) for L in sorted(set(pi["L"]))},
+             "r_below_4.5": stat(far & (pi["r"] < 4.5)), "r_from_4.5": stat(pi["r"] >= 4.5)}
     # one grid per box, a sample of the boxes
     samp = boxes[:sample]
-    sg = [Grid(b["L"], precision="mixed", max_blobs=26) for b in samp]
+    sg = [Grid(b["L"], max_blobs=26, **kw) for b in samp]
     sq = [dev(b["q"]) for b in samp]
     sv = [g.field() for g in sg]
     sf = [dev(b["Fext"]) for b in samp]
@@ -399,8 +424,9 @@ def bench_batch(torch, nbox, steps, sample=32):
     torch.cuda.synchronize()
     per_box_step = (time.perf_counter() - t0) / (ns * len(samp))
     sample_cells = sum(b["L"] ** 3 for b in samp)
-    return {"workload": f"pair sweep: {nbox} boxes of edge 24/32/48/64 (seeded), 2 particles "
-                        f"each at x-separation U[2,6], forces +-(1,0,0), mixed",
+    return {"workload": f"pair sweep: {nbox} boxes of edge 24/32/48/64 (seeded), 2 d = h "
+                        f"icosahedra each at x-separation U[2,6], forces +-(1,0,0), steady "
+                        f"Stokes, dt 0.05, mixed",
             "boxes": nbox, "cells": int(cells), "steps": steps,
             "batched_graph_ms_per_step": round(t_batch * 1e3, 4),
             "box_steps_per_s": round(nbox / t_batch, 1),
@@ -408,9 +434,9 @@ def bench_batch(torch, nbox, steps, sample=32):
             "one_grid_per_box_ms_per_box_step": round(per_box_step * 1e3, 4),
             "one_grid_per_box_sample": f"{len(samp)} boxes ({sample_cells} cells), eager",
             "speedup_vs_one_grid_per_box": round(per_box_step * nbox / t_batch, 2),
-            "relative_velocity_x": {"mean": float(np.mean(np.concatenate(rel_u))),
-                                    "min": float(np.min(np.concatenate(rel_u))),
-                                    "max": float(np.max(np.concatenate(rel_u)))}}
+            "relative_velocity_x": {"mean": float(rel_u.mean()), "min": float(rel_u.min()),
+                                    "max": float(rel_u.max())},
+            "pair_mobility_vs_eq_ab": eq_ab}
 
 
 def main():
@@ -426,7 +452,7 @@ def main():
                     help="run one precision (profiling)")
     ap.add_argument("--batch-boxes", type=int, default=512,
                     help="boxes of the batched pair-sweep measurement (0: skip it)")
-    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--large-steps", type=int, default=100,
                     help="steps per precision of the 256^3 phi = 0.4 suspension (0: skip it)")
     ap.add_argument("--no-extras", action="store_true",

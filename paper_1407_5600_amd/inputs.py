@@ -359,14 +359,18 @@ def diff(seed: int = 4) -> Workload:
 
 
 def pair_sweep(seed: int = 3, nbox: int = 512, sizes=(24, 32, 48, 64),
-               sep_range=(2.0, 6.0)) -> list:
+               sep_range=(2.0, 6.0), template=None, rotate=False) -> list:
     """Batched pair-mobility sweep: nbox independent periodic boxes with
     edges drawn uniformly from `sizes`, each with two particles separated
     along x by a distance uniform in sep_range, centred in the box, forces
     +-(1, 0, 0), dt = 0.01, 500 steps.  Returns one dict per box with L, q
-    (26, 3), Fext (2, 3), sep."""
+    (26, 3), Fext (2, 3), sep and the two centres c (2, 3).  The particle is
+    `template` (default: the filled icosahedron of circumradius 1), both
+    particles of a box in the canonical orientation or, with rotate, in one
+    random orientation per box (drawn after the boxes, which stay the
+    same)."""
     rng = np.random.default_rng(seed)
-    tmpl = icosahedron_template(1.0)
+    tmpl = icosahedron_template(1.0) if template is None else template
     Ls = rng.choice(np.asarray(sizes), size=nbox)
     seps = rng.uniform(sep_range[0], sep_range[1], size=nbox)
     F = np.array([[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0]])
@@ -375,7 +379,11 @@ def pair_sweep(seed: int = 3, nbox: int = 512, sizes=(24, 32, 48, 64),
         mid = np.full(3, L / 2.0) + rng.uniform(-0.5, 0.5, size=3)
         c = np.stack([mid - [sep / 2, 0, 0], mid + [sep / 2, 0, 0]])
         boxes.append({"L": int(L), "sep": float(sep), "q": place_particles(c, tmpl),
-                      "Fext": F.copy()})
+                      "Fext": F.copy(), "c": c})
+    if rotate:
+        R = random_rotations(rng, nbox)
+        for b, Rb in zip(boxes, R):
+            b["q"] = place_particles(b["c"], tmpl, np.stack([Rb, Rb]))
     return boxes
 
 

@@ -195,6 +195,88 @@ def pair_interaction_sphere(r, R, direction="normal"):
     return (1.0 - f(r, R)) / R
 
 
+def _lone_velocities(torch, q, L_box, F_x, tmpl, k, precision, eta=1.0, dt=0.01):
+    """x-velocity of each particle of each pair box when alone in a box of
+    the same edge, with the same blob positions (q: (nbox, 2 nb, 3)) and the
+    same force (F_x: (nbox, 2)); steady Stokes, zero mean, one step from
+    those positions: (nbox, 2) array."""
+    sp = _springs(tmpl, k)
+    nb = tmpl.shape[0]
+    out = np.zeros((len(L_box), 2))
+    for L in sorted(set(int(x) for x in L_box)):
+        idx = [i for i, x in enumerate(L_box) if int(x) == L]
+        ql = np.concatenate([q[i] for i in idx])  # particle 1, particle 2 of each box
+        F = np.zeros((2 * len(idx), 3))
+        F[:, 0] = np.asarray(F_x)[idx].reshape(-1)
+        g = Grid(L, eta=eta, dt=dt, precision=precision, mode="steady", zero_mean=True,
+                 max_blobs=ql.shape[0], nbox=2 * len(idx))
+        U0 = torch.empty((2 * len(idx), 3), dtype=torch.float64, device="cuda")
+        g.step(sp, _dev(torch, ql), g.field(), _dev(torch, F), 1, U0_out=U0)
+        out[idx] = U0[:, 0].view(-1, 2).cpu().numpy()
+        g.close()
+    return out
+
+
+def pair_sweep_interaction(torch, q, L_box, F_x, U_rel, tmpl, k=100.0, R_s=1.62,
+                           precision="mixed", eta=1.0, dt=0.01):
+    """Pair part of the mobility of two particles pulled apart along their
+    line of centres (x), from the relative velocity U_rel = (U1 - U2).x of
+    each pair box at blob positions q (nbox, 2 nb, 3) (steady Stokes, zero
+    mean, forces F_x (nbox, 2) = (F, -F)), against eq. ab.  With particle j
+    alone at the same blob positions (x-velocity U_ja, same force), the pair
+    mobility along x in the periodic box is
+    mu12(L) = [(U_1a - U_2a) - U_rel] / (2F), which cancels the dependence
+    of the self terms on the place within the cell; the image shift
+    -2.837 / (6 pi eta L) of eq. rhinf, common to self and pair terms, is
+    added back:
+        6 pi eta mu12 = 6 pi eta [(U_1a - U_2a) - U_rel] / (2F) + 2.837 / L,
+    to be compared with (1 - A(r)) / R_s for two spheres of radius R_s at
+    the centre distance r (remainder O(r^2 / L^3)).  Returns per box r, L,
+    the measured and the two-sphere values."""
+    q = np.asarray(q, dtype=np.float64)
+    nb = tmpl.shape[0]
+    Ua = _lone_velocities(torch, q, L_box, F_x, tmpl, k, precision, eta, dt)
+    F = np.abs(np.asarray(F_x)[:, 0])
+    L = np.asarray(L_box, dtype=np.float64)
+    c1, c2 = q[:, :nb].mean(1), q[:, nb:].mean(1)
+    d = c2 - c1
+    d -= L[:, None] * np.round(d / L[:, None])  # minimum image
+    r = np.linalg.norm(d, axis=1)
+    meas = 6.0 * math.pi * eta * ((Ua[:, 0] - Ua[:, 1]) - np.asarray(U_rel)) / (2.0 * F) \
+        + HASIMOTO / L
+    return {"r": r, "L": L, "interaction": meas,
+            "sphere": pair_interaction_sphere(r, R_s, "normal")}
+
+
+def pair_sweep_measure(torch, boxes, tmpl, steps=1000, k=100.0, R_s=1.62,
+                       precision="mixed", eta=1.0, dt=0.05):
+    """The sweep boxes (inputs.pair_sweep) as batch grids by edge, steady
+    Stokes with zero mean, advanced `steps` steps by one graph-captured
+    step each; then the relative velocity of each box's pair and its pair
+    part against eq. ab (pair_sweep_interaction)."""
+    sp = _springs(tmpl, k)
+    nb = tmpl.shape[0]
+    grids, qs, vs, fs, order = [], [], [], [], []
+    for L in sorted({b["L"] for b in boxes}):
+        idx = [i for i, b in enumerate(boxes) if b["L"] == L]
+        g = Grid(L, eta=eta, dt=dt, precision=precision, mode="steady", zero_mean=True,
+                 max_blobs=2 * nb * len(idx), nbox=len(idx))
+        grids.append(g), order.append(idx), vs.append(g.field())
+        qs.append(_dev(torch, np.concatenate([boxes[i]["q"] for i in idx])))
+        fs.append(_dev(torch, np.concatenate([boxes[i]["Fext"] for i in idx])))
+    _run(grids, [sp] * len(grids), qs, vs, fs, steps)
+    rel = np.zeros(len(boxes))
+    q_at = np.zeros((len(boxes), 2 * nb, 3))
+    for g, q, v, F, idx in zip(grids, qs, vs, fs, order):
+        q_at[idx] = q.view(len(idx), 2 * nb, 3).cpu().numpy()
+        U0 = torch.empty((2 * len(idx), 3), dtype=torch.float64, device="cuda")
+        g.step(sp, q, v, F, 1, U0_out=U0)
+        rel[idx] = (U0[0::2, 0] - U0[1::2, 0]).cpu().numpy()
+    F_x = np.array([b["Fext"][:, 0] for b in boxes])
+    return pair_sweep_interaction(torch, q_at, [b["L"] for b in boxes], F_x, rel, tmpl, k,
+                                  R_s, precision, eta, dt)
+
+
 def shear_force_field(L, f0, j=1, h=1.0, nbox=1):
     """Force density f0 sin(k_j y) x on the staggered grid, k_j = 2 pi j /
     (L h): the x component lives on the x faces, whose y coordinate is the

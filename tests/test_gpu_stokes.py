@@ -205,3 +205,29 @@ def test_viscosity_einstein_batchelor(torch_cuda):
         assert np.isfinite(p["eta_rel"]) and p["eta_rel"] > prev
         assert e < 0.03
         prev = p["eta_rel"]
+
+
+def test_pair_sweep_boxes_eq_ab(torch_cuda):
+    """Every box of a reduced pair sweep (edges 24-64, one batch grid per
+    edge, one random orientation per box, separations 4.5-6 h, beyond
+    2.5 R_s) against eq. ab: the pair part of the mobility from the box's
+    relative velocity and from its two particles each alone at the same blob
+    positions, after the springs have relaxed (steady Stokes, dt = 0.05,
+    1,000 steps, forces +-0.01 x so that the pair stays in place), against
+    (1 - A(r)) / R_s.  The bound is the multiblob's departure from the
+    two-sphere reflections at these distances (measured over 256 such
+    boxes: mean 3%, at most 9% per box)."""
+    torch = torch_cuda
+    from paper_1407_5600_amd import inputs, stokes
+    say("pair sweep boxes vs eq. ab")
+    tmpl = inputs.icosahedron_template(inputs.CIRCUMRADIUS_OVER_EDGE)
+    boxes = inputs.pair_sweep(seed=21, nbox=32, sep_range=(4.5, 6.0), template=tmpl,
+                              rotate=True)
+    for b in boxes:
+        b["Fext"] = 0.01 * b["Fext"]
+    r = stokes.pair_sweep_measure(torch, boxes, tmpl, steps=1000)
+    err = np.abs(r["interaction"] - r["sphere"]) / r["sphere"]
+    say("per box: r", np.round(r["r"], 2).tolist(), "L", r["L"].astype(int).tolist(),
+        "rel err", np.round(err, 3).tolist())
+    assert np.all(r["r"] > 2.5 * 1.62)
+    assert err.max() < 0.10 and err.mean() < 0.05

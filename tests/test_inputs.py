@@ -88,3 +88,31 @@ def test_cached_reloads_array_extras(tmp_path, monkeypatch):
     for k in ("centres", "rotations", "V"):
         assert np.array_equal(a.extra[k], b.extra[k])
     assert np.array_equal(a.q, b.q)
+
+
+def test_pair_sweep_boxes():
+    """Boxes of the pair sweep: edges from the set, the two centres along x
+    at the drawn separation about the box middle, forces +-x; the rotated
+    variant keeps every box (edge, separation, centres) and only turns the
+    particles about their centres."""
+    tmpl = inputs.icosahedron_template(inputs.CIRCUMRADIUS_OVER_EDGE)
+    a = inputs.pair_sweep(seed=7, nbox=40, template=tmpl)
+    b = inputs.pair_sweep(seed=7, nbox=40, template=tmpl, rotate=True)
+    nb = tmpl.shape[0]
+    for x, y in zip(a, b):
+        assert x["L"] in (24, 32, 48, 64) and 2.0 <= x["sep"] <= 6.0
+        assert x["L"] == y["L"] and x["sep"] == y["sep"]
+        np.testing.assert_array_equal(x["c"], y["c"])
+        d = x["c"][1] - x["c"][0]
+        np.testing.assert_allclose(d, [x["sep"], 0.0, 0.0], atol=1e-12)
+        assert np.all(np.abs(x["c"].mean(0) - x["L"] / 2) <= 0.5)
+        np.testing.assert_array_equal(x["Fext"], [[1.0, 0, 0], [-1.0, 0, 0]])
+        for j in (0, 1):
+            qa, qb = x["q"][j * nb:(j + 1) * nb], y["q"][j * nb:(j + 1) * nb]
+            np.testing.assert_allclose(qa.mean(0), x["c"][j], atol=1e-12)
+            np.testing.assert_allclose(qb.mean(0), x["c"][j], atol=1e-12)
+            # same shape: pairwise blob distances agree
+            da = np.linalg.norm(qa[:, None] - qa[None], axis=-1)
+            db = np.linalg.norm(qb[:, None] - qb[None], axis=-1)
+            np.testing.assert_allclose(da, db, atol=1e-12)
+        assert not np.allclose(x["q"], y["q"])
