@@ -280,12 +280,20 @@ struct SpringsBlk {
     int* adj;      // [nb + 1] incidence starts, then [2 np] (pair << 8 | other)
 };
 
+struct NoOp {
+    __device__ void operator()() const {}
+};
+
+// after_loads runs once the position loads are issued (more loads of the
+// caller, in flight with them).
+template <typename AfterLoads = NoOp>
 __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
                                                     const double* __restrict__ q,
                                                     const double* __restrict__ Fext,
                                                     const double* __restrict__ Gblob,
                                                     int64_t P, double* smem,
-                                                    double fe[3]) {
+                                                    double fe[3],
+                                                    AfterLoads after_loads = NoOp{}) {
     SpringsBlk B;
     const int nb = sp.nb, np = sp.npairs;
     B.p0 = (int64_t)blockIdx.x * sp.ppb;
@@ -295,38 +303,56 @@ __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
     B.r0s = smem + 3 * sp.ppb * nb;
     B.adj = (int*)(B.r0s + np);
     const double* qg = q + 3 * B.p0 * nb;  // contiguous blobs of the block
-    // the position loads are issued first (a block holds at most BLK blobs:
-    // springs_blocks), then the external force and the tables, then the
-    // LDS stores
+    // every load is issued before any result is used (one round trip): the
+    // positions (a block holds at most BLK blobs: springs_blocks), the
+    // external force of the thread's particle and its blob's own force
+    // (indices clamped into the block, values dropped below), the tables;
+    // then the LDS stores
     double ld[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int i = threadIdx.x + k * BLK;
         ld[k] = qg[i < 3 * B.nblob ? i : 0];
     }
-    fe[0] = fe[1] = fe[2] = 0.0;
-    if (Fext && (int)threadIdx.x < B.nblob) {
-        const double inv_nb = 1.0 / (double)nb;
-        const double* f = Fext + 3 * (B.p0 + threadIdx.x / nb);
-        fe[0] = f[0] * inv_nb;
-        fe[1] = f[1] * inv_nb;
-        fe[2] = f[2] * inv_nb;
+    after_loads();
+    const bool mine = (int)threadIdx.x < B.nblob;
+    const int j = mine ? (int)threadIdx.x : 0;
+    double fx[3] = {0.0, 0.0, 0.0}, gx[3] = {0.0, 0.0, 0.0};
+    if (Fext) {  // (a kernel argument: uniform over the block)
+        const double* f = Fext + 3 * (B.p0 + j / nb);
+        fx[0] = f[0];
+        fx[1] = f[1];
+        fx[2] = f[2];
     }
-    if (Gblob && (int)threadIdx.x < B.nblob) {
-        const double* gb = Gblob + 3 * (B.p0 * nb + threadIdx.x);
-        fe[0] += gb[0];
-        fe[1] += gb[1];
-        fe[2] += gb[2];
+    if (Gblob) {
+        const double* gb = Gblob + 3 * (B.p0 * nb + j);
+        gx[0] = gb[0];
+        gx[1] = gb[1];
+        gx[2] = gb[2];
     }
-    for (int e = threadIdx.x; e < np; e += BLK) B.r0s[e] = sp.r0[e];
-    for (int e = threadIdx.x; e <= nb; e += BLK) B.adj[e] = sp.adj_start[e];
-    for (int e = threadIdx.x; e < 2 * np; e += BLK) B.adj[nb + 1 + e] = sp.adj_pair[e];
+    // tables (each at least one entry): the first BLK rest lengths and 2 BLK
+    // incidence codes through registers, any beyond (more than 128 pairs) in
+    // loops
+    const int t = threadIdx.x;
+    const double tr0 = sp.r0[t < np ? t : 0];
+    const int tas = sp.adj_start[t <= nb ? t : 0];  // nb <= 64 < BLK
+    const int tap0 = sp.adj_pair[t < 2 * np ? t : 0];
+    const int tap1 = sp.adj_pair[t + BLK < 2 * np ? t + BLK : 0];
+    if (t < np) B.r0s[t] = tr0;
+    if (t <= nb) B.adj[t] = tas;
+    if (t < 2 * np) B.adj[nb + 1 + t] = tap0;
+    if (t + BLK < 2 * np) B.adj[nb + 1 + t + BLK] = tap1;
+    for (int e = t + BLK; e < np; e += BLK) B.r0s[e] = sp.r0[e];
+    for (int e = t + 2 * BLK; e < 2 * np; e += BLK) B.adj[nb + 1 + e] = sp.adj_pair[e];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int i = threadIdx.x + k * BLK;
         if (i < 3 * B.nblob) B.qs[i] = ld[k];
     }
     __syncthreads();
+    const double inv_nb = 1.0 / (double)nb;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) fe[b] = mine ? fx[b] * inv_nb + gx[b] : 0.0;
     return B;
 }
 
@@ -394,14 +420,15 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
     const int nblob = (int)((P - p0 < sp.ppb ? P - p0 : sp.ppb) * sp.nb);
     const bool own = (int)threadIdx.x < nblob;
     const int64_t ib = p0 * sp.nb + threadIdx.x;
-    int tl = 0, rk = 0, off = 0;
-    if (own) {
-        tl = tile_of[ib];
-        rk = rank[ib];
-        off = offs[tl];  // in flight while the block stages its positions
-    }
+    const int64_t ibc = own ? ib : p0 * sp.nb;  // loads without branches
+    const int tl = tile_of[ibc];
+    const int rk = rank[ibc];
+    int off = 0;
     double fe[3];
-    const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe);
+    // the block's positions are requested before the tile's offset, which
+    // waits for the tile; both arrive while the block stages its positions
+    const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe,
+                                       [&] { off = offs[tl]; });
     double F[3];
     int64_t i;
     springs_forces(sp, B, fe, F, &i);
@@ -720,15 +747,19 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
     // start[r] <= k < start[r + 1]
     int rfirst[NR], start[NR + 1];
     {
+        // all offset loads issued before any is used (one round trip)
         const int bx0 = tb.lo[0] / tl.tx, by0 = tb.lo[1] / tl.ty, bz0 = tb.lo[2] / tl.tz;
-        start[0] = 0;
+        int o1[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int dx = r % FX, dy = (r / FX) % FY, dz = r / (FX * FY);
             const int g = tb.box * tl.n + ((bz0 + dz) * tl.nty + by0 + dy) * tl.ntx + bx0 + dx;
             rfirst[r] = offs[g];
-            start[r + 1] = start[r] + (offs[g + 1] - rfirst[r]);
+            o1[r] = offs[g + 1];
         }
+        start[0] = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) start[r + 1] = start[r] + (o1[r] - rfirst[r]);
     }
     const int total = start[NR];
     auto rpos = [&](int k) {  // sorted position of concatenated record k
@@ -748,11 +779,12 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
         for (int b = 0; b < 3; ++b) F0[b] = recf[3 * (size_t)p + b];
     }
     double fm = 0.0;
-    for (int k = threadIdx.x; k < total; k += NT) {
-        const size_t p = k < NT ? 0 : (size_t)rpos(k);
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
-            fm = fmax(fm, fabs((double)(k < NT ? F0[b] : recf[3 * p + b])));
+    for (int b = 0; b < 3; ++b) fm = fmax(fm, fabs((double)F0[b]));
+    for (int k = threadIdx.x + NT; k < total; k += NT) {
+        const size_t p = (size_t)rpos(k);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) fm = fmax(fm, fabs((double)recf[3 * p + b]));
     }
     const double fmx = block_reduce<true>(fm, red);
     // mode 0: the fast fixed-point form (u32 for float, u64 for double)
@@ -948,16 +980,14 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
     // the thread's first record and its blob, loaded once
     RecG<T> r0{};
     int64_t i0 = -1;
-    double q0[3] = {0.0, 0.0, 0.0};  // its position, fetched before the staging
-    if (pos0 >= 0) {
-        r0 = rec[pos0];
-        i0 = perm[pos0];
-        // blob i0 belongs to this record only: no other thread updates it
-        if (q) {
-            q0[0] = q[3 * i0];
-            q0[1] = q[3 * i0 + 1];
-            q0[2] = q[3 * i0 + 2];
-        }
+    double q0[3] = {0.0, 0.0, 0.0};  // its position, fetched with the staging
+    {
+        // loads without branches (an index clamped into the records), so
+        // that nothing waits for them before their first use
+        const int pc = pos0 >= 0 ? pos0 : 0;
+        r0 = rec[pc];
+        const int ic = perm[pc];
+        i0 = pos0 >= 0 ? ic : -1;
     }
     double u0[3] = {0.0, 0.0, 0.0};  // velocity of the first record
     double sv[3] = {0.0, 0.0, 0.0};
@@ -967,10 +997,13 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
 #pragma unroll
     for (int a0 = 0; a0 < 3; a0 += NCS) {
         if (a0 > 0) __syncthreads();  // the previous component's gathers are done
-        if (sr < RP) {
-            // all loads of the thread first, then the LDS stores; row r of
-            // component a is (ey, ez) = (r mod EYA[a], r / EYA[a])
-            T ld[NCS][NR];
+        // all loads of the thread first, then the LDS stores; row r of
+        // component a is (ey, ez) = (r mod EYA[a], r / EYA[a])
+        // (threads beyond the staged rows load row 0 and store nothing:
+        // no branch around the loads)
+        T ld[NCS][NR];
+        {
+            const int srl = sr < RP ? sr : 0;
 #pragma unroll
             for (int c = 0; c < NCS; ++c) {
                 const int a = a0 + c;
@@ -978,13 +1011,25 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
                 const T* va = v + (int64_t)a * N;  // uniform base, 32-bit offsets
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
-                    int r = sr + k * RP;
-                    r = r < rows ? r : sr;
+                    int r = srl + k * RP;
+                    r = r < rows ? r : srl;
                     const int ey = r % EYA[a], ez = r / EYA[a];
                     ld[c][k] = ld32(va, (unsigned)((wrapL(tb.lo[2] - 1 + ez, L) * L +
                                                     wrapL(tb.lo[1] - 1 + ey, L)) * L + gx));
                 }
             }
+        }
+        if (a0 == 0 && q) {
+            // the first record's position, requested once its blob index is
+            // in and the staging loads are on their way (blob i0 belongs to
+            // this record only: no other thread updates it; without a record
+            // blob 0 is read and not used)
+            const int64_t ic = i0 >= 0 ? i0 : 0;
+            q0[0] = q[3 * ic];
+            q0[1] = q[3 * ic + 1];
+            q0[2] = q[3 * ic + 2];
+        }
+        if (sr < RP) {
 #pragma unroll
             for (int c = 0; c < NCS; ++c) {
                 const int a = a0 + c;
