@@ -315,6 +315,12 @@ __device__ __forceinline__ void st32(T* __restrict__ base, unsigned i, const T& 
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = x;
 }
 
+// A hook that does nothing (default of the "after the loads are issued"
+// callbacks).
+struct NoOp {
+    __device__ void operator()() const {}
+};
+
 __device__ __forceinline__ int xcd_remap(int b, int n) {
     const int per = n / 8;
     return (b % 8) * per + b / 8;

@@ -280,10 +280,6 @@ struct SpringsBlk {
     int* adj;      // [nb + 1] incidence starts, then [2 np] (pair << 8 | other)
 };
 
-struct NoOp {
-    __device__ void operator()() const {}
-};
-
 // after_loads runs once the position loads are issued (more loads of the
 // caller, in flight with them).
 template <typename AfterLoads = NoOp>
