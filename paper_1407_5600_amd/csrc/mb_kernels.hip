@@ -936,10 +936,10 @@ struct BinNext {
 // through LDS counts for the 27 tiles around this one (a blob moves less
 // than a tile per step), the rest, and any farther move, with a global
 // atomic each.
-// Float64: registers capped for six waves per SIMD (78 instead of 86, no
-// spills; 128^3: 37.2 against 38.6 us); float32 is bound by its LDS.
+// Float64: registers capped for five waves per SIMD (93, no spills; six
+// waves spill with the column staging below); float32 is bound by its LDS.
 template <typename T, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(BLK, (sizeof(T) == 8 ? 6 : 1))
+__global__ void __launch_bounds__(BLK, (sizeof(T) == 8 ? 5 : 1))
 k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
          const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
          double* __restrict__ u_out, double uscale, double* __restrict__ q, double dt,
@@ -956,14 +956,14 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
     constexpr int EZA[3] = {EZ, EZ, EZ - 1};   // along z
     constexpr int VOFF[4] = {0, EX * EY * EZ, EX * EY * EZ + EX * (EY - 1) * EZ,
                              EX * EY * EZ + EX * (EY - 1) * EZ + EX * EY * (EZ - 1)};
-    // Staging: for float32 fields where EX * EY threads fit in the block
-    // (COLS), thread (sx, sy) takes the x slot sx of the row ey = sy at every
-    // z of the component (the wrapped z offset is uniform over the block, so
-    // each load is one add to the thread's fixed offset: 128^3, 23.5 ->
-    // 21.2 us, against ~18 integer instructions per load for a flattened
-    // row); otherwise rows r = sr + k RP of the flattened (ey, ez) rows (the
-    // float64 kernel, capped at 80 registers, spills with the column form).
-    constexpr bool COLS = EX * EY <= BLK && sizeof(T) == 4;
+    // Staging: where EX * EY threads fit in the block (COLS), thread
+    // (sx, sy) takes the x slot sx of the row ey = sy at every z of the
+    // component (the wrapped z offset is uniform over the block, so each
+    // load is one add to the thread's fixed offset; 128^3: float32 23.5 ->
+    // 21.2 us, float64 34.2 -> 31.7 us, against ~18 integer instructions
+    // per load for a flattened row); otherwise rows r = sr + k RP of the
+    // flattened (ey, ez) rows.
+    constexpr bool COLS = EX * EY <= BLK;
     constexpr int NR = COLS ? EZ : (EY * EZ + RP - 1) / RP;  // loads per component
     __shared__ T vt[NCS == 3 ? VOFF[3] : EX * EY * EZ];
     __shared__ double red[16];
