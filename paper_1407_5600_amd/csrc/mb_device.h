@@ -43,10 +43,11 @@ __device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) {
 // two Newton steps y <- y + y (1/2 - x y^2 / 2) for the root of 1/y^2 - x,
 // each of which squares the relative error (an estimate good to 2^-14
 // ends below the float64 rounding).
+template <int NEWTON = 2>
 __device__ __forceinline__ double rsqrt_nr(double x) {
     double y = __builtin_amdgcn_rsq(x);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NEWTON; ++i) {
         const double r = fma(-(x * y), 0.5 * y, 0.5);
         y = fma(y, r, y);
     }

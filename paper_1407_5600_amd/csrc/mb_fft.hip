@@ -298,10 +298,50 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
     static_assert(EPT % KG == 0, "rounds of the x pass");
     // a wave's lanes share y when L is a multiple of the wave
     constexpr bool UNI = L % WAVE == 0 && NTHR % L == 0;
+    // with UNI, a thread's x (and its neighbours and x box sources) is the
+    // same in every round and its line differs by a constant per round, the
+    // wave's rows are uniform: each load is a uniform row base plus the
+    // thread's fixed x offset
+    [[maybe_unused]] const int xu = tid % L;
+    [[maybe_unused]] const int line0 = UNI ? __builtin_amdgcn_readfirstlane(tid / L) : 0;
+    [[maybe_unused]] const unsigned ox = (unsigned)xu * (unsigned)sizeof(T);
+    [[maybe_unused]] const unsigned oxm = (unsigned)(xu == 0 ? L - 1 : xu - 1) * (unsigned)sizeof(T);
+    [[maybe_unused]] const unsigned oxp = (unsigned)(xu == L - 1 ? 0 : xu + 1) * (unsigned)sizeof(T);
+    [[maybe_unused]] AxisSrc bxu{};
+    if constexpr (UNI && BOX) bxu = box_src_x(tl, xu);
 #pragma unroll
     for (int k0 = 0; k0 < EPT; k0 += KG) {
         T vc[KG][2], vn[KG][2][6], fv[KG][2];
         T eb[KG][2][4][2];
+        if constexpr (UNI && KG == 1) {
+            const int line = line0 + k0 * (NTHR / L);
+            const char* vb = reinterpret_cast<const char*>(v);
+            const char* fb = reinterpret_cast<const char*>(f);
+            auto at = [](const char* base, int row, unsigned o) {
+                return *reinterpret_cast<const T*>(base + (size_t)row * sizeof(T) + o);
+            };
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int y = y0 + 2 * line + hh;
+                const int row = cbase + (z * L + y) * L;
+                if (!BOX) fv[0][hh] = at(fb, row, ox);
+                if (!STEADY) {
+                    const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+                    vc[0][hh] = at(vb, row, ox);
+                    vn[0][hh][0] = at(vb, row, oxm);
+                    vn[0][hh][1] = at(vb, row, oxp);
+                    vn[0][hh][2] = at(vb, cbase + (z * L + ym) * L, ox);
+                    vn[0][hh][3] = at(vb, cbase + (z * L + yp) * L, ox);
+                    vn[0][hh][4] = at(vb, cbase + (zm * L + y) * L, ox);
+                    vn[0][hh][5] = at(vb, cbase + (zp * L + y) * L, ox);
+                }
+            }
+            if constexpr (BOX) {
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh)
+                    box_entries(Ec, bxu, box_src_y(tl, y0 + 2 * line + hh), bz, eb[0][hh]);
+            }
+        } else {
 #pragma unroll
         for (int g = 0; g < KG; ++g) {
             const int e = tid + (k0 + g) * NTHR;
@@ -333,6 +373,7 @@ k_x_fwd(const T* __restrict__ v, const T* __restrict__ f, Tiles tl,
                     box_entries(Ec, bx, box_src_y(tl, yu), bz, eb[g][hh]);
                 }
             }
+        }
         }
 #pragma unroll
         for (int g = 0; g < KG; ++g) {

@@ -276,7 +276,7 @@ struct SpringsBlk {
     int npart;     // particles of the block
     int nblob;     // blobs of the block (thread j < nblob owns blob p0 nb + j)
     double* qs;    // [ppb * nb][3] positions
-    double* r0s;   // [np] rest lengths
+    double* r0s;   // [np] rest lengths times r0scale
     int* adj;      // [nb + 1] incidence starts, then [2 np] (pair << 8 | other)
 };
 
@@ -288,7 +288,7 @@ __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
                                                     const double* __restrict__ Fext,
                                                     const double* __restrict__ Gblob,
                                                     int64_t P, double* smem,
-                                                    double fe[3],
+                                                    double fe[3], double r0scale,
                                                     AfterLoads after_loads = NoOp{}) {
     SpringsBlk B;
     const int nb = sp.nb, np = sp.npairs;
@@ -334,11 +334,11 @@ __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
     const int tas = sp.adj_start[t <= nb ? t : 0];  // nb <= 64 < BLK
     const int tap0 = sp.adj_pair[t < 2 * np ? t : 0];
     const int tap1 = sp.adj_pair[t + BLK < 2 * np ? t + BLK : 0];
-    if (t < np) B.r0s[t] = tr0;
+    if (t < np) B.r0s[t] = r0scale * tr0;
     if (t <= nb) B.adj[t] = tas;
     if (t < 2 * np) B.adj[nb + 1 + t] = tap0;
     if (t + BLK < 2 * np) B.adj[nb + 1 + t + BLK] = tap1;
-    for (int e = t + BLK; e < np; e += BLK) B.r0s[e] = sp.r0[e];
+    for (int e = t + BLK; e < np; e += BLK) B.r0s[e] = r0scale * sp.r0[e];
     for (int e = t + 2 * BLK; e < 2 * np; e += BLK) B.adj[nb + 1 + e] = sp.adj_pair[e];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -352,6 +352,11 @@ __device__ __forceinline__ SpringsBlk springs_stage(const SpringsDev& sp,
     return B;
 }
 
+// NEWTON: Newton steps of the reciprocal square root (two for float64
+// results; one for forces that are rounded to float32 records, whose
+// relative error it leaves far below float32 rounding).  B.r0s holds k r0
+// (springs_stage with r0scale = k).
+template <int NEWTON = 2>
 __device__ __forceinline__ void springs_forces(const SpringsDev& sp, const SpringsBlk& B,
                                                const double fe[3], double F[3],
                                                int64_t* blob) {
@@ -372,8 +377,8 @@ __device__ __forceinline__ void springs_forces(const SpringsDev& sp, const Sprin
         const double* qo = qp + 3 * o;
         const double dx = qo[0] - qx, dy = qo[1] - qy, dz = qo[2] - qz;
         // k (|d| - r0) / |d| = k - k r0 / |d|
-        const double inv_len = rsqrt_nr(dx * dx + dy * dy + dz * dz);
-        const double s = fma(-(sp.k * B.r0s[code >> 8]), inv_len, sp.k);
+        const double inv_len = rsqrt_nr<NEWTON>(dx * dx + dy * dy + dz * dz);
+        const double s = fma(-B.r0s[code >> 8], inv_len, sp.k);
         fx += s * dx;
         fy += s * dy;
         fz += s * dz;
@@ -385,7 +390,7 @@ __device__ __forceinline__ void springs_forces(const SpringsDev& sp, const Sprin
         int codes[DMAX];
 #pragma unroll
         for (int x = 0; x < DMAX; ++x) codes[x] = e0 + x < e1 ? inc[e0 + x] : -1;
-#pragma unroll 4
+#pragma clang loop unroll(full)
         for (int x = 0; x < DMAX; ++x)
             if (codes[x] >= 0) pair(codes[x]);
     } else {
@@ -423,11 +428,11 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
     double fe[3];
     // the block's positions are requested before the tile's offset, which
     // waits for the tile; both arrive while the block stages its positions
-    const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe,
+    const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe, sp.k,
                                        [&] { off = offs[tl]; });
     double F[3];
     int64_t i;
-    springs_forces(sp, B, fe, F, &i);
+    springs_forces<sizeof(T) == 4 ? 1 : 2>(sp, B, fe, F, &i);
     if (i >= 0) {
         const Geom g = blob_geom(B.qs, threadIdx.x, inv_h, L);
         write_record<T>(rec, recf, perm, (int64_t)off + rk, i, g, F, inv_vol);
@@ -451,7 +456,7 @@ k_springs(SpringsDev sp, const double* __restrict__ q,
           double* __restrict__ Fout) {
     extern __shared__ double smem[];
     double fe[3];
-    const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe);
+    const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe, sp.k);
     double F[3];
     int64_t i;
     springs_forces(sp, B, fe, F, &i);
@@ -482,7 +487,7 @@ k_springs_adjoint(SpringsDev sp, const double* __restrict__ q,
     extern __shared__ double smem[];
     __shared__ double red[16];
     double fe[3];
-    const SpringsBlk B = springs_stage(sp, q, nullptr, nullptr, P, smem, fe);
+    const SpringsBlk B = springs_stage(sp, q, nullptr, nullptr, P, smem, fe, 1.0);
     // Fbar of the block's blobs and the per-pair sums after the positions
     double* fb = B.qs + 3 * sp.ppb * sp.nb + sp.npairs + 
                  (sp.nb + 1 + 2 * sp.npairs + 1) / 2;
