@@ -941,10 +941,16 @@ struct BinNext {
 // through LDS counts for the 27 tiles around this one (a blob moves less
 // than a tile per step), the rest, and any farther move, with a global
 // atomic each.
+// Threads: one per four cells of the tile, at least BLK and at most 512 (the
+// 16x16x8 family: one record per thread at these densities).
 // Float64: registers capped for five waves per SIMD (93, no spills; six
 // waves spill with the column staging below); float32 is bound by its LDS.
+constexpr int interp_threads(int cells) {
+    return cells / 4 < BLK ? BLK : (cells / 4 > 512 ? 512 : cells / 4);
+}
+
 template <typename T, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(BLK, (sizeof(T) == 8 ? 5 : 1))
+__global__ void __launch_bounds__(interp_threads(TX * TY * TZ), (sizeof(T) == 8 ? 5 : 1))
 k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
          const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
          double* __restrict__ u_out, double uscale, double* __restrict__ q, double dt,
@@ -954,8 +960,9 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
     // along x; the components' regions follow one another in vt.
     constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3;
     constexpr int TV = TX * TY * TZ;
-    constexpr int RP = BLK / EX;             // rows staged per pass
-    constexpr int CPT = (TV + BLK - 1) / BLK; // own cells per thread
+    constexpr int NT = interp_threads(TV);
+    constexpr int RP = NT / EX;              // rows staged per pass
+    constexpr int CPT = (TV + NT - 1) / NT;  // own cells per thread
     constexpr int NCS = sizeof(T) == 4 ? 3 : 1;  // components staged together
     constexpr int EYA[3] = {EY, EY - 1, EY};   // rows along y per component
     constexpr int EZA[3] = {EZ, EZ, EZ - 1};   // along z
@@ -968,10 +975,10 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
     // 21.2 us, float64 34.2 -> 31.7 us, against ~18 integer instructions
     // per load for a flattened row); otherwise rows r = sr + k RP of the
     // flattened (ey, ez) rows.
-    constexpr bool COLS = EX * EY <= BLK;
+    constexpr bool COLS = EX * EY <= NT;
     constexpr int NR = COLS ? EZ : (EY * EZ + RP - 1) / RP;  // loads per component
     __shared__ T vt[NCS == 3 ? VOFF[3] : EX * EY * EZ];
-    __shared__ double red[16];
+    __shared__ double red[4 * (NT / WAVE)];
     __shared__ int lcount[27];
     __shared__ int lbase[27];
     const TileBox tb = tile_box(tl, L);
@@ -1082,10 +1089,10 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             }
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < total; k += BLK) {
+        for (int k = threadIdx.x; k < total; k += NT) {
             const int pos = first + k;
             RecG<T> r = r0;
-            if (k >= BLK) r = rec[pos];
+            if (k >= NT) r = rec[pos];
             double ua[NCS];
 #pragma unroll
             for (int c = 0; c < NCS; ++c) {
@@ -1113,7 +1120,7 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
                 }
                 ua[c] = uscale * (double)acc;
             }
-            if (k < BLK) {
+            if (k < NT) {
 #pragma unroll
                 for (int c = 0; c < NCS; ++c) u0[a0 + c] = ua[c];  // written at the end
             } else {
@@ -1133,7 +1140,7 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
                 const int str = a == 0 ? 1 : (a == 1 ? EX : EX * eya);
 #pragma unroll
                 for (int j = 0; j < CPT; ++j) {
-                    const int i = threadIdx.x + j * BLK;
+                    const int i = threadIdx.x + j * NT;
                     if (i < TV) {
                         const int x = i % TX + 1;
                         const int y = (i / TX) % TY + 1;
@@ -1192,7 +1199,7 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
         // this thread above): counted through the same LDS slots, their
         // rank within the slot stored and completed below (a global atomic
         // each only for a move beyond the neighbour tiles)
-        for (int k = threadIdx.x + BLK; k < total; k += BLK) {
+        for (int k = threadIdx.x + NT; k < total; k += NT) {
             const int64_t i = perm[first + k];
             const Geom gk = blob_geom(q, i, inv_h, L);
             const int t = tb.box * tl.n + tile_linear(gk.c, tl);
@@ -1224,7 +1231,7 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             bn.tile_of[i0] = tnew;
             bn.rank[i0] = slot >= 0 ? lbase[slot] + rk : rk;
         }
-        for (int k = threadIdx.x + BLK; k < total; k += BLK) {
+        for (int k = threadIdx.x + NT; k < total; k += NT) {
             const int64_t i = perm[first + k];
             int tc[3];  // the tile written above, back to its slot
             int t = bn.tile_of[i] - tb.box * tl.n;
@@ -1250,8 +1257,8 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
 #pragma unroll
         for (int j = 0; j < CPT; ++j) dmax = fmax(dmax, fabs(dv[j]) * inv_h);
         double w4[4] = {wave_sum(sv[0]), wave_sum(sv[1]), wave_sum(sv[2]), wave_max(dmax)};
-        constexpr int NW = BLK / WAVE;
-        static_assert(4 * NW <= 16, "reduction scratch");
+        constexpr int NW = NT / WAVE;
+        static_assert(4 * NW <= 4 * (NT / WAVE), "reduction scratch");
         const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
         if (lane == 0) {
 #pragma unroll
@@ -1714,7 +1721,9 @@ hipError_t interpolate(mb_grid* g, int64_t M, const T* v, double* u_out,
     if (bin_next && q_update) bn = BinNext{g->d_count, g->d_tile, g->d_rank};
     const bool ok = with_tile_shape(g->tiles, [&](auto X, auto Y, auto Z) {
         MB_LAUNCH(g, kid, s, (k_interp<T, decltype(X)::value, decltype(Y)::value, decltype(Z)::value>),
-                  g->tiles.n * g->tiles.nbox, BLK, 0, rec_geo<T>(g), g->d_perm,
+                  g->tiles.n * g->tiles.nbox,
+                  interp_threads(decltype(X)::value * decltype(Y)::value * decltype(Z)::value),
+                  0, rec_geo<T>(g), g->d_perm,
                   g->d_offs, g->L, g->tiles, v, u_out, uscale, q_update, g->d.dt,
                   1.0 / g->d.h, part, bn);
     });
