@@ -72,7 +72,21 @@ Tiles make_tiles(int L, int nbox, int tx, int ty, int tz) {
     t.n = t.ntx * t.nty * t.ntz;
     t.remap = (t.n % 8 == 0 && t.n >= 64) ? 1 : 0;
     t.nbox = nbox;
+    t.lfx = t.lfy = t.lfz = 0;
+    t.nbx = t.ntx;
+    t.nby = t.nty;
     return t;
+}
+
+// Groups tiles t by the box tiles b built from them (their extents
+// multiples of t's): the numbering of t becomes box-tile major.
+void link_box_tiles(Tiles& t, const Tiles& b) {
+    auto lg = [](int r) { int l = 0; while ((1 << l) < r) ++l; return l; };
+    t.lfx = lg(b.tx / t.tx);
+    t.lfy = lg(b.ty / t.ty);
+    t.lfz = lg(b.tz / t.tz);
+    t.nbx = b.ntx;
+    t.nby = b.nty;
 }
 
 // Box tiles of the spreading for binning tiles t: each extent below 16 is
@@ -358,6 +372,7 @@ mb_status mb_grid_create_batch(const mb_grid_desc* desc, int32_t nbox, mb_grid**
     g->nblk_x = fft_x_blocks(d.L, d.precision);
     g->tiles = default_tiles(d.L, nbox);
     g->btiles = make_box_tiles(d.L, g->tiles);
+    link_box_tiles(g->tiles, g->btiles);
     g->rec_size = record_size(d.precision);
     // springs blocks hold at least one particle of at least one blob
     g->force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
@@ -1048,6 +1063,7 @@ static mb_status set_tiles(mb_grid* g, int tx, int ty, int tz) {
     // the counts start from zero under the new numbering
     g->tiles = make_tiles(g->L, g->tiles.nbox, tx, ty, tz);
     g->btiles = make_box_tiles(g->L, g->tiles);
+    link_box_tiles(g->tiles, g->btiles);
     set_scan_blocks(g);
     e = zero_words(g->d_count, (size_t)g->ntiles_cap * g->tiles.nbox, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -1241,6 +1257,7 @@ mb_status mb_step_noalloc(const mb_grid_desc* desc, const mb_springs* sp, int64_
     g.nblk_x = fft_x_blocks(d.L, d.precision);
     g.tiles = default_tiles(d.L, 1);
     g.btiles = make_box_tiles(d.L, g.tiles);
+    link_box_tiles(g.tiles, g.btiles);
     g.rec_size = record_size(d.precision);
     g.force_blocks_cap = (int)std::max<int64_t>(d.max_blobs, 1);
     g.ws_owned = false;

@@ -52,13 +52,22 @@ struct SpringsDev {
 };
 
 // Tile geometry for spreading and interpolation.
+// Tiles are numbered box-tile major: the 2^(lfx+lfy+lfz) tiles of one
+// spreading box tile (2^lfx along x, ...) are consecutive, x fastest within
+// it, and the box tiles (nbx x nby x ...) follow one another x fastest, so a
+// box tile's blobs form one range of the tile-sorted records.  For the box
+// tiles themselves (and any tiles not grouped) lfx = lfy = lfz = 0, nbx =
+// ntx, nby = nty: plain x-fastest order.
 struct Tiles {
     int tx, ty, tz;     // tile extent in cells
     int ntx, nty, ntz;  // tiles per axis
     int n;              // tiles per box
     int remap;          // 1: XCD-aware block -> tile mapping
     int nbox;           // boxes of the grid (a batch of equal boxes)
+    int lfx, lfy, lfz;  // log2 of the tiles per box tile along each axis
+    int nbx, nby;       // box tiles along x and y
 };
+
 
 // Tile shapes (tx, ty, tz) with instantiated spreading and interpolation
 // kernels: the LDS of the float32 interpolation (three components of the

@@ -77,11 +77,33 @@ __device__ __forceinline__ Geom blob_geom(const double* __restrict__ q,
     return g;
 }
 
+// Index of the tile with tile coordinates tc (box-tile major, see Tiles).
+__device__ __forceinline__ int tile_index(const int tc[3], const Tiles& tl) {
+    const int bt = ((tc[2] >> tl.lfz) * tl.nby + (tc[1] >> tl.lfy)) * tl.nbx + (tc[0] >> tl.lfx);
+    const int lx = tc[0] & ((1 << tl.lfx) - 1), ly = tc[1] & ((1 << tl.lfy) - 1),
+              lz = tc[2] & ((1 << tl.lfz) - 1);
+    return (bt << (tl.lfx + tl.lfy + tl.lfz)) + (((lz << tl.lfy) + ly) << tl.lfx) + lx;
+}
+// Tile coordinates of tile index t (the inverse of tile_index).
+__device__ __forceinline__ void tile_coords(int t, const Tiles& tl, int tc[3]) {
+    const int nl = tl.lfx + tl.lfy + tl.lfz;
+    const int loc = t & ((1 << nl) - 1);
+    int bt = t >> nl;
+    const int bx = bt % tl.nbx;
+    bt /= tl.nbx;
+    const int by = bt % tl.nby;
+    const int bz = bt / tl.nby;
+    tc[0] = (bx << tl.lfx) + (loc & ((1 << tl.lfx) - 1));
+    tc[1] = (by << tl.lfy) + ((loc >> tl.lfx) & ((1 << tl.lfy) - 1));
+    tc[2] = (bz << tl.lfz) + (loc >> (tl.lfx + tl.lfy));
+}
+
 // Tile of a cell: blobs are sorted by the tiles of spreading and
-// interpolation (extents powers of two), tile index x fastest.
+// interpolation (extents powers of two).
 __device__ __forceinline__ int tile_linear(const int c[3], const Tiles& tl) {
-    return ((c[2] >> (__ffs(tl.tz) - 1)) * tl.nty + (c[1] >> (__ffs(tl.ty) - 1))) * tl.ntx +
-           (c[0] >> (__ffs(tl.tx) - 1));
+    const int tc[3] = {c[0] >> (__ffs(tl.tx) - 1), c[1] >> (__ffs(tl.ty) - 1),
+                       c[2] >> (__ffs(tl.tz) - 1)};
+    return tile_index(tc, tl);
 }
 
 // 1 when any of the n values is NaN or infinite.
@@ -657,12 +679,11 @@ __device__ __forceinline__ TileBox tile_box(const Tiles& t, int L) {
     if (t.remap) local = xcd_remap(local, t.n);
     tb.tile = local;
     tb.gt = tb.box * t.n + local;
-    const int ix = local % t.ntx;
-    const int iy = (local / t.ntx) % t.nty;
-    const int iz = local / (t.ntx * t.nty);
-    tb.lo[0] = ix * t.tx;
-    tb.lo[1] = iy * t.ty;
-    tb.lo[2] = iz * t.tz;
+    int tc[3];
+    tile_coords(local, t, tc);
+    tb.lo[0] = tc[0] * t.tx;
+    tb.lo[1] = tc[1] * t.ty;
+    tb.lo[2] = tc[2] * t.tz;
     tb.full[0] = t.tx == L;
     tb.full[1] = t.ty == L;
     tb.full[2] = t.tz == L;
@@ -743,33 +764,16 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
     const TileBox tb = tile_box(btl, L);
     const int tile = tb.tile;
     for (int i = threadIdx.x; i < EV; i += NT) acc[i] = 0ull;
-    // the record ranges of the binning tiles making up this box tile,
-    // concatenated: record k < total lies in range r with
-    // start[r] <= k < start[r + 1]
-    int rfirst[NR], start[NR + 1];
+    // the records of this box tile: its binning tiles are numbered
+    // consecutively (box-tile major), so their records form one range
+    int first, total;
     {
-        // all offset loads issued before any is used (one round trip)
-        const int bx0 = tb.lo[0] / tl.tx, by0 = tb.lo[1] / tl.ty, bz0 = tb.lo[2] / tl.tz;
-        int o1[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int dx = r % FX, dy = (r / FX) % FY, dz = r / (FX * FY);
-            const int g = tb.box * tl.n + ((bz0 + dz) * tl.nty + by0 + dy) * tl.ntx + bx0 + dx;
-            rfirst[r] = offs[g];
-            o1[r] = offs[g + 1];
-        }
-        start[0] = 0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) start[r + 1] = start[r] + (o1[r] - rfirst[r]);
+        const int tc[3] = {tb.lo[0] / tl.tx, tb.lo[1] / tl.ty, tb.lo[2] / tl.tz};
+        const int g = tb.box * tl.n + tile_index(tc, tl);  // its first binning tile
+        first = offs[g];
+        total = offs[g + NR] - first;
     }
-    const int total = start[NR];
-    auto rpos = [&](int k) {  // sorted position of concatenated record k
-        int p = rfirst[0] + k;
-#pragma unroll
-        for (int r = 1; r < NR; ++r)
-            if (k >= start[r]) p = rfirst[r] + (k - start[r]);
-        return p;
-    };
+    auto rpos = [&](int k) { return first + k; };  // sorted position of record k
     // this thread's first record is kept in registers for all components
     RecG<T> r0{};
     T F0[3] = {T(0), T(0), T(0)};
@@ -1221,7 +1225,7 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
                     if (tc[b] < 0) tc[b] += nt[b];
                     if (tc[b] >= nt[b]) tc[b] -= nt[b];
                 }
-                const int t = tb.box * tl.n + (tc[2] * tl.nty + tc[1]) * tl.ntx + tc[0];
+                const int t = tb.box * tl.n + tile_index(tc, tl);
                 base = atomicAdd(&bn.count[t], c);
             }
             lbase[threadIdx.x] = base;
@@ -1234,11 +1238,7 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
         for (int k = threadIdx.x + NT; k < total; k += NT) {
             const int64_t i = perm[first + k];
             int tc[3];  // the tile written above, back to its slot
-            int t = bn.tile_of[i] - tb.box * tl.n;
-            tc[0] = t % tl.ntx;
-            t /= tl.ntx;
-            tc[1] = t % tl.nty;
-            tc[2] = t / tl.nty;
+            tile_coords(bn.tile_of[i] - tb.box * tl.n, tl, tc);
             int sl = 0;
 #pragma unroll
             for (int b = 2; b >= 0; --b) {
