@@ -199,7 +199,7 @@ WsLayout ws_layout(const mb_grid_desc& d, int nbox) {
     sz[WsLayout::REC] = (size_t)cap * record_size(d.precision);
     sz[WsLayout::U] = (size_t)cap * 3 * sizeof(double);
     sz[WsLayout::FPART] = (size_t)cap * 3 * sizeof(double);  // one springs block per blob at most
-    sz[WsLayout::FLAG] = sizeof(int);
+    sz[WsLayout::FLAG] = 2 * sizeof(int);
     sz[WsLayout::QINT] = (size_t)cap * 3 * sizeof(double);
     sz[WsLayout::PINT] = (size_t)cap * 3 * sizeof(double);  // particles <= blobs
     sz[WsLayout::ORDER] = (size_t)cap * sizeof(int);
@@ -278,7 +278,9 @@ mb_status enter(mb_grid* g) {
 }
 
 // Result of a call whose launches gave e: with check_finite, waits for the
-// stream and reports (then clears) the non-finite flag its kernels set.
+// stream and reports (then clears) the flag its kernels set: bit 1 a
+// non-finite input, bit 2 a springs block that gave up waiting for the
+// tile offsets (a device failure).
 mb_status finish(mb_grid* g, hipError_t e, hipStream_t s) {
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? MB_ERR_NOMEM : MB_ERR_DEVICE;
     if (!g->d.check_finite) return MB_OK;
@@ -286,7 +288,7 @@ mb_status finish(mb_grid* g, hipError_t e, hipStream_t s) {
     e = hipMemcpyAsync(&flag, g->d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && flag) e = zero_words(g->d_flag, 1, s);
-    if (e != hipSuccess) return MB_ERR_DEVICE;
+    if (e != hipSuccess || (flag & 2)) return MB_ERR_DEVICE;
     return flag ? MB_ERR_NONFINITE : MB_OK;
 }
 
@@ -641,8 +643,9 @@ static hipError_t step_once(mb_grid* g, const SpringsDev& sd, int64_t P, int64_t
     // sums (forces, momentum, max |Dv|) are formed only when diag is set
     // (the step whose diagnostics are returned).
     auto forces = [&](const double* x, bool counted, bool sums) {
-        hipError_t e = bin_blobs<T>(g, M, x, s, counted);
-        if (e == hipSuccess) e = scatter_springs<T>(g, sd, P, x, Fext, s, Gblob, sums);
+        const bool fuse = fused_scan_ok(g, s);  // the scan in the springs kernel
+        hipError_t e = bin_blobs<T>(g, M, x, s, counted, !fuse);
+        if (e == hipSuccess) e = scatter_springs<T>(g, sd, P, x, Fext, s, Gblob, sums, fuse);
         if (e == hipSuccess) e = spread_boxes<T>(g, s);
         if (e == hipSuccess && ffluid) e = fold_boxes<T>(g, ff, s, ffluid);
         return e;

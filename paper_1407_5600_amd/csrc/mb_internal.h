@@ -107,7 +107,10 @@ struct mb_grid {
     void* ws;           // null until a workspace is set (external_workspace)
     size_t ws_bytes;
     bool ws_owned;      // allocated by the library (freed at destroy)
-    int* d_flag;        // non-finite flag (check_finite)
+    int* d_flag;        // [0] non-finite flag (check_finite; bit 2: a springs
+                        // block gave up waiting for the offsets), [1] the
+                        // fused scan's published launch number
+    uint32_t scan_epoch;  // launches of the springs kernel with the fused scan
     double* d_qint;     // [max_blobs][3] positions in the step calls' particle order
     double* d_pint;     // [max_blobs][3] per-particle forces, then velocities, same order
     int* d_order;       // [max_blobs] caller's particle of each internal particle
@@ -187,9 +190,11 @@ hipError_t zero_words(void* p, size_t n, hipStream_t s);
 // Tile, rank and counting sort of the blobs at q; with counted the counts,
 // tiles and ranks are already in place (the previous step's interpolation
 // binned these positions) and only the scan runs.
+// scan: also the scan of the counts into offsets (else the springs kernel
+// of the step does it: scatter_springs with scan).
 template <typename T>
 hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s,
-                     bool counted = false);
+                     bool counted = false, bool scan = true);
 // Records of the binned blobs with forces F scaled by fscale (h^-3 when
 // fscale <= 0: a force density).
 template <typename T>
@@ -199,10 +204,19 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
 inline int* finite_flag(mb_grid* g) { return g->d.check_finite ? g->d_flag : nullptr; }
 // Springs and records; force_sums: also the per-block sums of the blob
 // forces read by the diagnostics.
+// scan: block 0 of the kernel first scans the tile counts (left by the
+// binning, bin_blobs with scan = false) into the offsets the others wait for;
+// only where fused_scan_ok.
 template <typename T>
 hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
                            const double* q, const double* Fext, hipStream_t s,
-                           const double* Gblob = nullptr, bool force_sums = true);
+                           const double* Gblob = nullptr, bool force_sums = true,
+                           bool scan = false);
+// The scan can ride in the springs kernel: a single scan block's worth of
+// tiles and a stream not being captured (a captured launch would replay its
+// launch number; d_flag[1] is zeroed with the workspace, launch numbers
+// start at 1).
+bool fused_scan_ok(mb_grid* g, hipStream_t s);
 hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
                          const double* Fext, double* F, hipStream_t s,
                          mb_grid* timing_grid, const double* Gblob = nullptr);

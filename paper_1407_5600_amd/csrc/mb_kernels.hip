@@ -245,6 +245,61 @@ k_scan_apply(int* __restrict__ count, int64_t n, const int* __restrict__ bsum,
     if (base + SCAN_TILE >= n && threadIdx.x == 0) offs[n] = off + total;
 }
 
+// Exclusive scan of n <= BLK * SCAN_ITEMS tile counts into offs (offs[n]
+// = their total) by one block of BLK threads, the counts reset to zero:
+// thread t takes the counts [t K, t K + K) in registers (K = ceil(n / BLK)),
+// a wave scan of the thread sums and the sums of the waves before (wsum,
+// BLK / WAVE ints of LDS) give its exclusive prefix.
+__device__ void block_scan_counts(int* __restrict__ count, int n, int* __restrict__ offs,
+                                  int* wsum) {
+    const int t = threadIdx.x, lane = t % WAVE, wave = t / WAVE;
+    const int K = (n + BLK - 1) / BLK;
+    int c[SCAN_ITEMS];
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int idx = t * K + j;
+        c[j] = (j < K && idx < n) ? count[idx] : 0;
+        sum += c[j];
+    }
+    int x = sum;  // inclusive scan over the wave
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == WAVE - 1) wsum[wave] = x;
+    __syncthreads();
+    int run = x - sum, total = 0;
+#pragma unroll
+    for (int w = 0; w < BLK / WAVE; ++w) {
+        if (w < wave) run += wsum[w];
+        total += wsum[w];
+    }
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int idx = t * K + j;
+        if (j < K && idx < n) {
+            offs[idx] = run;
+            count[idx] = 0;
+        }
+        run += c[j];
+    }
+    if (t == 0) offs[n] = total;
+}
+
+// Spins (thread 0) until *flag == want, reading it where all XCDs see the
+// same value; gives up after ~2^22 polls (about half a second) and returns
+// false, so that a wait never hangs.
+__device__ bool wait_flag(const int* flag, int want) {
+    for (int it = 0; it < (1 << 22); ++it) {
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want)
+            return true;
+        __builtin_amdgcn_s_sleep(4);
+    }
+    return false;
+}
+
 // Writes the records of blob i at sorted position pos (recf may be null:
 // no forces).
 template <typename T>
@@ -433,13 +488,26 @@ __global__ void __launch_bounds__(BLK)
 k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
                   const double* __restrict__ Fext, const double* __restrict__ Gblob,
                   int64_t P, double inv_h, int L,
-                  double inv_vol, const int* __restrict__ offs,
+                  double inv_vol, int* __restrict__ offs,
                   const int* __restrict__ tile_of, const int* __restrict__ rank,
                   RecG<T>* __restrict__ rec, T* __restrict__ recf, int* __restrict__ perm,
-                  double* __restrict__ fpart, int* __restrict__ flag) {
+                  double* __restrict__ fpart, int* __restrict__ flag, int* __restrict__ count,
+                  int scan_n, int* __restrict__ sflag, int epoch, int* __restrict__ err) {
     extern __shared__ double smem[];
     __shared__ double red[16 * 3];
+    __shared__ int scan_ok;
     const int64_t p0 = (int64_t)blockIdx.x * sp.ppb;
+    // scan_n > 0: block 0 first scans the tile counts into offs (there is
+    // then no scan kernel ahead of this one) and publishes them by setting
+    // *sflag = epoch after a device-scope fence; every block reads its
+    // offsets only after seeing that (block 0 is dispatched first, so the
+    // others' bounded wait ends)
+    if (scan_n > 0 && blockIdx.x == 0) {
+        block_scan_counts(count, scan_n, offs, reinterpret_cast<int*>(red));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // offsets out of this XCD's L2
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(sflag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     const int nblob = (int)((P - p0 < sp.ppb ? P - p0 : sp.ppb) * sp.nb);
     const bool own = (int)threadIdx.x < nblob;
     const int64_t ib = p0 * sp.nb + threadIdx.x;
@@ -451,10 +519,21 @@ k_springs_scatter(SpringsDev sp, const double* __restrict__ q,
     // the block's positions are requested before the tile's offset, which
     // waits for the tile; both arrive while the block stages its positions
     const SpringsBlk B = springs_stage(sp, q, Fext, Gblob, P, smem, fe, sp.k,
-                                       [&] { off = offs[tl]; });
+                                       [&] { if (scan_n == 0) off = offs[tl]; });
     double F[3];
     int64_t i;
     springs_forces<sizeof(T) == 4 ? 1 : 2>(sp, B, fe, F, &i);
+    if (scan_n > 0) {
+        // the offsets as block 0 left them in memory (past any stale copy
+        // in this XCD's L2)
+        if (threadIdx.x == 0) scan_ok = wait_flag(sflag, epoch);
+        __syncthreads();
+        if (!scan_ok) {
+            if (threadIdx.x == 0) atomicOr(err, 2);
+            i = -1;  // no offsets: no records written (the error bit is set)
+        }
+        off = __hip_atomic_load(&offs[tl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (i >= 0) {
         const Geom g = blob_geom(B.qs, threadIdx.x, inv_h, L);
         write_record<T>(rec, recf, perm, (int64_t)off + rk, i, g, F, inv_vol);
@@ -1492,7 +1571,8 @@ static void scan_tiles(mb_grid* g, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s, bool counted) {
+hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s, bool counted,
+                     bool scan) {
     if (M > 0 && !counted) {
         // the previous sorted order, when it is a permutation of these blobs
         const int* order = g->perm_m == M ? g->d_perm : nullptr;
@@ -1500,7 +1580,7 @@ hipError_t bin_blobs(mb_grid* g, int64_t M, const double* q, hipStream_t s, bool
                   M / g->tiles.nbox, 1.0 / g->d.h, g->L, g->tiles, g->d_count, g->d_tile,
                   g->d_rank);
     }
-    scan_tiles(g, s);
+    if (scan) scan_tiles(g, s);
     return hipGetLastError();
 }
 
@@ -1541,16 +1621,36 @@ hipError_t scatter_records(mb_grid* g, int64_t M, const double* q,
 template <typename T>
 hipError_t scatter_springs(mb_grid* g, const SpringsDev& sp, int64_t P,
                            const double* q, const double* Fext, hipStream_t s,
-                           const double* Gblob, bool force_sums) {
+                           const double* Gblob, bool force_sums, bool scan) {
     const int64_t M = P * sp.nb;
-    if (M == 0) return hipSuccess;
+    if (M == 0) {
+        if (scan) scan_tiles(g, s);
+        return hipGetLastError();
+    }
     const double h = g->d.h;
+    int scan_n = 0, epoch = 0;
+    if (scan) {
+        scan_n = g->tiles.n * g->tiles.nbox;
+        epoch = (int)(++g->scan_epoch & 0x7fffffff);
+        if (epoch == 0) epoch = (int)(++g->scan_epoch & 0x7fffffff);
+    }
     MB_LAUNCH(g, K_SPRINGS_SCATTER, s, k_springs_scatter<T>, springs_blocks(sp, P), BLK,
               springs_lds(sp), sp, q, Fext, Gblob, P, 1.0 / h, g->L, 1.0 / (h * h * h), g->d_offs,
               g->d_tile, g->d_rank, rec_geo<T>(g), rec_force<T>(g), g->d_perm,
-              force_sums ? g->d_force_part : nullptr, finite_flag(g));
+              force_sums ? g->d_force_part : nullptr, finite_flag(g), g->d_count, scan_n,
+              g->d_flag + 1, epoch, g->d_flag);
     g->perm_m = M;
     return hipGetLastError();
+}
+
+bool fused_scan_ok(mb_grid* g, hipStream_t s) {
+    if (g->nscan != 1) return false;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return st == hipStreamCaptureStatusNone;
 }
 
 hipError_t spring_forces(const SpringsDev& sp, int64_t P, const double* q,
@@ -1608,7 +1708,7 @@ hipError_t init_workspace(mb_grid* g, hipStream_t s) {
     if (e == hipSuccess) e = zero_words(g->d_count, nt, s);
     if (e == hipSuccess) e = zero_words(g->d_tile_part, nt * 4 * 2, s);
     if (e == hipSuccess) e = zero_words(g->d_force_part, (size_t)g->force_blocks_cap * 3 * 2, s);
-    if (e == hipSuccess) e = zero_words(g->d_flag, 1, s);
+    if (e == hipSuccess) e = zero_words(g->d_flag, 2, s);
     return e;
 }
 
@@ -1759,12 +1859,12 @@ hipError_t diagnostics(mb_grid* g, int force_blocks, double* diag,
 }
 
 // Explicit instantiations.
-template hipError_t bin_blobs<float>(mb_grid*, int64_t, const double*, hipStream_t, bool);
-template hipError_t bin_blobs<double>(mb_grid*, int64_t, const double*, hipStream_t, bool);
+template hipError_t bin_blobs<float>(mb_grid*, int64_t, const double*, hipStream_t, bool, bool);
+template hipError_t bin_blobs<double>(mb_grid*, int64_t, const double*, hipStream_t, bool, bool);
 template hipError_t scatter_records<float>(mb_grid*, int64_t, const double*, const double*, hipStream_t, double);
 template hipError_t scatter_records<double>(mb_grid*, int64_t, const double*, const double*, hipStream_t, double);
-template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*, bool);
-template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*, bool);
+template hipError_t scatter_springs<float>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*, bool, bool);
+template hipError_t scatter_springs<double>(mb_grid*, const SpringsDev&, int64_t, const double*, const double*, hipStream_t, const double*, bool, bool);
 template hipError_t spread_boxes<float>(mb_grid*, hipStream_t);
 template hipError_t spread_boxes<double>(mb_grid*, hipStream_t);
 template hipError_t fold_boxes<float>(mb_grid*, float*, hipStream_t, const float*);
