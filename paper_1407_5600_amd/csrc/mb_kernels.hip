@@ -909,7 +909,9 @@ k_spread(const RecG<T>* __restrict__ rec, const T* __restrict__ recf,
       for (int pass = 0; pass < npass; ++pass) {
         for (int k = threadIdx.x, q = q0; k < total; k += NT, q = adv(q)) {
             RecG<T> r = r0;
-            T Fr = F0[a];
+            // (selected, not indexed: the component loop need not unroll, and an
+            // indexed register array would live in scratch memory)
+            T Fr = a == 0 ? F0[0] : (a == 1 ? F0[1] : F0[2]);
             if (k >= NT) {
                 const size_t p = (size_t)(first + q);
                 r = rec[p];
@@ -1043,14 +1045,20 @@ struct BinNext {
 // atomic each.
 // Threads: one per four cells of the tile, at least BLK and at most 512 (the
 // 16x16x8 family: one record per thread at these densities).
-// Float64: registers capped for five waves per SIMD (93, no spills; six
-// waves spill with the column staging below); float32 is bound by its LDS.
+// Float64: registers capped for five waves per SIMD with blocks of BLK
+// threads (93, no spills; six waves spill with the column staging below),
+// four with larger blocks (which fit two blocks per CU either way; five
+// spilled); float32 is bound by its LDS.
 constexpr int interp_threads(int cells) {
     return cells / 4 < BLK ? BLK : (cells / 4 > 512 ? 512 : cells / 4);
 }
+template <typename T>
+constexpr int interp_min_waves(int cells) {
+    return sizeof(T) == 8 ? (interp_threads(cells) > BLK ? 4 : 5) : 1;
+}
 
 template <typename T, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(interp_threads(TX * TY * TZ), (sizeof(T) == 8 ? 5 : 1))
+__global__ void __launch_bounds__(interp_threads(TX * TY * TZ), interp_min_waves<T>(TX * TY * TZ))
 k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
          const int* __restrict__ offs, int L, Tiles tl, const T* __restrict__ v,
          double* __restrict__ u_out, double uscale, double* __restrict__ q, double dt,
