@@ -485,6 +485,27 @@ def test_spread_crowded_tile(torch_cuda, prec, M):
     check(f"spread crowded {prec} M={M}", f.double().cpu().numpy(), ref, prec)
 
 
+@pytest.mark.parametrize("M", [1, 262, 263, 269, 526, 263 * 269])
+def test_spread_box_tile_record_counts(torch_cuda, M):
+    """Float32 spreading takes the k-th record of a box tile at position
+    (k P) mod n, P = 263, or 269 where 263 divides the tile's count n, or 1
+    where 269 does too: every record must be taken exactly once.  At L = 16
+    one box tile holds every blob, so n = M; 263 * 269 records also take
+    the 64-bit sums (more than 2048)."""
+    torch = torch_cuda
+    say("spread box-tile record count", M)
+    L = 16
+    rng = np.random.default_rng(M)
+    q = rng.uniform(0.0, L, size=(M, 3))
+    F = rng.standard_normal((M, 3))
+    g = grid(L, "mixed", M)
+    perm = rng.permutation(M)
+    a = g.spread(dev(torch, q), dev(torch, F)).cpu().numpy()
+    b = g.spread(dev(torch, q[perm]), dev(torch, F[perm])).cpu().numpy()
+    assert np.array_equal(a, b)
+    check(f"spread record count M={M}", a, oracle.spread(oracle.params(L), q, F), "mixed")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", ["suspension", "steady", "batch", "tile8", "fast", "crowded",
                                   "crowded_fast"])
