@@ -199,17 +199,15 @@ constexpr int cols_y(int L) {
 // ky columns per block of the z pass (a divisor of L; LDS <= 64 KB for
 // float32, 100 KB for float64).  At 128^3 float32, eight columns give 1,040
 // blocks of 384 threads, which fill the CUs in one round (sixteen gave 520
-// blocks of 768 threads: two per CU, and a nearly empty second round; four
-// were slower).  Float64 takes four up to L = 128 (2,080 blocks of 192
-// threads at 128^3: 26.5 us against 38.5 us with eight) and eight above,
-// where whole 128-byte lines per z row pay for one block per CU (256^3:
-// 288 us against 424 us with four).
-#ifndef MB_ZCOLS
-#define MB_ZCOLS 8
-#endif
+// blocks of 768 threads: two per CU, and a nearly empty second round;
+// sixteen with 384 threads of sixteen elements, three blocks per CU in one
+// round, 18.6 against 15.1 us; four were slower).  Float64 takes four up to
+// L = 128 (2,080 blocks of 192 threads at 128^3: 26.5 us against 38.5 us
+// with eight) and eight above, where whole 128-byte lines per z row pay
+// for one block per CU (256^3: 288 us against 424 us with four).
 template <typename T>
 constexpr int cols_z(int L) {
-    int w = sizeof(T) == 8 ? (L <= 128 ? 4 : 8) : MB_ZCOLS;
+    int w = sizeof(T) == 8 ? (L <= 128 ? 4 : 8) : 8;
     const int cap = sizeof(T) == 8 ? 102400 : 65536;
     while (w > 1 && (L % w != 0 || 3 * L * w * 2 * (int)sizeof(T) > cap ||
                      3 * w * L / EPT > 1024))

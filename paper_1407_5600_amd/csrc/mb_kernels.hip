@@ -289,10 +289,11 @@ __device__ void block_scan_counts(int* __restrict__ count, int n, int* __restric
 }
 
 // Spins (thread 0) until *flag == want, reading it where all XCDs see the
-// same value; gives up after ~2^22 polls (about half a second) and returns
-// false, so that a wait never hangs.
+// same value; gives up after 2^20 polls (each a device-memory round trip
+// and a short sleep: one to two seconds) and returns false, so that a wait
+// never hangs.
 __device__ bool wait_flag(const int* flag, int want) {
-    for (int it = 0; it < (1 << 22); ++it) {
+    for (int it = 0; it < (1 << 20); ++it) {
         if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want)
             return true;
         __builtin_amdgcn_s_sleep(4);
