@@ -132,6 +132,12 @@ typedef enum {
  * after its last replay.  check_finite = 0 (the default): no check and no
  * synchronisation; non-finite inputs give non-finite or meaningless
  * outputs, never an access outside the library's buffers.
+ * The same check reports a stalled scan: in a step the first workgroup of
+ * the spring-force kernel sums the tile counts and the others wait for it,
+ * for at most one to two seconds (only a device that does not run that
+ * workgroup makes them give up); a workgroup that gives up writes no
+ * records, and with check_finite = 1 the call returns MB_ERR_DEVICE, with
+ * check_finite = 0 its outputs are undefined.
  *
  * external_workspace = 1: mb_grid_create allocates no scratch; every call
  * on the grid returns MB_ERR_INVALID until a workspace of at least
