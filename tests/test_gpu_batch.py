@@ -126,7 +126,9 @@ def test_batch_step_vs_oracle(torch_cuda, prec, L):
 def test_graph_replays_match_eager_steps(torch_cuda):
     """Three grids (batches of different box sizes, one mixed) stepped by
     the captured graph and eagerly: equal after 5 replays, and again after
-    eager work and synchronisations, replay by replay."""
+    eager work and synchronisations, replay by replay.  The eager steps of
+    these grids scan the tile counts inside the springs kernel, the captured
+    ones in the separate scan kernel: the two give the same offsets."""
     torch = torch_cuda
     from paper_1407_5600_amd import Grid
     from paper_1407_5600_amd.binding import step_graph
