@@ -1036,14 +1036,14 @@ struct BinNext {
 // all three components at once for float32 fields and one at a time for
 // float64 ones (LDS size); then every record of the tile's cells gathers its
 // 27 nodes per component.  u (and the move of the blob by dt u) is written
-// once per blob for each thread's first record, per component for the rest
-// (tiles with more records than threads), scaled by uscale.  With part the
-// block also writes its float64 sum of each component and the max |Dv| over
-// its cells.  With bn.count the block also bins the moved blobs as
-// k_tile_count would bin the new positions: each thread's first record
-// through LDS counts for the 27 tiles around this one (a blob moves less
-// than a tile per step), the rest, and any farther move, with a global
-// atomic each.
+// once per blob for each thread's first record (float32 16x8x8-size tiles:
+// first two, held in registers), per component for the rest (tiles with more records than
+// threads), scaled by uscale.  With part the block also writes its float64
+// sum of each component and the max |Dv| over its cells.  With bn.count the
+// block also bins the moved blobs as k_tile_count would bin the new
+// positions: through LDS counts for the 27 tiles around this one (a blob
+// moves less than a tile per step), with one global atomic per tile, and a
+// global atomic of its own for any farther move.
 // Threads: one per four cells of the tile, at least BLK and at most 512 (the
 // 16x16x8 family: one record per thread at these densities).
 // Float64: registers capped for five waves per SIMD with blocks of BLK
@@ -1114,7 +1114,25 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
         const int ic = perm[pc];
         i0 = pos0 >= 0 ? ic : -1;
     }
+    // float32 tiles of four cells per thread and BLK threads (16x8x8: 233
+    // records on average at phi = 0.3, 310 at 0.4; registers to spare at
+    // the occupancy their LDS allows): the thread's second record too, so
+    // that tiles with more records than threads have no chain of dependent
+    // loads for it in the gathers or the binning
+    constexpr bool R2 = NCS == 3 && NT == BLK && TV >= 4 * NT;
+    constexpr int KREG = R2 ? 2 * NT : NT;  // records k < KREG are in registers
+    const int pos1 = R2 && (int)threadIdx.x + NT < total ? first + (int)threadIdx.x + NT : -1;
+    RecG<T> r1{};
+    int64_t i1 = -1;
+    double q1[3] = {0.0, 0.0, 0.0};
+    if constexpr (R2) {
+        const int pc = pos1 >= 0 ? pos1 : (pos0 >= 0 ? pos0 : 0);
+        r1 = rec[pc];
+        const int ic = perm[pc];
+        i1 = pos1 >= 0 ? ic : -1;
+    }
     double u0[3] = {0.0, 0.0, 0.0};  // velocity of the first record
+    double u1[3] = {0.0, 0.0, 0.0};  // of the second
     double sv[3] = {0.0, 0.0, 0.0};
     double dv[CPT];
 #pragma unroll
@@ -1172,6 +1190,12 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             q0[0] = q[3 * ic];
             q0[1] = q[3 * ic + 1];
             q0[2] = q[3 * ic + 2];
+            if constexpr (R2) {
+                const int64_t jc = i1 >= 0 ? i1 : ic;
+                q1[0] = q[3 * jc];
+                q1[1] = q[3 * jc + 1];
+                q1[2] = q[3 * jc + 2];
+            }
         }
         if constexpr (COLS) {
 #pragma unroll
@@ -1200,8 +1224,8 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
         __syncthreads();
         for (int k = threadIdx.x; k < total; k += NT) {
             const int pos = first + k;
-            RecG<T> r = r0;
-            if (k >= NT) r = rec[pos];
+            RecG<T> r = k < NT ? r0 : r1;
+            if (k >= KREG) r = rec[pos];
             double ua[NCS];
 #pragma unroll
             for (int c = 0; c < NCS; ++c) {
@@ -1232,6 +1256,9 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             if (k < NT) {
 #pragma unroll
                 for (int c = 0; c < NCS; ++c) u0[a0 + c] = ua[c];  // written at the end
+            } else if (k < KREG) {
+#pragma unroll
+                for (int c = 0; c < NCS; ++c) u1[a0 + c] = ua[c];  // likewise
             } else {
                 const int64_t i = perm[pos];
 #pragma unroll
@@ -1279,6 +1306,21 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             }
         }
     }
+    double qn1[3] = {0.0, 0.0, 0.0};  // the second record's new position
+    if (R2 && pos1 >= 0) {
+        if (u_out) {
+            u_out[3 * i1] = u1[0];
+            u_out[3 * i1 + 1] = u1[1];
+            u_out[3 * i1 + 2] = u1[2];
+        }
+        if (q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                qn1[c] = q1[c] + dt * u1[c];
+                q[3 * i1 + c] = qn1[c];
+            }
+        }
+    }
     if (bn.count) {
         // tile coordinates of this tile
         const int ot[3] = {tb.lo[0] / tl.tx, tb.lo[1] / tl.ty, tb.lo[2] / tl.tz};
@@ -1304,11 +1346,20 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             if (slot >= 0) rk = atomicAdd(&lcount[slot], 1);
             else rk = atomicAdd(&bn.count[tnew], 1);
         }
-        // records beyond each thread's first (positions re-read: written by
-        // this thread above): counted through the same LDS slots, their
-        // rank within the slot stored and completed below (a global atomic
-        // each only for a move beyond the neighbour tiles)
-        for (int k = threadIdx.x + NT; k < total; k += NT) {
+        // the second record (float32) from its registers
+        int slot1 = -1, rk1 = 0, tnew1 = 0;
+        if (R2 && pos1 >= 0) {
+            const Geom gn = blob_geom(qn1, 0, inv_h, L);
+            tnew1 = tb.box * tl.n + tile_linear(gn.c, tl);
+            slot1 = slot_of(gn.c);
+            if (slot1 >= 0) rk1 = atomicAdd(&lcount[slot1], 1);
+            else rk1 = atomicAdd(&bn.count[tnew1], 1);
+        }
+        // records beyond those (positions re-read: written by this thread
+        // above): counted through the same LDS slots, their rank within the
+        // slot stored and completed below (a global atomic each only for a
+        // move beyond the neighbour tiles)
+        for (int k = threadIdx.x + KREG; k < total; k += NT) {
             const int64_t i = perm[first + k];
             const Geom gk = blob_geom(q, i, inv_h, L);
             const int t = tb.box * tl.n + tile_linear(gk.c, tl);
@@ -1340,7 +1391,11 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
             bn.tile_of[i0] = tnew;
             bn.rank[i0] = slot >= 0 ? lbase[slot] + rk : rk;
         }
-        for (int k = threadIdx.x + NT; k < total; k += NT) {
+        if (R2 && pos1 >= 0) {
+            bn.tile_of[i1] = tnew1;
+            bn.rank[i1] = slot1 >= 0 ? lbase[slot1] + rk1 : rk1;
+        }
+        for (int k = threadIdx.x + KREG; k < total; k += NT) {
             const int64_t i = perm[first + k];
             int tc[3];  // the tile written above, back to its slot
             tile_coords(bn.tile_of[i] - tb.box * tl.n, tl, tc);
