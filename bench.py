@@ -13,15 +13,17 @@ divergence reductions (everything mb_step runs).  `value` is the mixed
 precision step rate; the float64 step rate on the same GPU is reported
 beside it.  The dominant kernel's duration is measured live in the timed
 region with HIP events around that kernel only, and set against the HBM
-roofline with the kernel's algorithmic bytes.  The oracle (float64, one CPU
-thread) is timed on a bounded sample of the same workload as the CPU
-baseline.
+roofline with the kernel's algorithmic bytes.  The oracle (float64, its
+OpenMP build on the host's cores) is timed on a bounded sample of the same
+workload as the CPU baseline.
 
 Also measured: the large suspension (256^3, phi = 0.4, 5,084,807 blobs),
 100 steps in each precision from the same state, with the mixed result's
 error against the float64 one (key "large"); the second-order (midpoint)
 scheme's step rate on the same workload (key "midpoint"); the steady-Stokes measurements (hydrodynamic
-radius against d, suspension viscosity) timed whole (key "stokes"); and
+radius against d, suspension viscosity) timed whole (key "stokes"); one loss
+and gradient evaluation of the differentiation case, 64^3, 16 particles, 100
+float64 steps through the adjoint kernels (key "diff"); and
 (key "batch") the pair-mobility sweep, 512 boxes of edge
 24/32/48/64 with two particles each, grouped by edge into four grids of equal
 boxes and advanced by a graph-captured step of all four, against the same
@@ -257,6 +259,64 @@ def bench_stokes(torch, oracle_sample=True):
                     np.zeros((3, rh["L"], rh["L"], rh["L"])), setup[3], n)
         out["oracle_box_steps_per_s"] = round(n / (time.perf_counter() - t0), 2)
         out["oracle_sample"] = f"{n} float64 steps of one {rh['L']}^3 radius box, one thread"
+    return out
+
+
+def bench_diff(torch, reps=3, oracle_sample=True):
+    """The differentiation case (64^3, 16 particles, 100 float64 steps of
+    dt = 0.01, checkpoints every 10): the loss sum_p |U_p - V_p|^2 alone and
+    with its gradients (624 blob-force components, stiffness, vertex radius)
+    by the library's adjoint kernels through torch.autograd; median wall
+    time of `reps` evaluations after one warm-up.  The oracle's reverse
+    sweep is timed on a few steps of the same case (one thread)."""
+    import numpy as np
+    from paper_1407_5600_amd import Grid, inputs
+    from paper_1407_5600_amd.autodiff import particle_means, place_template, trajectory
+    w = inputs.diff()
+    G = np.repeat(w.Fext / w.nb, w.nb, axis=0)
+    unit = inputs.icosahedron_template(1.0)
+    _, _, r0u = inputs.pair_table(unit)
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+    g = Grid(w.L, h=w.h, rho=w.rho, eta=w.eta, dt=w.dt, max_blobs=w.M)
+    cen, rot, V = dev(w.extra["centres"]), dev(w.extra["rotations"]), dev(w.extra["V"])
+    unit_t, r0u_t = dev(unit), dev(np.asarray(r0u, dtype=float))
+
+    def once(grad):
+        a = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=grad)
+        k = torch.tensor(float(w.k), dtype=torch.float64, device="cuda", requires_grad=grad)
+        Gt = dev(G).requires_grad_(grad)
+        q0 = place_template(cen, rot, unit_t, a)
+        v0 = torch.zeros((3, w.L, w.L, w.L), dtype=torch.float64, device="cuda")
+        u = trajectory(g, w.nb, w.pa, w.pb, q0, v0, Gt, k, a * r0u_t, w.steps, 10)
+        loss = ((particle_means(u, w.nb) - V) ** 2).sum()
+        if grad:
+            loss.backward()
+        torch.cuda.synchronize()
+
+    out = {"workload": f"diff: {w.L}^3, {w.P} particles x {w.nb} blobs, {w.steps} steps of "
+                       f"dt {w.dt}, checkpoints every 10, float64"}
+    for key, grad in (("loss_seconds", False), ("loss_and_gradient_seconds", True)):
+        once(grad)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            once(grad)
+            ts.append(time.perf_counter() - t0)
+        out[key] = round(sorted(ts)[len(ts) // 2], 4)
+    if oracle_sample:
+        import oracle
+        prm = oracle.params(w.L, h=w.h, rho=w.rho, eta=w.eta, dt=w.dt)
+        n = 5
+        t0 = time.perf_counter()
+        oracle.loss_grad(prm, w.springs(), w.q, np.zeros((3, w.L, w.L, w.L)), G,
+                         w.extra["V"], n)
+        sec = time.perf_counter() - t0
+        out["oracle_loss_and_gradient_seconds_per_step"] = round(sec / n, 4)
+        out["oracle_sample"] = (f"{n} float64 steps of the same case, loss and reverse sweep, "
+                                f"one thread")
     return out
 
 
@@ -540,6 +600,8 @@ def main():
         out["midpoint"] = bench_midpoint(torch, w, max(10, args.steps // 4), 5)
         print("[bench] steady-Stokes measurements", file=sys.stderr, flush=True)
         out["stokes"] = bench_stokes(torch, oracle_sample=not args.no_cpu_baseline)
+        print("[bench] differentiation case", file=sys.stderr, flush=True)
+        out["diff"] = bench_diff(torch, oracle_sample=not args.no_cpu_baseline)
     if args.batch_boxes > 0 and args.only is None:
         print(f"[bench] batched pair sweep ({args.batch_boxes} boxes)", file=sys.stderr,
               flush=True)
