@@ -1036,8 +1036,8 @@ struct BinNext {
 // all three components at once for float32 fields and one at a time for
 // float64 ones (LDS size); then every record of the tile's cells gathers its
 // 27 nodes per component.  u (and the move of the blob by dt u) is written
-// once per blob for each thread's first record (float32 16x8x8-size tiles:
-// first two, held in registers), per component for the rest (tiles with more records than
+// once per blob for each thread's first record (16x8x8-size tiles: first
+// two, held in registers), per component for the rest (tiles with more records than
 // threads), scaled by uscale.  With part the block also writes its float64
 // sum of each component and the max |Dv| over its cells.  With bn.count the
 // block also bins the moved blobs as k_tile_count would bin the new
@@ -1046,16 +1046,18 @@ struct BinNext {
 // global atomic of its own for any farther move.
 // Threads: one per four cells of the tile, at least BLK and at most 512 (the
 // 16x16x8 family: one record per thread at these densities).
-// Float64: registers capped for five waves per SIMD with blocks of BLK
-// threads (93, no spills; six waves spill with the column staging below),
-// four with larger blocks (which fit two blocks per CU either way; five
-// spilled); float32 is bound by its LDS.
+// Float64: registers capped for four waves per SIMD from 1,024 cells up
+// (16x8x8: 115 registers with its second record, 306 against 351 us at
+// 256^3 phi = 0.4 and 31.1 against 32.1 us at 128^3 phi = 0.3 with one
+// record at five waves; larger tiles fit two blocks per CU either way),
+// five below (93, no spills; six spill with the column staging); float32
+// is bound by its LDS.
 constexpr int interp_threads(int cells) {
     return cells / 4 < BLK ? BLK : (cells / 4 > 512 ? 512 : cells / 4);
 }
 template <typename T>
 constexpr int interp_min_waves(int cells) {
-    return sizeof(T) == 8 ? (interp_threads(cells) > BLK ? 4 : 5) : 1;
+    return sizeof(T) == 8 ? (cells >= 4 * BLK ? 4 : 5) : 1;
 }
 
 template <typename T, int TX, int TY, int TZ>
@@ -1114,12 +1116,13 @@ k_interp(const RecG<T>* __restrict__ rec, const int* __restrict__ perm,
         const int ic = perm[pc];
         i0 = pos0 >= 0 ? ic : -1;
     }
-    // float32 tiles of four cells per thread and BLK threads (16x8x8: 233
-    // records on average at phi = 0.3, 310 at 0.4; registers to spare at
-    // the occupancy their LDS allows): the thread's second record too, so
-    // that tiles with more records than threads have no chain of dependent
-    // loads for it in the gathers or the binning
-    constexpr bool R2 = NCS == 3 && NT == BLK && TV >= 4 * NT;
+    // tiles of four cells per thread and BLK threads (16x8x8: 233 records
+    // on average at phi = 0.3, 310 at 0.4): the thread's second record too,
+    // so that tiles with more records than threads have no chain of
+    // dependent loads for it in the gathers or the binning (float32 has the
+    // registers to spare at the occupancy its LDS allows; float64 is capped
+    // at four waves for it, above)
+    constexpr bool R2 = NT == BLK && TV >= 4 * NT;
     constexpr int KREG = R2 ? 2 * NT : NT;  // records k < KREG are in registers
     const int pos1 = R2 && (int)threadIdx.x + NT < total ? first + (int)threadIdx.x + NT : -1;
     RecG<T> r1{};
